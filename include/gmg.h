@@ -1,0 +1,208 @@
+/*
+ * gmg.h -- C ABI of libgmg.so, a geometric-multigrid (GMG) solver for the
+ * variable-coefficient pressure Poisson problem  div(L grad p) = sigma  on a
+ * Cartesian grid, written for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of "Scaling WaterLily.jl with MPI and an improved
+ * geometric multigrid solver" (Font, Lauber, Huang, Weymouth):
+ *   - GMG = smoothing plus coarse-grid correction (Sec. 3);
+ *   - red-black Gauss-Seidel smoothing with a relaxation factor that is
+ *     lowered on residual growth and raised on decay after every V-cycle
+ *     (Sec. 3.1);
+ *   - anisotropic coarsening: every direction is halved independently until
+ *     it reaches the coarsening limit; isotropic coarsening stops when the
+ *     smallest direction does (Sec. 3.2).
+ *
+ * Discretisation (unit cell size, finite-volume flux form):
+ *   (A x)(I) = sum_d L_d(I+e_d) (x(I+e_d) - x(I)) + L_d(I) (x(I-e_d) - x(I)),
+ *   D(I) = -sum of the six face coefficients; cells with D = 0 are inactive
+ *   (decoupled): their residual is 0 and the solver never changes them.
+ *
+ * Memory layout of every array argument (all DEVICE pointers unless stated):
+ *   cell fields x, sigma, r: C order [nz][ny][nx], x fastest, no ghost cells;
+ *   face coefficients L: [3][nz][ny][nx]; L[d][I] is the LOW d-face of cell I
+ *   (between I - e_d and I).  The high face of the last cell wraps to index 0
+ *   in a periodic direction and is a wall (coefficient 0) otherwise; the low
+ *   face at index 0 of a wall direction is treated as 0 whatever it holds.
+ *
+ * Precision: `dtype` is the element type of the caller's x, sigma, r and L;
+ * `cycle_dtype` is the V-cycle arithmetic; `l_storage` is how the handle
+ * stores the face coefficients of the hierarchy (BF16 = round to nearest
+ * even, loaded and computed in FP32).  Norms accumulate in FP64.
+ *
+ * Streams: all work is enqueued on the HIP stream given to gmg_setup (NULL =
+ * the legacy default stream).  Calls that return host scalars or fill an
+ * info struct synchronise that stream before returning; the others are
+ * asynchronous.  A handle is not thread-safe; distinct handles are
+ * independent.
+ *
+ * Errors: every call returns a gmg_status; no C++ exception crosses the ABI.
+ * Argument errors are detected before any side effect.  gmg_last_error()
+ * returns a thread-local message about the last failure.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gmg_status {
+  GMG_OK = 0,
+  GMG_EINVAL = 1,   /* null pointer, bad parameter, dtype mismatch */
+  GMG_ESHAPE = 2,   /* n_d < 1, or an odd size (or 1) in a periodic direction */
+  GMG_ENOMEM = 3,   /* device or pinned-host allocation failed */
+  GMG_EHIP = 4,     /* a HIP runtime error (message in gmg_last_error) */
+  GMG_ENOCONV = 5   /* max_cycles / max_outer reached before the tolerance */
+} gmg_status;
+
+typedef enum gmg_dtype { GMG_F32 = 0, GMG_F64 = 1, GMG_BF16 = 2 } gmg_dtype;
+
+/* Solver parameters.  gmg_default_params fills the defaults noted here. */
+typedef struct gmg_params {
+  int32_t n[3];          /* cells (nx, ny, nz)                                 */
+  int32_t periodic[3];   /* 1 periodic, 0 wall (Neumann), per direction x,y,z  */
+  int32_t dtype;         /* caller arrays: GMG_F32 or GMG_F64 (default F32)    */
+  int32_t cycle_dtype;   /* V-cycle arithmetic: GMG_F32 or GMG_F64; F64 needs
+                            dtype F64 (default: same as dtype)                 */
+  int32_t l_storage;     /* hierarchy faces: GMG_F32, GMG_F64 (F64 cycles
+                            only) or GMG_BF16 (F32 cycles only); default: the
+                            cycle dtype                                         */
+  int32_t anisotropic;   /* 1: coarsen each direction independently (Sec. 3.2,
+                            default); 0: isotropic, stop when any direction
+                            cannot be halved                                   */
+  int32_t min_coarse;    /* a direction is halved only if the result has at
+                            least this many cells (default 4), n is even, and
+                            (periodic) the half is even                        */
+  int32_t max_levels;    /* cap on the number of levels, 0 = none (default)   */
+  int32_t nu_pre;        /* red-black sweeps before restriction (default 2)   */
+  int32_t nu_post;       /* sweeps after the correction (default 2)           */
+  int32_t nu_coarse;     /* sweeps on the coarsest level, no direct solve (4) */
+  int32_t rollback;      /* 1: a V-cycle that grows the residual is discarded
+                            (default 1)                                        */
+  double omega0;         /* relaxation factor at the start of a solve (1.0)   */
+  double omega_min;      /* lower bound (0.1)                                 */
+  double omega_max;      /* upper bound (1.0)                                 */
+  double theta_dec;      /* factor applied on residual growth (0.5)           */
+  double theta_inc;      /* factor applied on residual decay (1.2)            */
+} gmg_params;
+
+#define GMG_MAX_HISTORY 512
+
+/* Filled by gmg_solve.  history[k] is ||r||/||sigma|| after cycle k (of the
+ * cycle's own result, accepted or not), omegas[k] the factor cycle k used,
+ * accepted[k] 1 if it was kept. */
+typedef struct gmg_solve_info {
+  int32_t status;        /* GMG_OK or GMG_ENOCONV                              */
+  int32_t cycles;        /* V-cycles run                                       */
+  int32_t accepted_cycles;
+  int32_t launches;      /* host launch rounds (diagnostic)                    */
+  double rnorm0;         /* ||sigma - A x0|| over the active cells            */
+  double rnorm;          /* ||sigma - A x|| of the returned x                  */
+  double snorm;          /* ||sigma|| over the active cells                    */
+  double omega;          /* factor after the last cycle                        */
+  double history[GMG_MAX_HISTORY];
+  double omegas[GMG_MAX_HISTORY];
+  int32_t accepted[GMG_MAX_HISTORY];
+} gmg_solve_info;
+
+typedef struct gmg_handle gmg_handle;
+
+/* Fill *p with the defaults above for an n[0] x n[1] x n[2] wall-bounded FP32
+ * problem.  Returns GMG_EINVAL if p is NULL. */
+gmg_status gmg_default_params(gmg_params* p);
+
+/* Plan the level hierarchy (Sec. 3.2 coarsening rule), copy L (device, dtype
+ * p->dtype, [3][nz][ny][nx]) into handle-owned storage (wall low faces
+ * zeroed, rounded to l_storage) and restrict it level by level:
+ *   L_d^{l+1}[J] = (1/c_d) * sum of the fine d-faces tiling the low d-face of
+ *   coarse cell J.
+ * The caller keeps ownership of L and may free it once this call returns.
+ * `stream` is a hipStream_t (may be NULL).  On success *out owns all device
+ * workspace (levels, work buffers, reduction partials, solver state) until
+ * gmg_destroy.  Errors: GMG_EINVAL (NULL p/L/out, bad dtype combination or
+ * parameter), GMG_ESHAPE, GMG_ENOMEM, GMG_EHIP.  Synchronises the stream. */
+gmg_status gmg_setup(const gmg_params* p, const void* L, void* stream,
+                     gmg_handle** out);
+
+/* Free everything the handle owns.  NULL is accepted. */
+gmg_status gmg_destroy(gmg_handle* h);
+
+/* Number of levels, and the shape (cells) and coarsening factor (to the next
+ * level, 0 0 0 on the coarsest) of level `level`.  Host pointers. */
+gmg_status gmg_num_levels(const gmg_handle* h, int32_t* nlevels);
+gmg_status gmg_level_shape(const gmg_handle* h, int32_t level, int32_t n[3],
+                           int32_t c[3]);
+
+/* Copy the stored face coefficients of `level` ([3][nz][ny][nx] of that
+ * level, element type l_storage; BF16 as raw uint16) into the caller's
+ * device buffer `L_out`.  Asynchronous. */
+gmg_status gmg_level_faces(gmg_handle* h, int32_t level, void* L_out);
+
+/* Residual of the level-0 problem in dtype arithmetic (Sec. 3: the quantity
+ * the V-cycle drives to zero):  r = sigma - A x on active cells, 0 elsewhere.
+ * x, sigma: device, dtype.  r: device output or NULL (not written).
+ * rnorm, snorm: host outputs or NULL: ||r||_2 and ||sigma||_2 over the active
+ * cells, FP64 accumulation.  If rnorm or snorm is given the call synchronises.
+ * The operator is the stored level-0 one, except that a handle with
+ * dtype F64 and cycle_dtype F32 uses an exact FP64 copy of L. */
+gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma,
+                        void* r, double* rnorm, double* snorm);
+
+/* `sweeps` red-black Gauss-Seidel sweeps (Sec. 3.1) in place on level
+ * `level`, at the handle's current omega: each sweep updates every active
+ * cell of colour (i+j+k) mod 2 == 0 at once, x(I) += omega r(I) / D(I) from
+ * the residual before that half-sweep, then every active cell of colour 1.
+ * x, sigma: device arrays of that level's shape in cycle_dtype.  Async. */
+gmg_status gmg_smooth(gmg_handle* h, int32_t level, void* x,
+                      const void* sigma, int32_t sweeps);
+
+/* Fused residual and restriction from `level` to level+1 (coarse-grid
+ * correction, Sec. 3):  sigma_c[J] = sum over the c-block of J of
+ * (sigma - A x), and x_c = 0 (the coarse initial guess).  Arrays in
+ * cycle_dtype, shapes of `level` (x, sigma) and level+1 (sigma_c, x_c);
+ * x_c may be NULL.  Async.  GMG_EINVAL on the coarsest level. */
+gmg_status gmg_restrict_residual(gmg_handle* h, int32_t level, const void* x,
+                                 const void* sigma, void* sigma_c, void* x_c);
+
+/* Piecewise-constant prolongation and correction from level+1 to `level`:
+ * x[a] += x_c[a / c] for active cells a.  Async. */
+gmg_status gmg_prolong_correct(gmg_handle* h, int32_t level,
+                               const void* x_c, void* x);
+
+/* Current relaxation factor (used by gmg_smooth and gmg_vcycle; set to
+ * omega0 at the start of each gmg_solve).  get synchronises. */
+gmg_status gmg_get_omega(gmg_handle* h, double* omega);
+gmg_status gmg_set_omega(gmg_handle* h, double omega);
+
+/* One V(nu_pre, nu_post) cycle (Sec. 3) in place on x (device, dtype ==
+ * cycle_dtype) at the current omega, with no adaptation:
+ *   nu_pre sweeps; restrict the residual; recurse (x_c = 0); prolong and
+ *   correct; nu_post sweeps; nu_coarse sweeps on the coarsest level.
+ * If rnorm_after is non-NULL it receives ||sigma - A x|| (synchronises). */
+gmg_status gmg_vcycle(gmg_handle* h, void* x, const void* sigma,
+                      double* rnorm_after);
+
+/* Adaptive GMG solve (Sec. 3.1): V-cycles from x (in: initial guess, out:
+ * solution; dtype == cycle_dtype) until ||r|| <= rtol ||sigma|| (norms over
+ * active cells) or max_cycles.  After each cycle the new residual norm is
+ * compared with the last accepted one: growth multiplies omega by theta_dec
+ * (>= omega_min) and, with rollback, discards the cycle; decay (or a tie)
+ * keeps it and multiplies omega by theta_inc (<= omega_max).  Decisions are
+ * taken on the device; the host only polls a flag between launch rounds.
+ * If ||sigma|| = 0, x is returned unchanged with status GMG_OK.
+ * Returns GMG_OK or GMG_ENOCONV (x then holds the last accepted iterate);
+ * info (host, may be NULL) is filled in both cases.  Synchronises. */
+gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol,
+                     int32_t max_cycles, gmg_solve_info* info);
+
+/* Thread-local description of the last error ("" if none). */
+const char* gmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMG_H */

@@ -228,10 +228,15 @@ def prolong(y, c):
     return np.repeat(np.repeat(np.repeat(y, cz, axis=0), cy, axis=1), cx, axis=2)
 
 
-def build_hierarchy(L, periodic, anisotropic=True, min_coarse=4, max_levels=0):
-    """Level list: dicts with 'L' (normalised FP64 faces), 'c' (factor to the
-    next level or None), 'periodic', 'active'."""
-    L0 = normalize_faces(L, periodic)
+def build_hierarchy(L, periodic, anisotropic=True, min_coarse=4, max_levels=0,
+                    storage="f64"):
+    """Level list: dicts with 'L' (normalised faces, promoted to FP64), 'c'
+    (factor to the next level or None), 'periodic', 'active'.
+
+    ``storage`` ('f64', 'f32', 'bf16') is the format the faces of every level
+    are kept in: level 0 is rounded to it, and each coarser level is
+    restricted from the stored finer one and rounded to it again."""
+    L0 = round_to(normalize_faces(L, periodic), storage)
     nz, ny, nx = L0.shape[1:]
     plan = level_plan((nx, ny, nz), periodic, anisotropic, min_coarse, max_levels)
     levels = []
@@ -241,7 +246,7 @@ def build_hierarchy(L, periodic, anisotropic=True, min_coarse=4, max_levels=0):
         levels.append({"L": Lc, "c": c, "periodic": tuple(periodic),
                        "active": active_set(Lc, periodic)})
         if c is not None:
-            Lc = restrict_faces(Lc, c)
+            Lc = round_to(restrict_faces(Lc, c), storage)
     return levels
 
 
@@ -365,8 +370,8 @@ def solve_ir(L, periodic, x0, sigma, rtol=1e-10, max_outer=50, max_inner=8,
     rounded inputs.  Returns dict(x, status, outer, inner_total, history)."""
     L64 = normalize_faces(L, periodic)
     act = active_set(L64, periodic)
-    levels = build_hierarchy(round_to(L64, inner_storage), periodic,
-                             anisotropic, min_coarse, max_levels)
+    levels = build_hierarchy(L64, periodic, anisotropic, min_coarse,
+                             max_levels, storage=inner_storage)
     x = np.array(x0, dtype=np.float64, copy=True)
     snorm = norm2(sigma, act)
     hist = []

@@ -1,0 +1,115 @@
+// Device-side helpers shared by the GMG kernels: grid geometry, face loads
+// for every storage format, the 7-point flux-form stencil, and deterministic
+// block reductions for 64-lane CDNA wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmg {
+
+// Geometry of one level.  n = nx*ny*nz cells; strides in elements.
+struct Geom {
+  int nx, ny, nz;
+  int px, py, pz;  // 1 = periodic
+  long long sy, sz, n;
+};
+
+// Face-coefficient loads: FP32, FP64, or BF16 kept as raw uint16 bits.
+template <typename T> __device__ __forceinline__ T ldL(const float* p, long long i) { return (T)p[i]; }
+template <typename T> __device__ __forceinline__ T ldL(const double* p, long long i) { return (T)p[i]; }
+template <typename T> __device__ __forceinline__ T ldL(const uint16_t* p, long long i) {
+  return (T)__uint_as_float(((uint32_t)p[i]) << 16);
+}
+
+// Stored-format conversions used when building the hierarchy.
+template <typename TL> __device__ __forceinline__ TL to_storage(double v);
+template <> __device__ __forceinline__ float to_storage<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ double to_storage<double>(double v) { return v; }
+template <> __device__ __forceinline__ uint16_t to_storage<uint16_t>(double v) {
+  // round to FP32 first, then FP32 -> BF16 round-to-nearest-even on the bits
+  uint32_t u = __float_as_uint((float)v);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Neighbour offsets along one direction for cell coordinate c of extent n:
+// low neighbour (c-1, wrapping when periodic; self at a wall, where the low
+// face is stored as 0) and high neighbour (c+1, wrapping; self at a wall with
+// hi_ok = false so that the high face counts as 0).
+struct Nb {
+  long long lo, hi;
+  bool hi_ok;
+};
+__device__ __forceinline__ Nb neighbours(int c, int n, int periodic, long long stride) {
+  Nb r;
+  r.lo = (c > 0) ? -stride : (periodic ? (long long)(n - 1) * stride : 0);
+  if (c + 1 < n) {
+    r.hi = stride;
+    r.hi_ok = true;
+  } else if (periodic) {
+    r.hi = -(long long)(n - 1) * stride;
+    r.hi_ok = true;
+  } else {
+    r.hi = 0;
+    r.hi_ok = false;
+  }
+  return r;
+}
+
+// (A x)(I) in flux form and the diagonal D(I) = -(sum of the six faces).
+// Summation order per direction: high face term, then low face term.
+template <typename T, typename TL>
+__device__ __forceinline__ T stencil_Ax(const Geom& g, const T* __restrict__ x,
+                                        const TL* __restrict__ L, long long idx, int i,
+                                        int j, int k, T xc, T& D) {
+  T ax = T(0), s = T(0);
+  {
+    const Nb nb = neighbours(i, g.nx, g.px, 1);
+    const T lm = ldL<T>(L, idx);
+    const T lp = nb.hi_ok ? ldL<T>(L, idx + nb.hi) : T(0);
+    ax += lp * (x[idx + nb.hi] - xc);
+    ax += lm * (x[idx + nb.lo] - xc);
+    s += lm + lp;
+  }
+  {
+    const TL* Ly = L + g.n;
+    const Nb nb = neighbours(j, g.ny, g.py, g.sy);
+    const T lm = ldL<T>(Ly, idx);
+    const T lp = nb.hi_ok ? ldL<T>(Ly, idx + nb.hi) : T(0);
+    ax += lp * (x[idx + nb.hi] - xc);
+    ax += lm * (x[idx + nb.lo] - xc);
+    s += lm + lp;
+  }
+  {
+    const TL* Lz = L + 2 * g.n;
+    const Nb nb = neighbours(k, g.nz, g.pz, g.sz);
+    const T lm = ldL<T>(Lz, idx);
+    const T lp = nb.hi_ok ? ldL<T>(Lz, idx + nb.hi) : T(0);
+    ax += lp * (x[idx + nb.hi] - xc);
+    ax += lm * (x[idx + nb.lo] - xc);
+    s += lm + lp;
+  }
+  D = -s;
+  return ax;
+}
+
+// Sum of v over a block of `nthreads` (multiple of 64, <= 1024) threads,
+// fixed order: wavefront shuffle tree, then wave partials in index order.
+// The result is valid in thread 0 only.
+__device__ __forceinline__ double block_sum(double v, int tid, int nthreads) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double wsum[16];
+  const int lane = tid & 63, w = tid >> 6;
+  if (lane == 0) wsum[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) {
+    const int nw = nthreads >> 6;
+    for (int q = 0; q < nw; ++q) s += wsum[q];
+  }
+  return s;
+}
+
+}  // namespace gmg

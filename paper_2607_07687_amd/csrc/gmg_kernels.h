@@ -1,0 +1,39 @@
+// GMG kernels for gfx950 (CDNA4): residual, red-black half-sweeps, fused
+// residual + restriction, prolongation + correction, hierarchy set-up,
+// reductions and the device-side solve state.  All of them are memory-bound
+// stencils (about 1 flop per byte); see the launch helpers in gmg_lib.hip.
+#pragma once
+
+#include "gmg_device.h"
+#include "../../include/gmg.h"
+
+namespace gmg {
+
+// Device-resident solver state: adaptive relaxation factor, accepted-iterate
+// selector and convergence flag, decided on the device after every V-cycle.
+struct SolveState {
+  double rho;      // ||r|| of the accepted iterate
+  double rho0;     // ||r|| of the initial guess
+  double snorm;    // ||sigma|| over active cells
+  double omega;    // relaxation factor for the next cycle
+  double rtol;
+  double last;     // ||r|| of the most recent cycle's result
+  int cur;         // 0: accepted iterate in buffer A, 1: in buffer B
+  int done;        // 1 once converged or out of cycles
+  int cycles, accepted, max_cycles, status;
+  int pad0, pad1;
+  double scr[4];   // scratch for one-off reductions (gmg_residual)
+  double hist[GMG_MAX_HISTORY];
+  double omegas[GMG_MAX_HISTORY];
+  int acc[GMG_MAX_HISTORY];
+};
+
+// Adaptive-relaxation constants, passed by value.
+struct OmegaRule {
+  double omega_min, omega_max, theta_dec, theta_inc;
+  int rollback;
+};
+
+constexpr int BX = 64, BY = 4, BT = BX * BY;  // cell-kernel block: one wave per row
+
+}  // namespace gmg

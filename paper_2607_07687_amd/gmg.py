@@ -1,0 +1,277 @@
+"""ctypes binding of libgmg.so (C ABI in include/gmg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Functions carry the C names.  Arrays are torch tensors on the GPU (device
+memory and streams come from PyTorch); the work is enqueued on torch's
+current stream of the tensor's device unless a stream is given.
+
+The library is loaded from this package directory on first use; if it is
+missing this raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_NAME = "libgmg.so"
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+GMG_OK, GMG_EINVAL, GMG_ESHAPE, GMG_ENOMEM, GMG_EHIP, GMG_ENOCONV = range(6)
+GMG_F32, GMG_F64, GMG_BF16 = 0, 1, 2
+GMG_MAX_HISTORY = 512
+STATUS_NAMES = {0: "GMG_OK", 1: "GMG_EINVAL", 2: "GMG_ESHAPE", 3: "GMG_ENOMEM",
+                4: "GMG_EHIP", 5: "GMG_ENOCONV"}
+
+
+class gmg_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("periodic", ctypes.c_int32 * 3),
+                ("dtype", ctypes.c_int32), ("cycle_dtype", ctypes.c_int32),
+                ("l_storage", ctypes.c_int32), ("anisotropic", ctypes.c_int32),
+                ("min_coarse", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+                ("nu_coarse", ctypes.c_int32), ("rollback", ctypes.c_int32),
+                ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
+                ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
+                ("theta_inc", ctypes.c_double)]
+
+
+class gmg_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("accepted_cycles", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("rnorm0", ctypes.c_double), ("rnorm", ctypes.c_double),
+                ("snorm", ctypes.c_double), ("omega", ctypes.c_double),
+                ("history", ctypes.c_double * GMG_MAX_HISTORY),
+                ("omegas", ctypes.c_double * GMG_MAX_HISTORY),
+                ("accepted", ctypes.c_int32 * GMG_MAX_HISTORY)]
+
+
+class GMGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("gmg_default_params", ctypes.c_int, [ctypes.POINTER(gmg_params)]),
+    ("gmg_setup", ctypes.c_int, [ctypes.POINTER(gmg_params), ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    ("gmg_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("gmg_num_levels", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    ("gmg_level_shape", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    ("gmg_level_faces", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("gmg_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
+    ("gmg_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int32]),
+    ("gmg_restrict_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    ("gmg_prolong_correct", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    ("gmg_get_omega", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    ("gmg_set_omega", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    ("gmg_vcycle", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_double)]),
+    ("gmg_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_double, ctypes.c_int32,
+                                 ctypes.POINTER(gmg_solve_info)]),
+    ("gmg_last_error", ctypes.c_char_p, []),
+]
+
+
+def lib_path():
+    return os.path.join(_HERE, LIB_NAME)
+
+
+def load():
+    """Load libgmg.so from the package directory (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
+                              "`python -m paper_2607_07687_amd.build` (HIP, gfx950)")
+        lib = ctypes.CDLL(path)
+        for name, res, args in _SIGS:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def _check(status):
+    if status != GMG_OK:
+        raise GMGError(status, load().gmg_last_error().decode())
+    return status
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return GMG_F32
+    if t.dtype == torch.float64:
+        return GMG_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t, what):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def gmg_default_params(n, periodic=(False, False, False), dtype=GMG_F32, **kw):
+    """gmg_params with the library defaults, then n, periodic, dtype and any
+    field given by keyword.  cycle_dtype and l_storage follow dtype unless
+    given."""
+    p = gmg_params()
+    _check(load().gmg_default_params(ctypes.byref(p)))
+    for d in range(3):
+        p.n[d] = int(n[d])
+        p.periodic[d] = int(bool(periodic[d]))
+    p.dtype = dtype
+    p.cycle_dtype = kw.pop("cycle_dtype", dtype)
+    p.l_storage = kw.pop("l_storage", p.cycle_dtype)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Handle:
+    """Owns a gmg_handle*; destroyed by close() or garbage collection."""
+
+    def __init__(self, ptr, params, stream):
+        self._ptr = ptr
+        self.params = params
+        self.stream = stream
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("handle is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr is not None:
+            load().gmg_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gmg_setup(params, L, stream=None):
+    """Build the hierarchy from face coefficients L ([3][nz][ny][nx] tensor in
+    params.dtype).  Returns a Handle."""
+    if _dtype_code(L) != params.dtype:
+        raise TypeError("L dtype does not match params.dtype")
+    s = _stream(stream, L.device)
+    out = ctypes.c_void_p()
+    _check(load().gmg_setup(ctypes.byref(params), _ptr(L, "L"), s, ctypes.byref(out)))
+    return Handle(out, params, s)
+
+
+def gmg_num_levels(h):
+    n = ctypes.c_int32()
+    _check(load().gmg_num_levels(h.ptr, ctypes.byref(n)))
+    return n.value
+
+
+def gmg_level_shape(h, level):
+    n = (ctypes.c_int32 * 3)()
+    c = (ctypes.c_int32 * 3)()
+    _check(load().gmg_level_shape(h.ptr, level, n, c))
+    return tuple(n), tuple(c)
+
+
+def gmg_level_faces(h, level, out):
+    _check(load().gmg_level_faces(h.ptr, level, _ptr(out, "out")))
+    return out
+
+
+def gmg_residual(h, x, sigma, r=None, norms=True):
+    """Returns (rnorm, snorm) if norms else None; fills r if given."""
+    rn, sn = ctypes.c_double(), ctypes.c_double()
+    _check(load().gmg_residual(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), _ptr(r, "r"),
+                               ctypes.byref(rn) if norms else None,
+                               ctypes.byref(sn) if norms else None))
+    return (rn.value, sn.value) if norms else None
+
+
+def gmg_smooth(h, level, x, sigma, sweeps):
+    _check(load().gmg_smooth(h.ptr, level, _ptr(x, "x"), _ptr(sigma, "sigma"), sweeps))
+
+
+def gmg_restrict_residual(h, level, x, sigma, sigma_c, x_c=None):
+    _check(load().gmg_restrict_residual(h.ptr, level, _ptr(x, "x"), _ptr(sigma, "sigma"),
+                                        _ptr(sigma_c, "sigma_c"), _ptr(x_c, "x_c")))
+
+
+def gmg_prolong_correct(h, level, x_c, x):
+    _check(load().gmg_prolong_correct(h.ptr, level, _ptr(x_c, "x_c"), _ptr(x, "x")))
+
+
+def gmg_get_omega(h):
+    w = ctypes.c_double()
+    _check(load().gmg_get_omega(h.ptr, ctypes.byref(w)))
+    return w.value
+
+
+def gmg_set_omega(h, omega):
+    _check(load().gmg_set_omega(h.ptr, float(omega)))
+
+
+def gmg_vcycle(h, x, sigma, want_norm=False):
+    rn = ctypes.c_double()
+    _check(load().gmg_vcycle(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"),
+                             ctypes.byref(rn) if want_norm else None))
+    return rn.value if want_norm else None
+
+
+def info_dict(info):
+    n = min(info.cycles, GMG_MAX_HISTORY)
+    return dict(status=STATUS_NAMES[info.status], cycles=info.cycles,
+                accepted_cycles=info.accepted_cycles, launches=info.launches,
+                rnorm0=info.rnorm0, rnorm=info.rnorm, snorm=info.snorm,
+                omega=info.omega, history=list(info.history[:n]),
+                omegas=list(info.omegas[:n]), accepted=list(info.accepted[:n]))
+
+
+def gmg_solve(h, x, sigma, rtol, max_cycles, raise_noconv=False):
+    """Adaptive solve in place on x.  Returns the info dict (status
+    'GMG_ENOCONV' is returned, not raised, unless raise_noconv)."""
+    info = gmg_solve_info()
+    st = load().gmg_solve(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), float(rtol),
+                          int(max_cycles), ctypes.byref(info))
+    if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
+        _check(st)
+    return info_dict(info)
+
+
+def gmg_last_error():
+    return load().gmg_last_error().decode()

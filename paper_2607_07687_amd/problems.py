@@ -42,19 +42,12 @@ def _sel(d, i):
 
 
 def face_centres(n, d):
-    """Cell-unit coordinates (X, Y, Z) of the low d-face centres, each an
-    array of shape (nz, ny, nx)."""
+    """Cell-unit coordinates (X, Y, Z) of the low d-face centres, as arrays
+    that broadcast to shape (nz, ny, nx)."""
     nx, ny, nz = n
-    k, j, i = np.meshgrid(np.arange(nz, dtype=np.float64),
-                          np.arange(ny, dtype=np.float64),
-                          np.arange(nx, dtype=np.float64), indexing="ij")
-    X, Y, Z = i + 0.5, j + 0.5, k + 0.5
-    if d == 0:
-        X = i
-    elif d == 1:
-        Y = j
-    else:
-        Z = k
+    X = np.arange(nx, dtype=np.float64)[None, None, :] + (0.0 if d == 0 else 0.5)
+    Y = np.arange(ny, dtype=np.float64)[None, :, None] + (0.0 if d == 1 else 0.5)
+    Z = np.arange(nz, dtype=np.float64)[:, None, None] + (0.0 if d == 2 else 0.5)
     return X, Y, Z
 
 
@@ -63,8 +56,11 @@ def mu0(dist):
     1 for dist >= 1, and (1 + dist)/2 + sin(pi dist)/(2 pi) in between (the
     integral of the kernel (1 + cos(pi s))/2 over s <= dist)."""
     d = np.asarray(dist, dtype=np.float64)
-    m = 0.5 * (1.0 + d) + np.sin(math.pi * d) / (2.0 * math.pi)
-    return np.where(d <= -1.0, 0.0, np.where(d >= 1.0, 1.0, m))
+    out = (d >= 1.0).astype(np.float64)
+    band = (d > -1.0) & (d < 1.0)
+    db = d[band]
+    out[band] = 0.5 * (1.0 + db) + np.sin(math.pi * db) / (2.0 * math.pi)
+    return out
 
 
 def zero_wall_faces(L, periodic):
@@ -82,7 +78,7 @@ def sphere_faces(n, periodic, centre, radius):
     L = np.empty((3, n[2], n[1], n[0]), dtype=np.float64)
     for d in range(3):
         X, Y, Z = face_centres(n, d)
-        r = np.sqrt((X - centre[0]) ** 2 + (Y - centre[1]) ** 2 +
+        r = np.sqrt(((X - centre[0]) ** 2 + (Y - centre[1]) ** 2) +
                     (Z - centre[2]) ** 2)
         L[d] = mu0(r - radius)
     return zero_wall_faces(L, periodic)
@@ -135,9 +131,9 @@ def tgv_velocity(n, period, kx=1, ky=1, kz=1, phase=(0.0, 0.0, 0.0)):
         Y = 2 * math.pi * ky * (Y + phase[1]) / period
         Z = 2 * math.pi * kz * (Z + phase[2]) / period
         if d == 0:
-            u[0] = np.sin(X) * np.cos(Y) * np.cos(Z)
+            u[0] = (np.sin(X) * np.cos(Y)) * np.cos(Z)
         else:
-            u[1] = -np.cos(X) * np.sin(Y) * np.cos(Z)
+            u[1] = -(np.cos(X) * np.sin(Y)) * np.cos(Z)
     return u
 
 
