@@ -82,6 +82,10 @@ typedef struct gmg_params {
   int32_t nu_coarse;     /* sweeps on the coarsest level, no direct solve (4) */
   int32_t rollback;      /* 1: a V-cycle that grows the residual is discarded
                             (default 1)                                        */
+  int32_t graphs;        /* 1: replay the solve's V-cycle (and refinement step)
+                            as a captured HIP graph (default); 0: launch each
+                            kernel directly.  Results are identical.           */
+  int32_t reserved;      /* must be 0                                          */
   double omega0;         /* relaxation factor at the start of a solve (1.0)   */
   double omega_min;      /* lower bound (0.1)                                 */
   double omega_max;      /* upper bound (1.0)                                 */
@@ -197,6 +201,63 @@ gmg_status gmg_vcycle(gmg_handle* h, void* x, const void* sigma,
  * info (host, may be NULL) is filled in both cases.  Synchronises. */
 gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol,
                      int32_t max_cycles, gmg_solve_info* info);
+
+/* Filled by gmg_solve_ir.  history[m] is ||sigma - A x||/||sigma|| (FP64,
+ * exact faces) before outer step m, and after the last one. */
+typedef struct gmg_ir_info {
+  int32_t status;        /* GMG_OK or GMG_ENOCONV                              */
+  int32_t outer;         /* refinement steps applied                           */
+  int32_t inner_total;   /* inner V-cycles over all steps                      */
+  int32_t pad;
+  double snorm;          /* ||sigma|| over the active cells (FP64)             */
+  double rnorm;          /* final ||sigma - A x|| (FP64)                       */
+  double history[GMG_MAX_HISTORY];
+  int32_t inner_cycles[GMG_MAX_HISTORY];
+} gmg_ir_info;
+
+/* Mixed-precision iterative refinement: the residual and the update are FP64
+ * on the exact level-0 faces, the corrections come from FP32 V-cycles on the
+ * stored (FP32 or BF16) hierarchy.  Needs a handle with dtype F64 and
+ * cycle_dtype F32.  Outer step m:
+ *   r = sigma - A x (FP64); stop if ||r|| <= rtol ||sigma|| or m == max_outer;
+ *   beta = ||r|| / sqrt(#active cells); b = fp32(r / beta);
+ *   e = adaptive FP32 GMG solve of A e = b from e = 0 (omega reset to omega0,
+ *       same rule as gmg_solve) until ||b - A e|| <= inner_rtol ||b|| or
+ *       max_inner cycles;
+ *   x += beta * e (FP64).
+ * x (in: initial guess, out: solution) and sigma are device FP64 arrays of the
+ * level-0 shape.  All decisions are taken on the device; the host polls one
+ * flag per outer step.  Returns GMG_OK or GMG_ENOCONV; info may be NULL.
+ * Synchronises the stream. */
+gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rtol,
+                        int32_t max_outer, int32_t max_inner, double inner_rtol,
+                        gmg_ir_info* info);
+
+typedef struct gmg_batch gmg_batch;
+
+/* Set up a batch of nprob independent problems of (possibly) different sizes
+ * for gmg_batch_solve_ir.  params: host array of nprob parameter sets, each
+ * with dtype F64 and cycle_dtype F32, all sharing l_storage, the sweep counts
+ * (with nu_coarse == nu_pre + nu_post) and the relaxation rule.  L: host array
+ * of nprob device pointers to FP64 faces ([3][nz][ny][nx] of each problem).
+ * Each problem gets its own hierarchy as in gmg_setup; device descriptor
+ * tables let one launch cover the same step of every problem.  The caller
+ * may free the L arrays after the call.  Synchronises the stream. */
+gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32_t nprob,
+                           void* stream, gmg_batch** out);
+
+/* Iterative refinement (as gmg_solve_ir) of every problem of the batch, all
+ * recorded into ONE HIP graph and launched once (the graph is kept and
+ * replayed while x, sigma and the tolerances stay the same).  x, sigma: host
+ * arrays of nprob device FP64 pointers.  Problems that converge become no-ops
+ * inside the graph.  infos: host array of nprob results, or NULL.  Returns
+ * GMG_ENOCONV if any problem missed rtol.  Synchronises the stream. */
+gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* const* sigma,
+                              double rtol, int32_t max_outer, int32_t max_inner,
+                              double inner_rtol, gmg_ir_info* infos);
+
+/* Free the batch and all its problems.  NULL is accepted. */
+gmg_status gmg_batch_destroy(gmg_batch* b);
 
 /* Thread-local description of the last error ("" if none). */
 const char* gmg_last_error(void);

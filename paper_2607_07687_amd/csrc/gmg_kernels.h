@@ -28,6 +28,23 @@ struct SolveState {
   int acc[GMG_MAX_HISTORY];
 };
 
+// Device-resident state of the mixed-precision iterative refinement.
+struct IRState {
+  double snorm;    // ||sigma|| (FP64, active cells)
+  double rnorm;    // latest ||sigma - A x|| (FP64)
+  double beta;     // scale of the current correction problem
+  double rtol;
+  int outer;       // refinement steps applied
+  int done;
+  int status;
+  int max_outer;
+  int inner_total;
+  int n_active;
+  int pad0, pad1;
+  double hist[GMG_MAX_HISTORY];
+  int inner[GMG_MAX_HISTORY];
+};
+
 // Adaptive-relaxation constants, passed by value.
 struct OmegaRule {
   double omega_min, omega_max, theta_dec, theta_inc;

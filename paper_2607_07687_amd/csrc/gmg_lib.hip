@@ -18,8 +18,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "gmg_kernels.h"
+#include "gmg_sweep.h"
 
 using namespace gmg;
 
@@ -54,48 +56,56 @@ static gmg_status fail(gmg_status s, const std::string& msg) {
 
 __device__ __forceinline__ bool stopped(const int* done) { return done != nullptr && *done; }
 
-// Which level-0 buffer a cycle kernel reads (src) and works on (dst).  With a
-// selector, the accepted iterate is in xa when *sel == 0 and in xb otherwise,
-// and the cycle's work buffer is the other one; without one, both are xb.
+// Iterate buffers of a level by role.  Level 0 has three buffers whose roles
+// rotate on the device: role 0 is the accepted iterate, roles 1 and 2 are the
+// cycle's ping-pong work buffers; with a selector, buffer (*sel + role) % 3
+// plays `role`.  Coarse levels (and calls without a selector) use the
+// buffers directly by role.
 template <typename T>
-__device__ __forceinline__ void pick(T* xa, T* xb, const int* sel, T*& src, T*& dst) {
-  if (sel == nullptr) {
-    src = xa;
-    dst = xb;
-  } else if (*sel) {
-    src = xb;
-    dst = xa;
-  } else {
-    src = xa;
-    dst = xb;
+struct Roles {
+  T* p[3];
+  const int* sel;
+  __device__ __forceinline__ T* get(int role) const {
+    const int base = (sel != nullptr) ? *sel : 0;
+    return p[(base + role) % 3];
   }
-}
+};
 
-// r = sigma - A x on active cells (0 elsewhere); optional store of r and
-// per-block partial sums of r^2 (FP64).
+// r = sigma - A x on active cells (0 elsewhere) for column (i, j) over the
+// z-planes [k0, k1); optional store of r; returns the column's sum of r^2.
 template <typename T, typename TL>
-__global__ __launch_bounds__(BT) void k_residual(Geom g, const T* xa, const T* xb,
-                                                 const int* sel, int use_dst,
-                                                 const T* __restrict__ sigma,
-                                                 const TL* __restrict__ L, T* r,
-                                                 double* partials, const int* done) {
-  if (stopped(done)) return;
-  T *src, *dst;
-  pick(const_cast<T*>(xa), const_cast<T*>(xb), sel, src, dst);
-  const T* x = use_dst ? dst : src;
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
+__device__ __forceinline__ double residual_column(const Geom& g, const T* __restrict__ x,
+                                                  const T* __restrict__ sigma,
+                                                  const TL* __restrict__ L, T* r, int i, int j,
+                                                  int k0, int k1) {
   double acc = 0.0;
   if (i < g.nx && j < g.ny) {
-    const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
-    const T xc = x[idx];
-    T D;
-    const T ax = stencil_Ax<T, TL>(g, x, L, idx, i, j, k, xc, D);
-    const T rv = (D != T(0)) ? sigma[idx] - ax : T(0);
-    if (r) r[idx] = rv;
-    acc = (double)rv * (double)rv;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+      const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
+      const T xc = x[idx];
+      T D;
+      const T ax = stencil_Ax<T, TL>(g, x, L, idx, i, j, k, xc, D);
+      const T rv = (D != T(0)) ? sigma[idx] - ax : T(0);
+      if (r) r[idx] = rv;
+      acc += (double)rv * (double)rv;
+    }
   }
+  return acc;
+}
+
+// r = sigma - A x over a chunk of z-planes; one FP64 partial of r^2 per block.
+template <typename T, typename TL>
+__global__ __launch_bounds__(BT) void k_residual(Geom g, Roles<T> X, int role,
+                                                 const T* __restrict__ sigma,
+                                                 const TL* __restrict__ L, T* r,
+                                                 double* partials, int kchunk, const int* done) {
+  if (stopped(done)) return;
+  const int k0 = blockIdx.z * kchunk;
+  const double acc = residual_column<T, TL>(g, X.get(role), sigma, L, r,
+                                            blockIdx.x * BX + threadIdx.x,
+                                            blockIdx.y * BY + threadIdx.y, k0,
+                                            min(g.nz, k0 + kchunk));
   if (partials) {
     const int tid = threadIdx.x + BX * threadIdx.y;
     const double s = block_sum(acc, tid, BT);
@@ -104,18 +114,20 @@ __global__ __launch_bounds__(BT) void k_residual(Geom g, const T* xa, const T* x
   }
 }
 
-// Sum of v^2 over active cells (mask != 0), per-block partials.
+// Sum of v^2 over active cells (mask != 0), per-block partials, z-chunked.
 template <typename T>
 __global__ __launch_bounds__(BT) void k_masked_sumsq(Geom g, const T* __restrict__ v,
                                                      const uint8_t* __restrict__ mask,
-                                                     double* partials) {
+                                                     double* partials, int kchunk) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
+  const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
   double acc = 0.0;
   if (i < g.nx && j < g.ny) {
-    const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
-    if (mask[idx]) acc = (double)v[idx] * (double)v[idx];
+    for (int k = k0; k < k1; ++k) {
+      const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
+      if (mask[idx]) acc += (double)v[idx] * (double)v[idx];
+    }
   }
   const int tid = threadIdx.x + BX * threadIdx.y;
   const double s = block_sum(acc, tid, BT);
@@ -123,51 +135,81 @@ __global__ __launch_bounds__(BT) void k_masked_sumsq(Geom g, const T* __restrict
     partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
 
-// One red-black half-sweep of colour `colour`: each thread owns the pair of
-// x-cells (2p, 2p+1) of its row and updates the one with (i+j+k)%2 == colour
-// from the residual of the pre-sweep iterate.  mode 0: in place on dst.
-// mode 1: reads src, writes the updated colour AND copies the other colour
-// into dst (first half-sweep of a cycle that keeps src for rollback).
+// Fused residual + restriction, one thread per FINE cell of the 64 x 4 tile
+// at (i0, j0): each thread sums the residuals of its column over the cz fine
+// planes of coarse plane K; x-pairs are combined by a lane shuffle and y-pairs
+// through LDS; the thread at each block's origin writes sigma_c and zeroes x_c.
 template <typename T, typename TL>
-__global__ __launch_bounds__(BT) void k_rb_half(Geom g, T* xa, T* xb, const int* sel, int mode,
-                                                const T* __restrict__ sigma,
-                                                const TL* __restrict__ L, int colour,
-                                                const double* omega_p, const int* done) {
-  if (stopped(done)) return;
-  T *src, *dst;
-  pick(xa, xb, sel, src, dst);
-  const T* x = mode ? src : dst;
-  const int p = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  if (j >= g.ny) return;
-  const int par = (j + k + colour) & 1;
-  const int i = 2 * p + par;
-  const long long row = (long long)k * g.sz + (long long)j * g.sy;
-  if (mode) {
-    const int io = 2 * p + (par ^ 1);
-    if (io < g.nx) dst[row + io] = src[row + io];
+__device__ __forceinline__ void restrict_tile(T (*rows)[BX], const Geom& gf,
+                                              const T* __restrict__ x,
+                                              const T* __restrict__ sigma,
+                                              const TL* __restrict__ L, const Geom& gc, int cx,
+                                              int cy, int cz, T* __restrict__ sigma_c,
+                                              T* __restrict__ x_c, int i0, int j0, int K) {
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i = i0 + tx, j = j0 + ty;
+  T acc = T(0);
+  if (i < gf.nx && j < gf.ny) {
+    for (int sz = 0; sz < cz; ++sz) {
+      const int k = K * cz + sz;
+      const long long idx = (long long)k * gf.sz + (long long)j * gf.sy + i;
+      const T xc = x[idx];
+      T D;
+      const T ax = stencil_Ax<T, TL>(gf, x, L, idx, i, j, k, xc, D);
+      if (D != T(0)) acc += sigma[idx] - ax;
+    }
   }
-  if (i >= g.nx) return;
-  const long long idx = row + i;
-  const T xc = x[idx];
-  T D;
-  const T ax = stencil_Ax<T, TL>(g, x, L, idx, i, j, k, xc, D);
-  T xn = xc;
-  if (D != T(0)) {
-    const T omega = (T)(*omega_p);
-    xn = xc + omega * (sigma[idx] - ax) / D;
+  if (cx == 2) acc += __shfl_xor(acc, 1, 64);
+  if (cy == 2) {
+    rows[ty][tx] = acc;
+    __syncthreads();
+    acc += rows[ty ^ 1][tx];
   }
-  dst[idx] = xn;
+  if (i < gf.nx && j < gf.ny && (i % cx) == 0 && (j % cy) == 0) {
+    const long long cidx = (long long)K * gc.sz + (long long)(j / cy) * gc.sy + i / cx;
+    sigma_c[cidx] = acc;
+    if (x_c) x_c[cidx] = T(0);
+  }
 }
 
-// Copy src -> dst (level-0 work buffer initialisation when no pre-sweep runs).
-template <typename T>
-__global__ __launch_bounds__(BT) void k_copy_sel(Geom g, T* xa, T* xb, const int* sel,
-                                                 const int* done) {
+template <typename T, typename TL>
+__global__ __launch_bounds__(BT) void k_restrict_residual(
+    Geom gf, Roles<T> X, int role, const T* __restrict__ sigma, const TL* __restrict__ L,
+    Geom gc, int cx, int cy, int cz, T* __restrict__ sigma_c, T* __restrict__ x_c,
+    const int* done) {
   if (stopped(done)) return;
-  T *src, *dst;
-  pick(xa, xb, sel, src, dst);
+  __shared__ T rows[BY][BX];
+  restrict_tile<T, TL>(rows, gf, X.get(role), sigma, L, gc, cx, cy, cz, sigma_c, x_c,
+                       blockIdx.x * BX, blockIdx.y * BY, blockIdx.z);
+}
+
+// Piecewise-constant prolongation + correction on active fine cells:
+// X[rd] = X[rs] + P x_c (in place when rs == rd).
+template <typename T>
+__global__ __launch_bounds__(BT) void k_prolong(Geom gf, Roles<T> X, int rs, int rd,
+                                                const uint8_t* __restrict__ active,
+                                                const T* __restrict__ x_c, Geom gc, int cx,
+                                                int cy, int cz, const int* done) {
+  if (stopped(done)) return;
+  const T* src = X.get(rs);
+  T* dst = X.get(rd);
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= gf.nx || j >= gf.ny) return;
+  const long long idx = (long long)k * gf.sz + (long long)j * gf.sy + i;
+  T v = src[idx];
+  if (active[idx]) v += x_c[(long long)(k / cz) * gc.sz + (long long)(j / cy) * gc.sy + i / cx];
+  dst[idx] = v;
+}
+
+// Copy X[rs] -> X[rd].
+template <typename T>
+__global__ __launch_bounds__(BT) void k_copy_role(Geom g, Roles<T> X, int rs, int rd,
+                                                  const int* done) {
+  if (stopped(done)) return;
+  const T* src = X.get(rs);
+  T* dst = X.get(rd);
   const int i = blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
@@ -175,58 +217,21 @@ __global__ __launch_bounds__(BT) void k_copy_sel(Geom g, T* xa, T* xb, const int
   dst[idx] = src[idx];
 }
 
-// Fused residual + restriction: one thread per coarse cell J sums the fine
-// residuals over its c-block and zeroes the coarse initial guess.
-template <typename T, typename TL>
-__global__ __launch_bounds__(BT) void k_restrict_residual(
-    Geom gf, const T* xa, const T* xb, const int* sel, const T* __restrict__ sigma,
-    const TL* __restrict__ L, Geom gc, int cx, int cy, int cz, T* __restrict__ sigma_c,
-    T* __restrict__ x_c, const int* done) {
+// Fused red-black sweep X[rd] = sweep(X[rs] (+ P x_c)), see gmg_sweep.h.
+template <typename T, typename TL, int TY, int VEC>
+__global__ __launch_bounds__(32 * TY) void k_rb_sweep(Geom g, Roles<T> X, int rs, int rd,
+                                                      const T* __restrict__ sigma,
+                                                      const TL* __restrict__ L,
+                                                      const T* __restrict__ xc,
+                                                      const uint8_t* __restrict__ active, Geom gc,
+                                                      int cx, int cy, int cz, int kchunk,
+                                                      const double* omega_p, const int* done) {
   if (stopped(done)) return;
-  T *src, *dst;
-  pick(const_cast<T*>(xa), const_cast<T*>(xb), sel, src, dst);
-  const T* x = dst;
-  const int I = blockIdx.x * BX + threadIdx.x;
-  const int J = blockIdx.y * BY + threadIdx.y;
-  const int K = blockIdx.z;
-  if (I >= gc.nx || J >= gc.ny) return;
-  T acc = T(0);
-  for (int sz = 0; sz < cz; ++sz) {
-    const int k = K * cz + sz;
-    for (int sy = 0; sy < cy; ++sy) {
-      const int j = J * cy + sy;
-      for (int sx = 0; sx < cx; ++sx) {
-        const int i = I * cx + sx;
-        const long long idx = (long long)k * gf.sz + (long long)j * gf.sy + i;
-        const T xc = x[idx];
-        T D;
-        const T ax = stencil_Ax<T, TL>(gf, x, L, idx, i, j, k, xc, D);
-        if (D != T(0)) acc += sigma[idx] - ax;
-      }
-    }
-  }
-  const long long cidx = (long long)K * gc.sz + (long long)J * gc.sy + I;
-  sigma_c[cidx] = acc;
-  if (x_c) x_c[cidx] = T(0);
-}
-
-// Piecewise-constant prolongation + correction on active fine cells.
-template <typename T>
-__global__ __launch_bounds__(BT) void k_prolong(Geom gf, T* xa, T* xb, const int* sel,
-                                                const uint8_t* __restrict__ active,
-                                                const T* __restrict__ x_c, Geom gc, int cx,
-                                                int cy, int cz, const int* done) {
-  if (stopped(done)) return;
-  T *src, *dst;
-  pick(xa, xb, sel, src, dst);
-  const int i = blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= gf.nx || j >= gf.ny) return;
-  const long long idx = (long long)k * gf.sz + (long long)j * gf.sy + i;
-  if (!active[idx]) return;
-  const long long cidx = (long long)(k / cz) * gc.sz + (long long)(j / cy) * gc.sy + i / cx;
-  dst[idx] += x_c[cidx];
+  __shared__ SweepSmem<T, TY> sm;
+  SweepArgs<T, TL, TY, VEC> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
+  const int k0 = blockIdx.z * kchunk;
+  rb_sweep_tile<T, TL, TY, VEC>(sm, a, X.get(rd), blockIdx.x * SW_TX, blockIdx.y * TY, k0,
+                                min(g.nz, k0 + kchunk), (T)(*omega_p));
 }
 
 // Level-0 face copy from the caller's dtype into storage, zeroing the low
@@ -312,7 +317,9 @@ __device__ double reduce_partials(const double* p, long long n) {
 __global__ __launch_bounds__(256) void k_solve_init(const double* pa, long long na,
                                                     const double* pb, long long nb,
                                                     SolveState* st, double rtol,
-                                                    int max_cycles, double omega0) {
+                                                    int max_cycles, double omega0,
+                                                    const int* skip) {
+  if (skip != nullptr && *skip) return;
   const double ss = reduce_partials(pa, na);
   __syncthreads();
   const double rr = reduce_partials(pb, nb);
@@ -334,7 +341,8 @@ __global__ __launch_bounds__(256) void k_solve_init(const double* pa, long long 
 // End of a V-cycle: new residual norm, the adaptive-relaxation decision
 // (Sec. 3.1) and the convergence flag.
 __global__ __launch_bounds__(256) void k_cycle_finish(const double* p, long long n,
-                                                      SolveState* st, OmegaRule rule) {
+                                                      SolveState* st, OmegaRule rule,
+                                                      int final_role) {
   if (st->done) return;
   const double rr = reduce_partials(p, n);
   if (threadIdx.x != 0) return;
@@ -345,24 +353,23 @@ __global__ __launch_bounds__(256) void k_cycle_finish(const double* p, long long
     st->omegas[c] = st->omega;
   }
   st->last = rn;
-  int accept;
-  if (rn > st->rho) {  // growth
+  // the cycle's result sits in role `final_role`; accepting it makes that
+  // buffer the new role 0
+  const int next = (st->cur + final_role) % 3;
+  if (rn > st->rho) {  // growth: lower omega, and discard the cycle with rollback
     st->omega = fmax(rule.omega_min, rule.theta_dec * st->omega);
-    accept = rule.rollback ? 0 : 1;
     if (c < GMG_MAX_HISTORY) st->acc[c] = rule.rollback ? 0 : 1;
     if (!rule.rollback) {
-      st->cur ^= 1;
+      st->cur = next;
       st->rho = rn;
     }
-  } else {
-    st->cur ^= 1;
+  } else {  // decay (or a tie): keep the cycle and raise omega
+    st->cur = next;
     st->rho = rn;
     st->omega = fmin(rule.omega_max, rule.theta_inc * st->omega);
     st->accepted += 1;
-    accept = 1;
     if (c < GMG_MAX_HISTORY) st->acc[c] = 1;
   }
-  (void)accept;
   st->cycles = c + 1;
   const bool conv = st->rho <= st->rtol * st->snorm;
   if (conv) st->status = 0;
@@ -376,6 +383,106 @@ __global__ __launch_bounds__(256) void k_sum_to(const double* p, long long n, do
   if (threadIdx.x == 0) *out = s;
 }
 
+// Number of active cells (per-block partials, z-chunked).
+__global__ __launch_bounds__(BT) void k_count_mask(Geom g, const uint8_t* __restrict__ mask,
+                                                   double* partials, int kchunk) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+  double acc = 0.0;
+  if (i < g.nx && j < g.ny)
+    for (int k = k0; k < k1; ++k) acc += mask[(long long)k * g.sz + (long long)j * g.sy + i];
+  const int tid = threadIdx.x + BX * threadIdx.y;
+  const double s = block_sum(acc, tid, BT);
+  if (tid == 0)
+    partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+}
+
+// Start of a refinement solve: ||sigma|| and the active-cell count.
+__global__ __launch_bounds__(256) void k_ir_init(const double* ps, const double* pc, long long n,
+                                                 IRState* ir, SolveState* inner, double rtol,
+                                                 int max_outer) {
+  const double ss = reduce_partials(ps, n);
+  __syncthreads();
+  const double cnt = reduce_partials(pc, n);
+  if (threadIdx.x == 0) {
+    ir->snorm = sqrt(ss);
+    ir->n_active = (int)cnt;
+    ir->rtol = rtol;
+    ir->outer = 0;
+    ir->inner_total = 0;
+    ir->max_outer = max_outer;
+    ir->done = 0;
+    ir->status = 5;
+    inner->done = 1;
+  }
+}
+
+// Outer-step check on the FP64 residual norm: converged, out of steps, or the
+// scale beta = ||r|| / sqrt(#active) of the next correction problem.
+__global__ __launch_bounds__(256) void k_ir_check(const double* p, long long n, IRState* ir) {
+  if (ir->done) return;
+  const double rr = reduce_partials(p, n);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(rr);
+  ir->rnorm = rn;
+  if (ir->outer < GMG_MAX_HISTORY) ir->hist[ir->outer] = (ir->snorm > 0.0) ? rn / ir->snorm : 0.0;
+  if (ir->snorm == 0.0 || rn <= ir->rtol * ir->snorm) {
+    ir->status = 0;
+    ir->done = 1;
+  } else if (ir->outer >= ir->max_outer) {
+    ir->done = 1;
+  } else {
+    ir->beta = rn / sqrt((double)max(ir->n_active, 1));
+  }
+}
+
+// b = fp32(r / beta) and the inner initial guess e = 0; partials of b^2.
+__global__ __launch_bounds__(BT) void k_scale_cast(Geom g, const double* __restrict__ r,
+                                                   const IRState* ir, float* __restrict__ b,
+                                                   float* __restrict__ e, double* partials,
+                                                   int kchunk) {
+  if (ir->done) return;
+  const double inv = 1.0 / ir->beta;
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+  double acc = 0.0;
+  if (i < g.nx && j < g.ny)
+    for (int k = k0; k < k1; ++k) {
+      const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
+      const float v = (float)(r[idx] * inv);
+      b[idx] = v;
+      e[idx] = 0.0f;
+      acc += (double)v * (double)v;
+    }
+  const int tid = threadIdx.x + BX * threadIdx.y;
+  const double s = block_sum(acc, tid, BT);
+  if (tid == 0)
+    partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+}
+
+// x += beta * e in FP64; block (0,0,0) also books the step.
+__global__ __launch_bounds__(BT) void k_ir_update(Geom g, double* __restrict__ x, Roles<float> E,
+                                                  IRState* ir, const SolveState* inner) {
+  if (ir->done) return;
+  const float* e = E.get(0);
+  const double beta = ir->beta;
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i < g.nx && j < g.ny) {
+    const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
+    x[idx] += beta * (double)e[idx];
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0 &&
+      threadIdx.y == 0) {
+    if (ir->outer < GMG_MAX_HISTORY) ir->inner[ir->outer] = inner->cycles;
+    ir->inner_total += inner->cycles;
+    ir->outer += 1;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Handle
 // ---------------------------------------------------------------------------
@@ -383,14 +490,16 @@ __global__ __launch_bounds__(256) void k_sum_to(const double* p, long long n, do
 namespace {
 
 constexpr int kMaxLevels = 32;
+constexpr int kResChunk = 16;  // z-planes per block in the norm reductions
 
 struct Level {
   Geom g;
-  int c[3];      // factor to the next level; 0 on the coarsest
-  void* L;       // [3][nz][ny][nx] in l_storage
+  int c[3];        // factor to the next level; 0 on the coarsest
+  void* L;         // [3][nz][ny][nx] in l_storage
   uint8_t* active;
-  void* x;       // cycle dtype (levels >= 1)
+  void* x[2];      // cycle dtype ping-pong iterates (levels >= 1)
   void* sigma;
+  int kchunk;      // z-planes per workgroup of the fused sweep
 };
 
 size_t dsize(int dt) { return dt == GMG_F64 ? 8 : (dt == GMG_BF16 ? 2 : 4); }
@@ -410,13 +519,31 @@ Geom make_geom(const int n[3], const int per[3]) {
 }
 
 dim3 cell_grid(const Geom& g) { return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz); }
-dim3 pair_grid(const Geom& g) {
-  const int np = (g.nx + 1) / 2;
-  return dim3((np + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
+dim3 red_grid(const Geom& g) {
+  return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + kResChunk - 1) / kResChunk);
 }
 long long nblocks(dim3 d) { return (long long)d.x * d.y * d.z; }
 
+// Fused-sweep tile height per precision (LDS budget: six 3-plane rings).
+template <typename T> struct SweepTY { static constexpr int v = 8; };
+template <> struct SweepTY<double> { static constexpr int v = 4; };
+
+// z-chunk of the fused sweep: aim for >= 1024 workgroups, at least 4 planes.
+int sweep_kchunk(const Geom& g, int ty) {
+  const long long tiles = (long long)((g.nx + SW_TX - 1) / SW_TX) * ((g.ny + ty - 1) / ty);
+  int kc = g.nz;
+  while (kc > 4 && tiles * ((g.nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
+  return kc;
+}
+
 }  // namespace
+
+// A captured kernel sequence keyed by the caller pointers baked into it.
+struct CapturedSeq {
+  hipGraphExec_t exec;
+  const void* k0;
+  const void* k1;
+};
 
 struct gmg_handle {
   gmg_params p;
@@ -424,12 +551,24 @@ struct gmg_handle {
   int nlev;
   Level lev[kMaxLevels];
   void* L0x;     // exact FP64 level-0 faces (dtype F64 with F32 cycles)
-  void* xwork;   // second level-0 iterate (cycle dtype)
+  void* w[2];    // level-0 work iterates (cycle dtype); the caller's x is the third
   double* partials;  // 2 * maxpart
   long long maxpart;
   SolveState* st;
   SolveState* hst;   // pinned host mirror
   OmegaRule rule;
+  // iterative refinement (dtype F64 with F32 cycles)
+  IRState* ir;
+  IRState* hir;      // pinned host mirror
+  double* r64;       // FP64 outer residual
+  float* b32;        // scaled, rounded correction right-hand side
+  float* e32;        // correction (role 0 of the inner solve)
+  // captured launch sequences, replayed with hipGraphLaunch
+  hipStream_t cap;   // capture stream (the caller's may be the legacy stream)
+  CapturedSeq cyc;   // one V-cycle of gmg_solve
+  CapturedSeq irs;   // one outer step of gmg_solve_ir
+  int ir_inner;      // max_inner / inner_rtol recorded in irs
+  double ir_inner_rtol;
 };
 
 static const dim3 kBlock(BX, BY, 1);
@@ -438,76 +577,112 @@ static const dim3 kBlock(BX, BY, 1);
 // Typed enqueue helpers
 // ---------------------------------------------------------------------------
 
+template <typename T>
+static Roles<T> level_roles(gmg_handle* h, int l, T* x0, const int* sel) {
+  Roles<T> R;
+  if (l == 0) {
+    R.p[0] = x0;
+    R.p[1] = (T*)h->w[0];
+    R.p[2] = (T*)h->w[1];
+    R.sel = sel;
+  } else {
+    R.p[0] = (T*)h->lev[l].x[0];
+    R.p[1] = (T*)h->lev[l].x[1];
+    R.p[2] = (T*)h->lev[l].x[0];  // unused
+    R.sel = nullptr;
+  }
+  return R;
+}
+
+// next ping-pong role: level 0 cycles 0 -> 1 -> 2 -> 1 -> 2 ... so that the
+// accepted iterate (role 0) is never written; coarse levels alternate 0 <-> 1
+static int next_role(int l, int r) { return l == 0 ? (r == 1 ? 2 : 1) : 1 - r; }
+
 template <typename T, typename TL>
-static void enq_half(gmg_handle* h, int l, T* xa, T* xb, const int* sel, int mode,
-                     const T* sigma, int colour, const int* done) {
+static void enq_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
+                      const T* xc, const int* done) {
+  constexpr int TY = SweepTY<T>::v;
   const Level& lv = h->lev[l];
-  hipLaunchKernelGGL((k_rb_half<T, TL>), pair_grid(lv.g), kBlock, 0, h->s, lv.g, xa, xb, sel,
-                     mode, sigma, (const TL*)lv.L, colour, &h->st->omega, done);
+  const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
+  const dim3 grid((lv.g.nx + SW_TX - 1) / SW_TX, (lv.g.ny + TY - 1) / TY,
+                  (lv.g.nz + lv.kchunk - 1) / lv.kchunk);
+  const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
+  if (lv.g.nx % 2 == 0)
+    hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 2>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,
+                       sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, lv.kchunk,
+                       &h->st->omega, done);
+  else
+    hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 1>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,
+                       sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, lv.kchunk,
+                       &h->st->omega, done);
 }
 
 template <typename T, typename TL>
-static void enq_sweeps(gmg_handle* h, int l, T* xa, T* xb, const int* sel, int& first_copy,
-                       const T* sigma, int sweeps, const int* done) {
-  for (int s = 0; s < sweeps; ++s)
-    for (int c = 0; c < 2; ++c) {
-      enq_half<T, TL>(h, l, xa, xb, sel, first_copy, sigma, c, done);
-      first_copy = 0;
-    }
+static void enq_restrict(gmg_handle* h, int l, const Roles<T>& X, int role, const T* sigma,
+                         T* sigma_c, T* x_c, const int* done) {
+  const Level& lv = h->lev[l];
+  const Level& lc = h->lev[l + 1];
+  const dim3 grid((lv.g.nx + BX - 1) / BX, (lv.g.ny + BY - 1) / BY, lc.g.nz);
+  hipLaunchKernelGGL((k_restrict_residual<T, TL>), grid, kBlock, 0, h->s, lv.g, X, role, sigma,
+                     (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c, done);
 }
 
-// V-cycle from level 0 with the level-0 iterate selected by (xa, xb, sel);
-// `copy` = 1 makes the first level-0 operation read src and fill dst.
+// V-cycle from level 0.  X0 is the level-0 role-0 buffer (with `sel`, the
+// roles rotate on the device).  Returns the level-0 role of the result.
 template <typename T, typename TL>
-static void enq_vcycle(gmg_handle* h, T* xa, T* xb, const int* sel, int copy,
-                       const T* sigma0, const int* done) {
+static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, const int* done) {
   const int nl = h->nlev;
   const gmg_params& p = h->p;
-  // descend
+  int role[kMaxLevels];
+  // descend: pre-smooth, then restrict the residual (coarse x starts at 0)
   for (int l = 0; l < nl; ++l) {
-    T* a = (l == 0) ? xa : (T*)h->lev[l].x;
-    T* b = (l == 0) ? xb : (T*)h->lev[l].x;
-    const int* sl = (l == 0) ? sel : nullptr;
+    const Roles<T> X = level_roles<T>(h, l, X0, sel);
     const T* sg = (l == 0) ? sigma0 : (const T*)h->lev[l].sigma;
-    int fc = (l == 0) ? copy : 0;
     const bool coarsest = (l == nl - 1);
-    enq_sweeps<T, TL>(h, l, a, b, sl, fc, sg, coarsest ? p.nu_coarse : p.nu_pre, done);
-    if (fc) {  // no sweep ran on level 0: initialise the work buffer
-      const Level& lv = h->lev[l];
-      hipLaunchKernelGGL((k_copy_sel<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, a, b, sl, done);
+    int r = 0;
+    const int nsw = coarsest ? p.nu_coarse : p.nu_pre;
+    for (int s = 0; s < nsw; ++s) {
+      const int rd = next_role(l, r);
+      enq_sweep<T, TL>(h, l, X, r, rd, sg, nullptr, done);
+      r = rd;
     }
+    role[l] = r;
     if (coarsest) break;
-    const Level& lv = h->lev[l];
-    const Level& lc = h->lev[l + 1];
-    hipLaunchKernelGGL((k_restrict_residual<T, TL>), cell_grid(lc.g), kBlock, 0, h->s, lv.g,
-                       (const T*)a, (const T*)b, sl, sg, (const TL*)lv.L, lc.g, lv.c[0], lv.c[1],
-                       lv.c[2], (T*)lc.sigma, (T*)lc.x, done);
+    enq_restrict<T, TL>(h, l, X, r, sg, (T*)h->lev[l + 1].sigma, (T*)h->lev[l + 1].x[0], done);
   }
-  // ascend
+  // ascend: prolong + correct (folded into the first post-sweep), post-smooth
   for (int l = nl - 2; l >= 0; --l) {
-    T* a = (l == 0) ? xa : (T*)h->lev[l].x;
-    T* b = (l == 0) ? xb : (T*)h->lev[l].x;
-    const int* sl = (l == 0) ? sel : nullptr;
+    const Roles<T> X = level_roles<T>(h, l, X0, sel);
     const T* sg = (l == 0) ? sigma0 : (const T*)h->lev[l].sigma;
     const Level& lv = h->lev[l];
-    const Level& lc = h->lev[l + 1];
-    hipLaunchKernelGGL((k_prolong<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, a, b, sl,
-                       lv.active, (const T*)lc.x, lc.g, lv.c[0], lv.c[1], lv.c[2], done);
-    int fc = 0;
-    enq_sweeps<T, TL>(h, l, a, b, sl, fc, sg, p.nu_post, done);
+    const T* xc = (const T*)h->lev[l + 1].x[role[l + 1]];
+    int r = role[l];
+    if (p.nu_post > 0) {
+      for (int s = 0; s < p.nu_post; ++s) {
+        const int rd = next_role(l, r);
+        enq_sweep<T, TL>(h, l, X, r, rd, sg, s == 0 ? xc : nullptr, done);
+        r = rd;
+      }
+    } else {
+      const int rd = (l == 0 && r == 0) ? 1 : r;  // never modify the accepted iterate
+      const Level& lc = h->lev[l + 1];
+      hipLaunchKernelGGL((k_prolong<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, X, r, rd,
+                         lv.active, xc, lc.g, lv.c[0], lv.c[1], lv.c[2], done);
+      r = rd;
+    }
+    role[l] = r;
   }
+  return role[0];
 }
 
-// Level-0 residual norm partials into partials[off ...].  use_dst selects the
-// work buffer of (xa, xb, sel).  Returns the partial count.
+// Level-0 residual-norm partials of role `role` into partials[off ...].
 template <typename T, typename TL>
-static long long enq_resnorm(gmg_handle* h, const T* xa, const T* xb, const int* sel,
-                             int use_dst, const T* sigma, const TL* L, T* r, long long off,
-                             const int* done) {
+static long long enq_resnorm(gmg_handle* h, const Roles<T>& X, int role, const T* sigma,
+                             const TL* L, T* r, long long off, const int* done) {
   const Level& lv = h->lev[0];
-  const dim3 gr = cell_grid(lv.g);
-  hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, xa, xb, sel, use_dst,
-                     sigma, L, r, h->partials + off, done);
+  const dim3 gr = red_grid(lv.g);
+  hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, X, role, sigma, L, r,
+                     h->partials + off, kResChunk, done);
   return nblocks(gr);
 }
 
@@ -573,14 +748,24 @@ static void free_handle(gmg_handle* h) {
   for (int l = 0; l < h->nlev; ++l) {
     (void)hipFree(h->lev[l].L);
     (void)hipFree(h->lev[l].active);
-    (void)hipFree(h->lev[l].x);
+    (void)hipFree(h->lev[l].x[0]);
+    (void)hipFree(h->lev[l].x[1]);
     (void)hipFree(h->lev[l].sigma);
   }
   (void)hipFree(h->L0x);
-  (void)hipFree(h->xwork);
+  (void)hipFree(h->w[0]);
+  (void)hipFree(h->w[1]);
   (void)hipFree(h->partials);
   (void)hipFree(h->st);
   if (h->hst) (void)hipHostFree(h->hst);
+  (void)hipFree(h->ir);
+  if (h->hir) (void)hipHostFree(h->hir);
+  (void)hipFree(h->r64);
+  (void)hipFree(h->b32);
+  (void)hipFree(h->e32);
+  if (h->cyc.exec) (void)hipGraphExecDestroy(h->cyc.exec);
+  if (h->irs.exec) (void)hipGraphExecDestroy(h->irs.exec);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
 }
 
@@ -647,14 +832,18 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
     HIP_TRY(hipMalloc(&lv.L, 3 * lv.g.n * ls));
     HIP_TRY(hipMalloc(&lv.active, lv.g.n));
     if (l > 0) {
-      HIP_TRY(hipMalloc(&lv.x, lv.g.n * cs));
+      HIP_TRY(hipMalloc(&lv.x[0], lv.g.n * cs));
+      HIP_TRY(hipMalloc(&lv.x[1], lv.g.n * cs));
       HIP_TRY(hipMalloc(&lv.sigma, lv.g.n * cs));
     }
+    lv.kchunk = sweep_kchunk(lv.g, p->cycle_dtype == GMG_F64 ? SweepTY<double>::v
+                                                              : SweepTY<float>::v);
   }
-  maxpart = nblocks(cell_grid(h->lev[0].g));
+  maxpart = nblocks(red_grid(h->lev[0].g));
   h->maxpart = maxpart;
   HIP_TRY(hipMalloc(&h->partials, 2 * maxpart * sizeof(double)));
-  HIP_TRY(hipMalloc(&h->xwork, h->lev[0].g.n * cs));
+  HIP_TRY(hipMalloc(&h->w[0], h->lev[0].g.n * cs));
+  HIP_TRY(hipMalloc(&h->w[1], h->lev[0].g.n * cs));
   HIP_TRY(hipMalloc(&h->st, sizeof(SolveState)));
   HIP_TRY(hipHostMalloc((void**)&h->hst, sizeof(SolveState), hipHostMallocDefault));
   std::memset(h->hst, 0, sizeof(SolveState));
@@ -667,8 +856,14 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
     else if (p->l_storage == GMG_BF16) enq_copy_faces<double, uint16_t>(h, L, L0);
     else enq_copy_faces<double, float>(h, L, L0);
     if (p->cycle_dtype == GMG_F32) {
-      HIP_TRY(hipMalloc(&h->L0x, 3 * h->lev[0].g.n * sizeof(double)));
+      const long long n0 = h->lev[0].g.n;
+      HIP_TRY(hipMalloc(&h->L0x, 3 * n0 * sizeof(double)));
       enq_copy_faces<double, double>(h, L, h->L0x);
+      HIP_TRY(hipMalloc(&h->ir, sizeof(IRState)));
+      HIP_TRY(hipHostMalloc((void**)&h->hir, sizeof(IRState), hipHostMallocDefault));
+      HIP_TRY(hipMalloc(&h->r64, n0 * sizeof(double)));
+      HIP_TRY(hipMalloc(&h->b32, n0 * sizeof(float)));
+      HIP_TRY(hipMalloc(&h->e32, n0 * sizeof(float)));
     }
   } else {
     if (p->l_storage == GMG_BF16) enq_copy_faces<float, uint16_t>(h, L, L0);
@@ -687,6 +882,87 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
 // C ABI
 // ---------------------------------------------------------------------------
 
+// Record the launches of `enqueue` (which must only enqueue work on h->s)
+// into a graph on the capture stream, or reuse the one recorded for the same
+// key pointers.  On success *exec is ready for hipGraphLaunch on any stream.
+template <typename F>
+static gmg_status captured(gmg_handle* h, CapturedSeq& cs, const void* k0, const void* k1,
+                           F&& enqueue, hipGraphExec_t* exec) {
+  if (cs.exec && cs.k0 == k0 && cs.k1 == k1) {
+    *exec = cs.exec;
+    return GMG_OK;
+  }
+  if (cs.exec) {
+    HIP_TRY(hipGraphExecDestroy(cs.exec));
+    cs.exec = nullptr;
+  }
+  if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  hipStream_t orig = h->s;
+  h->s = h->cap;
+  HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  gmg_status st = enqueue();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap, &g);
+  h->s = orig;
+  if (st != GMG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(GMG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(&cs.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    cs.exec = nullptr;
+    return fail(GMG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+  }
+  cs.k0 = k0;
+  cs.k1 = k1;
+  *exec = cs.exec;
+  return GMG_OK;
+}
+
+// One cycle of the adaptive solve: V-cycle, residual norm, decision.
+template <typename T, typename TL>
+static gmg_status enq_solve_cycle(gmg_handle* h, T* xa, const T* sigma) {
+  const Level& lv = h->lev[0];
+  const long long np = nblocks(red_grid(lv.g));
+  const Roles<T> XS{{xa, (T*)h->w[0], (T*)h->w[1]}, &h->st->cur};
+  const int f = enq_vcycle<T, TL>(h, xa, &h->st->cur, sigma, &h->st->done);
+  enq_resnorm<T, TL>(h, XS, f, sigma, (const TL*)lv.L, nullptr, 0, &h->st->done);
+  hipLaunchKernelGGL(k_cycle_finish, dim3(1), dim3(256), 0, h->s, h->partials, np, h->st, h->rule,
+                     f);
+  HIP_TRY(hipGetLastError());
+  return GMG_OK;
+}
+
+template <typename TL>
+static gmg_status ir_outer_step(gmg_handle* h, double* x, const double* sigma, int max_inner,
+                                double inner_rtol) {
+  const Level& lv = h->lev[0];
+  const dim3 gr = red_grid(lv.g);
+  const long long np = nblocks(gr);
+  const Roles<double> X{{x, x, x}, nullptr};
+  hipLaunchKernelGGL((k_residual<double, double>), gr, kBlock, 0, h->s, lv.g, X, 0, sigma,
+                     (const double*)h->L0x, h->r64, h->partials, kResChunk, &h->ir->done);
+  hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(256), 0, h->s, h->partials, np, h->ir);
+  hipLaunchKernelGGL(k_scale_cast, gr, kBlock, 0, h->s, lv.g, (const double*)h->r64, h->ir,
+                     h->b32, h->e32, h->partials + h->maxpart, kResChunk);
+  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, h->s, h->partials + h->maxpart, np,
+                     h->partials + h->maxpart, np, h->st, inner_rtol, max_inner, h->p.omega0,
+                     &h->ir->done);
+  const Roles<float> XS{{h->e32, (float*)h->w[0], (float*)h->w[1]}, &h->st->cur};
+  for (int c = 0; c < max_inner; ++c) {
+    const int f = enq_vcycle<float, TL>(h, h->e32, &h->st->cur, h->b32, &h->st->done);
+    enq_resnorm<float, TL>(h, XS, f, h->b32, (const TL*)lv.L, nullptr, 0, &h->st->done);
+    hipLaunchKernelGGL(k_cycle_finish, dim3(1), dim3(256), 0, h->s, h->partials, np, h->st,
+                       h->rule, f);
+  }
+  hipLaunchKernelGGL(k_ir_update, cell_grid(lv.g), kBlock, 0, h->s, lv.g, x, XS, h->ir,
+                     (const SolveState*)h->st);
+  HIP_TRY(hipGetLastError());
+  return GMG_OK;
+}
+
 extern "C" {
 
 gmg_status gmg_default_params(gmg_params* p) {
@@ -703,6 +979,7 @@ gmg_status gmg_default_params(gmg_params* p) {
   p->nu_post = 2;
   p->nu_coarse = 4;
   p->rollback = 1;
+  p->graphs = 1;
   p->omega0 = 1.0;
   p->omega_min = 0.1;
   p->omega_max = 1.0;
@@ -763,29 +1040,29 @@ gmg_status gmg_level_faces(gmg_handle* h, int32_t level, void* L_out) {
 gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma, void* r,
                         double* rnorm, double* snorm) {
   if (!h || !x || !sigma) return fail(GMG_EINVAL, "NULL argument");
-  const bool need = rnorm || snorm;
   const Level& lv = h->lev[0];
-  const dim3 gr = cell_grid(lv.g);
+  const dim3 gr = red_grid(lv.g);
   double* pa = rnorm ? h->partials : nullptr;
   if (h->p.dtype == GMG_F64 && h->p.cycle_dtype == GMG_F32) {
-    hipLaunchKernelGGL((k_residual<double, double>), gr, kBlock, 0, h->s, lv.g,
-                       (const double*)x, (const double*)x, nullptr, 0, (const double*)sigma,
-                       (const double*)h->L0x, (double*)r, pa, nullptr);
+    Roles<double> X{{(double*)x, (double*)x, (double*)x}, nullptr};
+    hipLaunchKernelGGL((k_residual<double, double>), gr, kBlock, 0, h->s, lv.g, X, 0,
+                       (const double*)sigma, (const double*)h->L0x, (double*)r, pa, kResChunk,
+                       nullptr);
     if (snorm)
       hipLaunchKernelGGL((k_masked_sumsq<double>), gr, kBlock, 0, h->s, lv.g,
-                         (const double*)sigma, lv.active, h->partials + h->maxpart);
+                         (const double*)sigma, lv.active, h->partials + h->maxpart, kResChunk);
   } else {
     DISPATCH_CYCLE(h, {
-      hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, (const T*)x,
-                         (const T*)x, nullptr, 0, (const T*)sigma, (const TL*)lv.L, (T*)r, pa,
-                         nullptr);
+      Roles<T> X{{(T*)x, (T*)x, (T*)x}, nullptr};
+      hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, X, 0, (const T*)sigma,
+                         (const TL*)lv.L, (T*)r, pa, kResChunk, nullptr);
       if (snorm)
         hipLaunchKernelGGL((k_masked_sumsq<T>), gr, kBlock, 0, h->s, lv.g, (const T*)sigma,
-                           lv.active, h->partials + h->maxpart);
+                           lv.active, h->partials + h->maxpart, kResChunk);
     });
   }
   HIP_TRY(hipGetLastError());
-  if (!need) return GMG_OK;
+  if (!rnorm && !snorm) return GMG_OK;
   // reduce both partial sets into the state's scratch, then read them back
   if (rnorm)
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(256), 0, h->s, h->partials, nblocks(gr),
@@ -807,9 +1084,20 @@ gmg_status gmg_smooth(gmg_handle* h, int32_t level, void* x, const void* sigma,
   if (!h || !x || !sigma) return fail(GMG_EINVAL, "NULL argument");
   if (level < 0 || level >= h->nlev) return fail(GMG_EINVAL, "level out of range");
   if (sweeps < 0) return fail(GMG_EINVAL, "sweeps < 0");
+  if (level == 0 && h->p.dtype != h->p.cycle_dtype)
+    return fail(GMG_EINVAL, "level-0 smoothing needs dtype == cycle_dtype");
+  const Level& lv = h->lev[level];
   DISPATCH_CYCLE(h, {
-    int fc = 0;
-    enq_sweeps<T, TL>(h, level, (T*)x, (T*)x, nullptr, fc, (const T*)sigma, sweeps, nullptr);
+    // ping-pong between the caller's x and a work buffer of that level
+    T* work = (level == 0) ? (T*)h->w[0] : (T*)lv.x[1];
+    Roles<T> X{{(T*)x, work, (T*)x}, nullptr};
+    int r = 0;
+    for (int s = 0; s < sweeps; ++s) {
+      enq_sweep<T, TL>(h, level, X, r, 1 - r, (const T*)sigma, nullptr, nullptr);
+      r = 1 - r;
+    }
+    if (r == 1)
+      HIP_TRY(hipMemcpyAsync(x, work, lv.g.n * sizeof(T), hipMemcpyDeviceToDevice, h->s));
   });
   HIP_TRY(hipGetLastError());
   return GMG_OK;
@@ -819,12 +1107,9 @@ gmg_status gmg_restrict_residual(gmg_handle* h, int32_t level, const void* x,
                                  const void* sigma, void* sigma_c, void* x_c) {
   if (!h || !x || !sigma || !sigma_c) return fail(GMG_EINVAL, "NULL argument");
   if (level < 0 || level + 1 >= h->nlev) return fail(GMG_EINVAL, "level has no coarser level");
-  const Level& lv = h->lev[level];
-  const Level& lc = h->lev[level + 1];
   DISPATCH_CYCLE(h, {
-    hipLaunchKernelGGL((k_restrict_residual<T, TL>), cell_grid(lc.g), kBlock, 0, h->s, lv.g,
-                       (const T*)x, (const T*)x, nullptr, (const T*)sigma, (const TL*)lv.L, lc.g,
-                       lv.c[0], lv.c[1], lv.c[2], (T*)sigma_c, (T*)x_c, nullptr);
+    Roles<T> X{{(T*)x, (T*)x, (T*)x}, nullptr};
+    enq_restrict<T, TL>(h, level, X, 0, (const T*)sigma, (T*)sigma_c, (T*)x_c, nullptr);
   });
   HIP_TRY(hipGetLastError());
   return GMG_OK;
@@ -836,9 +1121,9 @@ gmg_status gmg_prolong_correct(gmg_handle* h, int32_t level, const void* x_c, vo
   const Level& lv = h->lev[level];
   const Level& lc = h->lev[level + 1];
   DISPATCH_CYCLE(h, {
-    hipLaunchKernelGGL((k_prolong<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, (T*)x, (T*)x,
-                       nullptr, lv.active, (const T*)x_c, lc.g, lv.c[0], lv.c[1], lv.c[2],
-                       nullptr);
+    Roles<T> X{{(T*)x, (T*)x, (T*)x}, nullptr};
+    hipLaunchKernelGGL((k_prolong<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, X, 0, 0,
+                       lv.active, (const T*)x_c, lc.g, lv.c[0], lv.c[1], lv.c[2], nullptr);
   });
   HIP_TRY(hipGetLastError());
   return GMG_OK;
@@ -862,7 +1147,12 @@ gmg_status gmg_set_omega(gmg_handle* h, double omega) {
 gmg_status gmg_vcycle(gmg_handle* h, void* x, const void* sigma, double* rnorm_after) {
   if (!h || !x || !sigma) return fail(GMG_EINVAL, "NULL argument");
   if (h->p.dtype != h->p.cycle_dtype) return fail(GMG_EINVAL, "gmg_vcycle needs dtype == cycle_dtype");
-  DISPATCH_CYCLE(h, { enq_vcycle<T, TL>(h, (T*)x, (T*)x, nullptr, 0, (const T*)sigma, nullptr); });
+  DISPATCH_CYCLE(h, {
+    const int f = enq_vcycle<T, TL>(h, (T*)x, nullptr, (const T*)sigma, nullptr);
+    if (f != 0)
+      HIP_TRY(hipMemcpyAsync(x, h->w[f - 1], h->lev[0].g.n * sizeof(T), hipMemcpyDeviceToDevice,
+                             h->s));
+  });
   HIP_TRY(hipGetLastError());
   if (rnorm_after) return gmg_residual(h, x, sigma, nullptr, rnorm_after, nullptr);
   return GMG_OK;
@@ -874,18 +1164,17 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
   if (h->p.dtype != h->p.cycle_dtype) return fail(GMG_EINVAL, "gmg_solve needs dtype == cycle_dtype");
   if (!(rtol >= 0) || max_cycles < 0) return fail(GMG_EINVAL, "bad rtol / max_cycles");
   const Level& lv = h->lev[0];
-  const dim3 gr = cell_grid(lv.g);
-  const long long np = nblocks(gr);
+  const long long np = nblocks(red_grid(lv.g));
   int rounds = 0;
   DISPATCH_CYCLE(h, {
     T* xa = (T*)x;
-    T* xb = (T*)h->xwork;
-    hipLaunchKernelGGL((k_masked_sumsq<T>), gr, kBlock, 0, h->s, lv.g, (const T*)sigma, lv.active,
-                       h->partials);
-    enq_resnorm<T, TL>(h, xa, xa, nullptr, 0, (const T*)sigma, (const TL*)lv.L, nullptr,
-                       h->maxpart, nullptr);
+    const Roles<T> X0{{xa, (T*)h->w[0], (T*)h->w[1]}, nullptr};
+    hipLaunchKernelGGL((k_masked_sumsq<T>), red_grid(lv.g), kBlock, 0, h->s, lv.g,
+                       (const T*)sigma, lv.active, h->partials, kResChunk);
+    enq_resnorm<T, TL>(h, X0, 0, (const T*)sigma, (const TL*)lv.L, nullptr, h->maxpart, nullptr);
     hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, h->s, h->partials, np,
-                       h->partials + h->maxpart, np, h->st, rtol, (int)max_cycles, h->p.omega0);
+                       h->partials + h->maxpart, np, h->st, rtol, (int)max_cycles, h->p.omega0,
+                       nullptr);
     HIP_TRY(hipGetLastError());
     int launched = 0, chunk = 2;
     while (true) {
@@ -908,21 +1197,23 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
         }
       }
       chunk = std::min(chunk, max_cycles - launched);
-      for (int c = 0; c < chunk; ++c) {
-        enq_vcycle<T, TL>(h, xa, xb, &h->st->cur, 1, (const T*)sigma, &h->st->done);
-        enq_resnorm<T, TL>(h, xa, xb, &h->st->cur, 1, (const T*)sigma, (const TL*)lv.L, nullptr,
-                           0, &h->st->done);
-        hipLaunchKernelGGL(k_cycle_finish, dim3(1), dim3(256), 0, h->s, h->partials, np, h->st,
-                           h->rule);
+      if (h->p.graphs) {
+        hipGraphExec_t ex = nullptr;
+        GMG_TRY(captured(h, h->cyc, xa, sigma,
+                         [&]() { return enq_solve_cycle<T, TL>(h, xa, (const T*)sigma); }, &ex));
+        for (int c = 0; c < chunk; ++c) HIP_TRY(hipGraphLaunch(ex, h->s));
+      } else {
+        for (int c = 0; c < chunk; ++c) GMG_TRY((enq_solve_cycle<T, TL>(h, xa, (const T*)sigma)));
       }
-      HIP_TRY(hipGetLastError());
       launched += chunk;
       ++rounds;
     }
     HIP_TRY(hipMemcpyAsync(h->hst, h->st, sizeof(SolveState), hipMemcpyDeviceToHost, h->s));
     HIP_TRY(hipStreamSynchronize(h->s));
-    if (h->hst->cur == 1)
-      HIP_TRY(hipMemcpyAsync(xa, xb, lv.g.n * sizeof(T), hipMemcpyDeviceToDevice, h->s));
+    const int cur = h->hst->cur;
+    if (cur != 0)
+      HIP_TRY(hipMemcpyAsync(xa, h->w[cur - 1], lv.g.n * sizeof(T), hipMemcpyDeviceToDevice,
+                             h->s));
     HIP_TRY(hipStreamSynchronize(h->s));
   });
   const SolveState& s = *h->hst;
@@ -947,6 +1238,68 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
   return GMG_OK;
 }
 
+gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rtol,
+                        int32_t max_outer, int32_t max_inner, double inner_rtol,
+                        gmg_ir_info* info) {
+  if (!h || !x || !sigma) return fail(GMG_EINVAL, "NULL argument");
+  if (h->p.dtype != GMG_F64 || h->p.cycle_dtype != GMG_F32)
+    return fail(GMG_EINVAL, "gmg_solve_ir needs dtype F64 and cycle_dtype F32");
+  if (!(rtol >= 0) || max_outer < 0 || max_inner < 0 || !(inner_rtol >= 0))
+    return fail(GMG_EINVAL, "bad tolerances / step counts");
+  const Level& lv = h->lev[0];
+  const dim3 gr = red_grid(lv.g);
+  const long long np = nblocks(gr);
+  hipLaunchKernelGGL((k_masked_sumsq<double>), gr, kBlock, 0, h->s, lv.g, sigma, lv.active,
+                     h->partials, kResChunk);
+  hipLaunchKernelGGL(k_count_mask, gr, kBlock, 0, h->s, lv.g, lv.active, h->partials + h->maxpart,
+                     kResChunk);
+  hipLaunchKernelGGL(k_ir_init, dim3(1), dim3(256), 0, h->s, h->partials, h->partials + h->maxpart,
+                     np, h->ir, h->st, rtol, (int)max_outer);
+  HIP_TRY(hipGetLastError());
+  auto step = [&]() {
+    return h->p.l_storage == GMG_BF16 ? ir_outer_step<uint16_t>(h, x, sigma, max_inner, inner_rtol)
+                                      : ir_outer_step<float>(h, x, sigma, max_inner, inner_rtol);
+  };
+  hipGraphExec_t ex = nullptr;
+  if (h->p.graphs) {
+    // the step depends on max_inner and inner_rtol too: re-record when they change
+    if (h->irs.exec && (h->ir_inner != max_inner || h->ir_inner_rtol != inner_rtol)) {
+      HIP_TRY(hipGraphExecDestroy(h->irs.exec));
+      h->irs.exec = nullptr;
+    }
+    GMG_TRY(captured(h, h->irs, x, sigma, step, &ex));
+    h->ir_inner = max_inner;
+    h->ir_inner_rtol = inner_rtol;
+  }
+  for (int m = 0; m <= max_outer; ++m) {
+    if (ex)
+      HIP_TRY(hipGraphLaunch(ex, h->s));
+    else
+      GMG_TRY(step());
+    HIP_TRY(hipMemcpyAsync(h->hir, h->ir, offsetof(IRState, hist), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+    if (h->hir->done) break;
+  }
+  HIP_TRY(hipMemcpyAsync(h->hir, h->ir, sizeof(IRState), hipMemcpyDeviceToHost, h->s));
+  HIP_TRY(hipStreamSynchronize(h->s));
+  const IRState& r = *h->hir;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = r.status;
+    info->outer = r.outer;
+    info->inner_total = r.inner_total;
+    info->snorm = r.snorm;
+    info->rnorm = r.rnorm;
+    const int nh = std::min(r.outer + 1, GMG_MAX_HISTORY);
+    for (int m = 0; m < nh; ++m) info->history[m] = r.hist[m];
+    for (int m = 0; m < std::min(r.outer, GMG_MAX_HISTORY); ++m) info->inner_cycles[m] = r.inner[m];
+  }
+  if (r.status != 0) return fail(GMG_ENOCONV, "max_outer reached before rtol");
+  return GMG_OK;
+}
+
 const char* gmg_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+#include "gmg_batch.h"

@@ -1,0 +1,374 @@
+// Fused red-black Gauss-Seidel sweep for gfx950.
+//
+// One launch performs a whole sweep (red half-sweep, then black) out of place:
+// W = sweep(S).  Each workgroup owns a 64 x TY tile of (x, y) columns and a
+// chunk of z-planes and marches up the chunk with rings of three LDS planes:
+//
+//   step k:  issue the global loads of plane k+3 (S, sigma, the three face
+//            arrays; tile plus halo) into registers -> red update on plane
+//            k+1 over the tile and a one-cell ring -> black update on plane k
+//            over the tile from the red values of planes k-1, k, k+1, store
+//            plane k of W -> write the prefetched plane into the LDS slot that
+//            plane k used.
+//
+// Each thread owns an x-pair of cells (one red, one black on every plane), so
+// no lane idles on the wrong colour, and loads/stores are 2-wide.  The red
+// values on the ring are recomputed redundantly by neighbouring tiles: no
+// workgroup reads another one's output, and no grid-wide synchronisation is
+// needed.  HBM traffic per cell is one read of S, sigma and L and one write of
+// W (24 B in FP32), half that of two separate half-sweeps; halo re-reads are
+// served by L2 / Infinity Cache.
+//
+// Optionally the prolongation + correction of the coarse-grid correction is
+// folded into the load: S(a) += x_c[a / c] on active cells before smoothing.
+#pragma once
+
+#include "gmg_device.h"
+
+namespace gmg {
+
+constexpr int SW_TX = 64;  // tile width in x
+constexpr int SW_EX = 68;  // LDS row: tile plus a 2-cell halo on each side
+
+// Wrap / clip a coordinate: the in-domain index, or -1 outside a wall.
+__device__ __forceinline__ int wrap_coord(int c, int n, int periodic) {
+  if (c >= 0 && c < n) return c;
+  if (!periodic) return -1;
+  c %= n;
+  return c < 0 ? c + n : c;
+}
+
+__device__ __forceinline__ int ring3(int p) {
+  const int m = p % 3;
+  return m < 0 ? m + 3 : m;
+}
+
+template <int TY, int VEC>
+struct SweepCfg {
+  static constexpr int NT = 32 * TY;    // threads: one per x-pair of the tile
+  static constexpr int IPR = SW_EX / VEC;  // load items per LDS row
+  static constexpr int RS = TY + 4;     // S rows: j0-2 .. j0+TY+1
+  static constexpr int RF = TY + 2;     // sigma, Lx, Lz, red rows: j0-1 .. j0+TY
+  static constexpr int RY = TY + 3;     // Ly rows: j0-1 .. j0+TY+1 (high face)
+  static constexpr int NS = (RS * IPR + NT - 1) / NT;
+  static constexpr int NF = (RF * IPR + NT - 1) / NT;
+  static constexpr int NY = (RY * IPR + NT - 1) / NT;
+  static constexpr int NRING = 64 + 2 * TY;  // ring work items of the red phase
+};
+
+template <typename T, int TY>
+struct SweepSmem {
+  T s[3][TY + 4][SW_EX];
+  T sg[3][TY + 2][SW_EX];
+  T lx[3][TY + 2][SW_EX];
+  T ly[3][TY + 3][SW_EX];
+  T lz[3][TY + 2][SW_EX];
+  T r[3][TY + 2][SW_EX];  // red values after the red half-sweep (red cells only)
+};
+
+// VEC consecutive face coefficients as T.
+template <typename T, int VEC>
+__device__ __forceinline__ void ldLv(const float* p, long long i, T* v) {
+  if constexpr (VEC == 2) {
+    const float2 a = *reinterpret_cast<const float2*>(p + i);
+    v[0] = (T)a.x;
+    v[1] = (T)a.y;
+  } else {
+    v[0] = (T)p[i];
+  }
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void ldLv(const double* p, long long i, T* v) {
+  if constexpr (VEC == 2) {
+    const double2 a = *reinterpret_cast<const double2*>(p + i);
+    v[0] = (T)a.x;
+    v[1] = (T)a.y;
+  } else {
+    v[0] = (T)p[i];
+  }
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void ldLv(const uint16_t* p, long long i, T* v) {
+  if constexpr (VEC == 2) {
+    const uint32_t a = *reinterpret_cast<const uint32_t*>(p + i);
+    v[0] = (T)__uint_as_float(a << 16);
+    v[1] = (T)__uint_as_float(a & 0xFFFF0000u);
+  } else {
+    v[0] = (T)__uint_as_float(((uint32_t)p[i]) << 16);
+  }
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void ldv(const T* p, long long i, T* v) {
+  if constexpr (VEC == 2) {
+    if constexpr (sizeof(T) == 4) {
+      const float2 a = *reinterpret_cast<const float2*>(p + i);
+      v[0] = a.x;
+      v[1] = a.y;
+    } else {
+      const double2 a = *reinterpret_cast<const double2*>(p + i);
+      v[0] = a.x;
+      v[1] = a.y;
+    }
+  } else {
+    v[0] = p[i];
+  }
+}
+
+// Per-thread load plan of one array: for each item the in-plane element
+// offset (or -1 outside a wall) and the LDS position.
+template <int N>
+struct LoadPlan {
+  int ii[N], jj[N];  // in-domain column / row of the item's first element, -1 outside
+  int row[N], col[N];
+  bool use[N];
+};
+
+template <int TY, int VEC, int N>
+__device__ __forceinline__ void make_plan(LoadPlan<N>& pl, const Geom& g, int i0, int jbase,
+                                          int rows) {
+  using C = SweepCfg<TY, VEC>;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    const int q = tid + u * C::NT;
+    pl.use[u] = q < rows * C::IPR;
+    const int row = q / C::IPR, it = q - row * C::IPR;
+    pl.row[u] = row;
+    pl.col[u] = it * VEC;
+    // VEC == 2 is only used with an even nx: a pair is wholly in or out
+    pl.ii[u] = wrap_coord(i0 - 2 + it * VEC, g.nx, g.px);
+    pl.jj[u] = wrap_coord(jbase + row, g.ny, g.py);
+  }
+}
+
+// Registers holding one prefetched plane.
+template <typename T, int TY, int VEC>
+struct PlaneRegs {
+  using C = SweepCfg<TY, VEC>;
+  T s[C::NS][VEC], sg[C::NF][VEC], lx[C::NF][VEC], ly[C::NY][VEC], lz[C::NF][VEC];
+};
+
+template <typename T, typename TL, int TY, int VEC>
+struct SweepArgs {
+  Geom g;
+  const T* S;
+  const T* sigma;
+  const TL* L;
+  const T* xc;
+  const uint8_t* active;
+  Geom gc;
+  int cx, cy, cz;
+};
+
+template <typename T, typename TL, int TY, int VEC>
+__device__ __forceinline__ void fetch_plane(PlaneRegs<T, TY, VEC>& rg,
+                                            const SweepArgs<T, TL, TY, VEC>& a, int k,
+                                            const LoadPlan<SweepCfg<TY, VEC>::NS>& ps,
+                                            const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
+                                            const LoadPlan<SweepCfg<TY, VEC>::NY>& py) {
+  using C = SweepCfg<TY, VEC>;
+  const Geom& g = a.g;
+  const int kk = wrap_coord(k, g.nz, g.pz);
+  const long long po = (long long)kk * g.sz;
+#pragma unroll
+  for (int u = 0; u < C::NS; ++u) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) rg.s[u][e] = T(0);
+    if (ps.use[u] && ps.ii[u] >= 0 && ps.jj[u] >= 0 && kk >= 0) {
+      const int ii = ps.ii[u], jj = ps.jj[u];
+      const long long idx = po + (long long)jj * g.sy + ii;
+      ldv<T, VEC>(a.S, idx, rg.s[u]);
+      if (a.xc != nullptr) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (a.active[idx + e])
+            rg.s[u][e] += a.xc[(long long)(kk / a.cz) * a.gc.sz + (long long)(jj / a.cy) * a.gc.sy +
+                               (ii + e) / a.cx];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < C::NF; ++u) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) rg.sg[u][e] = rg.lx[u][e] = rg.lz[u][e] = T(0);
+    if (pf.use[u] && pf.ii[u] >= 0 && pf.jj[u] >= 0 && kk >= 0) {
+      const long long idx = po + (long long)pf.jj[u] * g.sy + pf.ii[u];
+      ldv<T, VEC>(a.sigma, idx, rg.sg[u]);
+      ldLv<T, VEC>(a.L, idx, rg.lx[u]);
+      ldLv<T, VEC>(a.L + 2 * g.n, idx, rg.lz[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < C::NY; ++u) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) rg.ly[u][e] = T(0);
+    if (py.use[u] && py.ii[u] >= 0 && py.jj[u] >= 0 && kk >= 0)
+      ldLv<T, VEC>(a.L + g.n, po + (long long)py.jj[u] * g.sy + py.ii[u], rg.ly[u]);
+  }
+}
+
+template <typename T, int TY, int VEC>
+__device__ __forceinline__ void store_plane(SweepSmem<T, TY>& sm, int slot,
+                                            const PlaneRegs<T, TY, VEC>& rg,
+                                            const LoadPlan<SweepCfg<TY, VEC>::NS>& ps,
+                                            const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
+                                            const LoadPlan<SweepCfg<TY, VEC>::NY>& py) {
+  using C = SweepCfg<TY, VEC>;
+#pragma unroll
+  for (int u = 0; u < C::NS; ++u)
+    if (ps.use[u])
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) sm.s[slot][ps.row[u]][ps.col[u] + e] = rg.s[u][e];
+#pragma unroll
+  for (int u = 0; u < C::NF; ++u)
+    if (pf.use[u])
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        sm.sg[slot][pf.row[u]][pf.col[u] + e] = rg.sg[u][e];
+        sm.lx[slot][pf.row[u]][pf.col[u] + e] = rg.lx[u][e];
+        sm.lz[slot][pf.row[u]][pf.col[u] + e] = rg.lz[u][e];
+      }
+#pragma unroll
+  for (int u = 0; u < C::NY; ++u)
+    if (py.use[u])
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) sm.ly[slot][py.row[u]][py.col[u] + e] = rg.ly[u][e];
+}
+
+// Relaxed Gauss-Seidel update of a red cell from S (rows of the S ring are
+// offset by one from the face rows: fr = sr - 1).
+template <typename T, int TY>
+__device__ __forceinline__ T red_update(const SweepSmem<T, TY>& sm, int dm, int d, int dp, int sr,
+                                        int ex, T omega) {
+  const int fr = sr - 1;
+  const T xc = sm.s[d][sr][ex];
+  const T lxm = sm.lx[d][fr][ex], lxp = sm.lx[d][fr][ex + 1];
+  const T lym = sm.ly[d][fr][ex], lyp = sm.ly[d][fr + 1][ex];
+  const T lzm = sm.lz[d][fr][ex], lzp = sm.lz[dp][fr][ex];
+  T ax = T(0);
+  ax += lxp * (sm.s[d][sr][ex + 1] - xc);
+  ax += lxm * (sm.s[d][sr][ex - 1] - xc);
+  ax += lyp * (sm.s[d][sr + 1][ex] - xc);
+  ax += lym * (sm.s[d][sr - 1][ex] - xc);
+  ax += lzp * (sm.s[dp][sr][ex] - xc);
+  ax += lzm * (sm.s[dm][sr][ex] - xc);
+  const T s = ((lxm + lxp) + (lym + lyp)) + (lzm + lzp);
+  if (s == T(0)) return xc;
+  return xc + omega * (sm.sg[d][fr][ex] - ax) / (-s);
+}
+
+// Black update from the red values (rows of the red ring = face rows).
+template <typename T, int TY>
+__device__ __forceinline__ T black_update(const SweepSmem<T, TY>& sm, int dm, int d, int dp,
+                                          int fr, int ex, T omega) {
+  const T xc = sm.s[d][fr + 1][ex];
+  const T lxm = sm.lx[d][fr][ex], lxp = sm.lx[d][fr][ex + 1];
+  const T lym = sm.ly[d][fr][ex], lyp = sm.ly[d][fr + 1][ex];
+  const T lzm = sm.lz[d][fr][ex], lzp = sm.lz[dp][fr][ex];
+  T ax = T(0);
+  ax += lxp * (sm.r[d][fr][ex + 1] - xc);
+  ax += lxm * (sm.r[d][fr][ex - 1] - xc);
+  ax += lyp * (sm.r[d][fr + 1][ex] - xc);
+  ax += lym * (sm.r[d][fr - 1][ex] - xc);
+  ax += lzp * (sm.r[dp][fr][ex] - xc);
+  ax += lzm * (sm.r[dm][fr][ex] - xc);
+  const T s = ((lxm + lxp) + (lym + lyp)) + (lzm + lzp);
+  if (s == T(0)) return xc;
+  return xc + omega * (sm.sg[d][fr][ex] - ax) / (-s);
+}
+
+// Red phase for plane p: interior pairs (one red cell each) and the ring.
+template <typename T, int TY>
+__device__ __forceinline__ void red_phase(SweepSmem<T, TY>& sm, int i0, int j0, int p, T omega) {
+  const int tid = threadIdx.x;
+  const int d = ring3(p), dm = ring3(p - 1), dp = ring3(p + 1);
+  {
+    const int px = tid & 31, ty = tid >> 5;
+    const int j = j0 + ty;
+    const int ex = 2 + 2 * px + ((i0 + j + p) & 1);
+    sm.r[d][ty + 1][ex] = red_update<T, TY>(sm, dm, d, dp, ty + 2, ex, omega);
+  }
+  if (tid < SweepCfg<TY, 1>::NRING) {
+    int fr, ex;
+    bool red = true;
+    if (tid < 64) {  // ring rows below (j0-1) and above (j0+TY)
+      const int px = tid & 31;
+      fr = (tid < 32) ? 0 : TY + 1;
+      const int j = j0 - 1 + fr;
+      ex = 2 + 2 * px + ((i0 + j + p) & 1);
+    } else {  // ring columns left (i0-1) and right (i0+64)
+      const int q = tid - 64;
+      const int right = q >= TY;
+      const int ty = right ? q - TY : q;
+      fr = ty + 1;
+      ex = right ? SW_TX + 2 : 1;
+      const int i = i0 - 2 + ex, j = j0 + ty;
+      red = ((i + j + p) & 1) == 0;
+    }
+    if (red) sm.r[d][fr][ex] = red_update<T, TY>(sm, dm, d, dp, fr + 1, ex, omega);
+  }
+}
+
+// Sweep of the tile with origin (i0, j0) over the z-planes [k0, k1).
+template <typename T, typename TL, int TY, int VEC>
+__device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
+                                              const SweepArgs<T, TL, TY, VEC>& a,
+                                              T* __restrict__ W, int i0, int j0, int k0, int k1,
+                                              T omega) {
+  using C = SweepCfg<TY, VEC>;
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+
+  LoadPlan<C::NS> ps;
+  LoadPlan<C::NF> pf;
+  LoadPlan<C::NY> py;
+  make_plan<TY, VEC, C::NS>(ps, g, i0, j0 - 2, C::RS);
+  make_plan<TY, VEC, C::NF>(pf, g, i0, j0 - 1, C::RF);
+  make_plan<TY, VEC, C::NY>(py, g, i0, j0 - 1, C::RY);
+
+  PlaneRegs<T, TY, VEC> rg;
+  for (int p = k0 - 2; p <= k0; ++p) {
+    fetch_plane<T, TL, TY, VEC>(rg, a, p, ps, pf, py);
+    store_plane<T, TY, VEC>(sm, ring3(p), rg, ps, pf, py);
+  }
+  __syncthreads();
+
+  const int px = tid & 31, ty = tid >> 5;
+  const int j = j0 + ty;
+  const int ib = i0 + 2 * px;
+  for (int k = k0 - 2; k < k1; ++k) {
+    const bool pre = (k + 3 <= k1 + 1);
+    if (pre) fetch_plane<T, TL, TY, VEC>(rg, a, k + 3, ps, pf, py);  // in flight meanwhile
+    red_phase<T, TY>(sm, i0, j0, k + 1, omega);
+    __syncthreads();
+    if (k >= k0) {
+      const int d = ring3(k), dm = ring3(k - 1), dp = ring3(k + 1);
+      const int ob = (i0 + j + k + 1) & 1;  // black offset within the pair
+      const int exb = 2 + 2 * px + ob, exr = 2 + 2 * px + (ob ^ 1);
+      const T vb = black_update<T, TY>(sm, dm, d, dp, ty + 1, exb, omega);
+      const T vr = sm.r[d][ty + 1][exr];
+      T w[2];
+      w[ob] = vb;
+      w[ob ^ 1] = vr;
+      if (j < g.ny) {
+        const long long idx = (long long)k * g.sz + (long long)j * g.sy + ib;
+        if constexpr (VEC == 2) {
+          if (ib + 1 < g.nx) {
+            if constexpr (sizeof(T) == 4)
+              *reinterpret_cast<float2*>(W + idx) = make_float2(w[0], w[1]);
+            else
+              *reinterpret_cast<double2*>(W + idx) = make_double2(w[0], w[1]);
+          }
+        } else {
+          if (ib < g.nx) W[idx] = w[0];
+          if (ib + 1 < g.nx) W[idx + 1] = w[1];
+        }
+      }
+    }
+    __syncthreads();
+    if (pre) store_plane<T, TY, VEC>(sm, ring3(k + 3), rg, ps, pf, py);
+    __syncthreads();
+  }
+}
+
+}  // namespace gmg

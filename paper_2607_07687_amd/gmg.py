@@ -30,6 +30,7 @@ class gmg_params(ctypes.Structure):
                 ("min_coarse", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("nu_coarse", ctypes.c_int32), ("rollback", ctypes.c_int32),
+                ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
                 ("theta_inc", ctypes.c_double)]
@@ -43,6 +44,14 @@ class gmg_solve_info(ctypes.Structure):
                 ("history", ctypes.c_double * GMG_MAX_HISTORY),
                 ("omegas", ctypes.c_double * GMG_MAX_HISTORY),
                 ("accepted", ctypes.c_int32 * GMG_MAX_HISTORY)]
+
+
+class gmg_ir_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("inner_total", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("snorm", ctypes.c_double), ("rnorm", ctypes.c_double),
+                ("history", ctypes.c_double * GMG_MAX_HISTORY),
+                ("inner_cycles", ctypes.c_int32 * GMG_MAX_HISTORY)]
 
 
 class GMGError(RuntimeError):
@@ -81,6 +90,17 @@ _SIGS = [
     ("gmg_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_double, ctypes.c_int32,
                                  ctypes.POINTER(gmg_solve_info)]),
+    ("gmg_solve_ir", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.POINTER(gmg_ir_info)]),
+    ("gmg_batch_setup", ctypes.c_int, [ctypes.POINTER(gmg_params),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    ("gmg_batch_solve_ir", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_double,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                          ctypes.POINTER(gmg_ir_info)]),
+    ("gmg_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("gmg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -271,6 +291,92 @@ def gmg_solve(h, x, sigma, rtol, max_cycles, raise_noconv=False):
     if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
         _check(st)
     return info_dict(info)
+
+
+def gmg_solve_ir(h, x, sigma, rtol=1e-10, max_outer=50, max_inner=8, inner_rtol=1e-4,
+                 raise_noconv=False):
+    """FP64 iterative refinement around FP32 V-cycles, in place on the FP64
+    tensor x.  Returns the info dict."""
+    info = gmg_ir_info()
+    st = load().gmg_solve_ir(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), float(rtol),
+                             int(max_outer), int(max_inner), float(inner_rtol),
+                             ctypes.byref(info))
+    if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
+        _check(st)
+    n = min(info.outer + 1, GMG_MAX_HISTORY)
+    return dict(status=STATUS_NAMES[info.status], outer=info.outer,
+                inner_total=info.inner_total, snorm=info.snorm, rnorm=info.rnorm,
+                history=list(info.history[:n]),
+                inner_cycles=list(info.inner_cycles[:min(info.outer, GMG_MAX_HISTORY)]))
+
+
+def _ir_dict(info):
+    n = min(info.outer + 1, GMG_MAX_HISTORY)
+    return dict(status=STATUS_NAMES[info.status], outer=info.outer,
+                inner_total=info.inner_total, snorm=info.snorm, rnorm=info.rnorm,
+                history=list(info.history[:n]),
+                inner_cycles=list(info.inner_cycles[:min(info.outer, GMG_MAX_HISTORY)]))
+
+
+class Batch:
+    """Owns a gmg_batch*."""
+
+    def __init__(self, ptr, n, stream):
+        self._ptr = ptr
+        self.n = n
+        self.stream = stream
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise ValueError("batch is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr is not None:
+            load().gmg_batch_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gmg_batch_setup(params_list, L_list, stream=None):
+    n = len(params_list)
+    if len(L_list) != n or n == 0:
+        raise ValueError("need one L per parameter set")
+    for p, L in zip(params_list, L_list):
+        if _dtype_code(L) != p.dtype:
+            raise TypeError("L dtype does not match params.dtype")
+    parr = (gmg_params * n)(*params_list)
+    larr = (ctypes.c_void_p * n)(*[L.data_ptr() for L in L_list])
+    for L in L_list:
+        _ptr(L, "L")
+    s = _stream(stream, L_list[0].device)
+    out = ctypes.c_void_p()
+    _check(load().gmg_batch_setup(parr, larr, n, s, ctypes.byref(out)))
+    return Batch(out, n, s)
+
+
+def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inner_rtol=1e-4,
+                       raise_noconv=False):
+    """Refinement of every problem in one graph launch; x tensors updated in
+    place.  Returns the list of per-problem info dicts."""
+    if len(xs) != b.n or len(sigmas) != b.n:
+        raise ValueError("need one x and one sigma per problem")
+    for t in list(xs) + list(sigmas):
+        _ptr(t, "x/sigma")
+    xarr = (ctypes.c_void_p * b.n)(*[t.data_ptr() for t in xs])
+    sarr = (ctypes.c_void_p * b.n)(*[t.data_ptr() for t in sigmas])
+    infos = (gmg_ir_info * b.n)()
+    st = load().gmg_batch_solve_ir(b.ptr, xarr, sarr, float(rtol), int(max_outer),
+                                   int(max_inner), float(inner_rtol), infos)
+    if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
+        _check(st)
+    return [_ir_dict(infos[p]) for p in range(b.n)]
 
 
 def gmg_last_error():

@@ -323,3 +323,31 @@ def test_abi_errors():
     with pytest.raises(G.GMGError):
         G.gmg_restrict_residual(h, 0, L[0], L[0], L[0])  # single level: no coarser
     h.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_graph_replays_match_direct_launches(prec):
+    # the captured V-cycle is replayed many times per solve and reused across
+    # solves; every replay must give exactly what direct launches give
+    L, s, per = P.sphere_box((64, 32, 32), (30.0, 16.0, 16.0), 6.0, "uniform", 4)
+    hg, Ld, sd, levels, L64, s64 = build(L, s, per, prec, graphs=1)
+    he = G.gmg_setup(G.gmg_default_params((64, 32, 32), per, hg.params.dtype, graphs=0), Ld)
+    outs = []
+    for h in (hg, he, hg):
+        x = torch.zeros_like(sd)
+        res = G.gmg_solve(h, x, sd, 1e-8 if prec == "f64" else 1e-6, 60)
+        torch.cuda.synchronize()
+        outs.append((x.clone(), res))
+    for x, res in outs[1:]:
+        assert torch.equal(x, outs[0][0])
+        assert res["history"] == outs[0][1]["history"]
+        assert res["cycles"] == outs[0][1]["cycles"]
+    # a different right-hand side buffer forces a new capture
+    s2 = sd * 0.5
+    x = torch.zeros_like(sd)
+    r2 = G.gmg_solve(hg, x, s2, 1e-6, 60)
+    x2 = torch.zeros_like(sd)
+    r3 = G.gmg_solve(he, x2, s2, 1e-6, 60)
+    assert torch.equal(x, x2) and r2["history"] == r3["history"]
+    hg.close()
+    he.close()
