@@ -2,12 +2,11 @@
 
     python -m paper_2607_07687_amd.build
 
-Compiles every .hip source under csrc/ into one shared library next to this
-file.  Always recompiles.
+Compiles libgmg.so (the GMG solver) and libunet.so (the U-Net warm start)
+next to this file.  Always recompiles.
 """
 from __future__ import annotations
 
-import glob
 import os
 import subprocess
 import sys
@@ -25,25 +24,33 @@ FLAGS = [
 ]
 
 
-def sources():
-    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+LIBS = {
+    "libgmg.so": ["csrc/gmg_lib.hip"],
+    "libunet.so": ["csrc/unet_lib.hip"],
+}
 
 
-def build(verbose=False):
-    out = os.path.join(HERE, "libgmg.so")
+def build_one(name, srcs, verbose=False):
+    out = os.path.join(HERE, name)
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, f"-I{os.path.join(ROOT, 'include')}", *sources(), "-o", tmp]
+    cmd = [HIPCC, *FLAGS, f"-I{os.path.join(ROOT, 'include')}",
+           *[os.path.join(HERE, s) for s in srcs], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
             if "packed-fp32-ops" not in ln]
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
+        raise RuntimeError(f"hipcc failed for {name}:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(tmp, out)
     return out
+
+
+def build(verbose=False):
+    """Compile every library; returns their paths."""
+    return [build_one(name, srcs, verbose) for name, srcs in LIBS.items()]
 
 
 if __name__ == "__main__":

@@ -233,3 +233,40 @@ def random_problem(n, periodic, seed, contrast=1.0, holes=0.0):
     L = zero_wall_faces(L, periodic)
     u = rng.uniform(-1.0, 1.0, shape)
     return L, rhs_from_velocity(L, u, periodic), periodic
+
+
+def tgv_modes_velocity(n, rng, modes=3, kmax=4):
+    """Sum of `modes` Taylor-Green modes with random amplitude a ~ U[-1, 1],
+    wavenumber k in {1..kmax}, phase in [0, 2 pi)^3 and a random assignment of
+    the mode's (u, v, w = 0) components to the three axes; the period is the
+    box length along each axis."""
+    u = np.zeros((3, n[2], n[1], n[0]), dtype=np.float64)
+    for _ in range(modes):
+        a = rng.uniform(-1.0, 1.0)
+        k = int(rng.integers(1, kmax + 1))
+        ph = rng.uniform(0.0, 2 * math.pi, 3)
+        perm = rng.permutation(3)  # mode component c acts along axis perm[c]
+        for c in range(2):
+            d = int(perm[c])
+            pos = face_centres(n, d)
+            ang = [k * 2 * math.pi * pos[int(perm[e])] / n[int(perm[e])] + ph[e] for e in range(3)]
+            if c == 0:
+                f = (np.sin(ang[0]) * np.cos(ang[1])) * np.cos(ang[2])
+            else:
+                f = -(np.cos(ang[0]) * np.sin(ang[1])) * np.cos(ang[2])
+            u[d] += a * np.broadcast_to(f, u[d].shape)
+    return u
+
+
+def tgv_modes_sphere(n, seed, dmin=8.0, dmax=24.0):
+    """Warm-start training/evaluation problem: walls, a sphere of diameter
+    U[dmin, dmax] at a random centre (sphere, band and one cell inside), and
+    sigma from a sum of random Taylor-Green modes.  Returns (L, sigma,
+    periodic)."""
+    rng = np.random.default_rng(seed)
+    radius = 0.5 * float(rng.uniform(dmin, dmax))
+    centre = tuple(float(rng.uniform(radius + 3.0, n[d] - radius - 3.0)) for d in range(3))
+    periodic = (False, False, False)
+    L = sphere_faces(n, periodic, centre, radius)
+    u = tgv_modes_velocity(n, rng)
+    return L, rhs_from_velocity(L, u, periodic), periodic

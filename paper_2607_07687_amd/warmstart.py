@@ -1,0 +1,216 @@
+"""Learned warm start for the GMG solve: data from the solver itself,
+training with the project's kernels, and the timed comparison with plain GMG.
+
+* Data: warm-start problems (walls, a random sphere, sigma from random
+  Taylor-Green modes) generated on the host; each is solved on the GPU by
+  the FP64 iterative refinement of libgmg.so to 1e-10; the target is p / s
+  with its mean over the active cells removed, s = RMS of sigma there.
+* Training: the U-Net of unet_net.py (BF16 activations and weights, FP32
+  master weights and accumulation), masked MSE over the active cells, Adam
+  with a cosine learning-rate decay.
+* Use: x0 = s * U(sigma / s, L); then the adaptive GMG solve from x0.  The
+  final residual judges the prediction: if the warm-started solve misses the
+  tolerance in its cycle budget, plain GMG from zero runs instead.
+
+Run on a GPU machine:  python -m paper_2607_07687_amd.warmstart --help
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+from . import gmg as G
+from . import problems as P
+from . import unet as UN
+from . import unet_net as NET
+
+
+def _gen(args):
+    n, seed = args
+    L, s, per = P.tgv_modes_sphere(n, seed)
+    return L.astype(np.float64), s.astype(np.float64), per
+
+
+def generate(n, seeds, workers=8):
+    """Host-side generation of the warm-start problems (process pool)."""
+    if workers <= 1:
+        return [_gen((n, s)) for s in seeds]
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_gen, [(n, s) for s in seeds], chunksize=4))
+
+
+class Sample:
+    """Device tensors of one problem: FP32 sigma and faces (network input and
+    FP32 solve), target p / s, active mask, scale s."""
+
+    def __init__(self, L, s, per, p=None):
+        import torch
+        t = P.touched_cells(L, per)
+        self.n = (L.shape[3], L.shape[2], L.shape[1])
+        self.per = per
+        self.scale = float(np.sqrt(np.mean(s[t] ** 2))) if t.any() else 1.0
+        self.sigma = torch.from_numpy(s.astype(np.float32)).cuda()
+        self.L = torch.from_numpy(L.astype(np.float32)).cuda()
+        self.mask = torch.from_numpy(t.astype(np.uint8)).cuda()
+        self.target = None
+        if p is not None:
+            q = p - p[t].mean()
+            self.target = torch.from_numpy((q / self.scale).astype(np.float32)).cuda()
+
+
+def solve_fp64(L, s, per):
+    """FP64 iterative-refinement solve to 1e-10 on the GPU."""
+    import torch
+    n = (L.shape[3], L.shape[2], L.shape[1])
+    prm = G.gmg_default_params(n, per, G.GMG_F64, cycle_dtype=G.GMG_F32)
+    h = G.gmg_setup(prm, torch.from_numpy(L).cuda())
+    sd = torch.from_numpy(s).cuda()
+    x = torch.zeros_like(sd)
+    info = G.gmg_solve_ir(h, x, sd, rtol=1e-10, max_outer=20)
+    h.close()
+    if info["status"] != "GMG_OK":
+        raise RuntimeError(f"training target solve failed: {info}")
+    return x.cpu().numpy()
+
+
+def make_samples(n, seeds, workers=8, with_target=True):
+    out = []
+    for L, s, per in generate(n, seeds, workers):
+        p = solve_fp64(L, s, per) if with_target else None
+        out.append(Sample(L, s, per, p))
+    return out
+
+
+def pack(samples, x_buf):
+    """BF16 network input of a batch of samples into x_buf [B][d][h][w][8]."""
+    import torch
+    B = len(samples)
+    nx, ny, nz = samples[0].n
+    sig = torch.stack([sm.sigma for sm in samples]) if B > 1 else samples[0].sigma[None]
+    L = torch.stack([sm.L for sm in samples]) if B > 1 else samples[0].L[None]
+    UN.unet_pack_input(UN.shape(B, nz, ny, nx), sig.contiguous(), L.contiguous(),
+                       [sm.scale for sm in samples], x_buf)
+
+
+def train(net, samples, steps, batch=2, lr=1e-3, seed=0, log_every=50):
+    import torch
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = samples[0].n
+    x = torch.zeros((batch, nz, ny, nx, NET.IN_CH), dtype=torch.int16, device="cuda")
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        idx = rng.choice(len(samples), batch, replace=False)
+        bs = [samples[i] for i in idx]
+        pack(bs, x)
+        tgt = torch.stack([b.target for b in bs]).contiguous()
+        msk = torch.stack([b.mask for b in bs]).contiguous()
+        net.forward(x, batch, nz, ny, nx)
+        want = (it % log_every == 0) or it == steps - 1
+        loss = net.backward(x, tgt, msk, want_loss=want)
+        net.adam(lr * 0.5 * (1.0 + math.cos(math.pi * it / steps)))
+        if want:
+            losses.append((it, loss))
+            print(f"step {it} loss {loss:.5f} ({time.perf_counter() - t0:.1f}s)", flush=True)
+    return losses
+
+
+def predict(net, sm, x_buf, out):
+    """x0 = s * U(sigma / s, L) into out (FP32 [d][h][w])."""
+    nx, ny, nz = sm.n
+    pack([sm], x_buf)
+    y = net.forward(x_buf, 1, nz, ny, nx)
+    UN.unet_scale(y, sm.scale, out)
+    return out
+
+
+def compare(net, samples, rtol=1e-6, reps=5, max_cycles=100):
+    """Wall time of plain GMG (x0 = 0) against U-Net inference + GMG from its
+    prediction, FP32 solves on the same GPU; medians over reps."""
+    import torch
+    res = []
+    for sm in samples:
+        nx, ny, nz = sm.n
+        prm = G.gmg_default_params(sm.n, sm.per, G.GMG_F32)
+        h = G.gmg_setup(prm, sm.L)
+        x = torch.zeros_like(sm.sigma)
+        xb = torch.zeros((1, nz, ny, nx, NET.IN_CH), dtype=torch.int16, device="cuda")
+        G.gmg_solve(h, x, sm.sigma, rtol, max_cycles)  # warm-up (graph capture)
+        predict(net, sm, xb, x)
+        G.gmg_solve(h, x, sm.sigma, rtol, max_cycles)
+        tp, tw, cp, cw, fb = [], [], 0, 0, 0
+        for _ in range(reps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ip = G.gmg_solve(h, x, sm.sigma, rtol, max_cycles)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+            cp = ip["cycles"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            predict(net, sm, xb, x)
+            iw = G.gmg_solve(h, x, sm.sigma, rtol, max_cycles)
+            if iw["status"] != "GMG_OK":  # fallback: plain GMG from zero
+                fb += 1
+                x.zero_()
+                iw = G.gmg_solve(h, x, sm.sigma, rtol, max_cycles)
+            torch.cuda.synchronize()
+            tw.append(time.perf_counter() - t0)
+            cw = iw["cycles"]
+        rel0 = iw["rnorm0"] / iw["snorm"] if iw["snorm"] > 0 else 0.0
+        res.append(dict(plain_ms=1e3 * float(np.median(tp)), warm_ms=1e3 * float(np.median(tw)),
+                        plain_cycles=cp, warm_cycles=cw, warm_rel_r0=rel0, fallbacks=fb))
+        h.close()
+    return res
+
+
+def main():
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=128, help="training grid")
+    ap.add_argument("--eval-n", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=2000)
+    ap.add_argument("--eval-samples", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--batch", type=int, default=2)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--out", default="gpurun_out/warmstart")
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    G.load()
+    UN.load()
+    assert torch.cuda.is_available()
+    t0 = time.perf_counter()
+    train_set = make_samples((args.n,) * 3, range(10000, 10000 + args.samples), args.workers)
+    t_data = time.perf_counter() - t0
+    print(f"{len(train_set)} training pairs in {t_data:.1f}s", flush=True)
+    net = NET.UNet()
+    net.init_he(0)
+    t0 = time.perf_counter()
+    losses = train(net, train_set, args.steps, args.batch, args.lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    np.save(os.path.join(args.out, "unet_params.npy"), net.get_flat())
+    del train_set
+    evals = make_samples((args.eval_n,) * 3, range(20000, 20000 + args.eval_samples),
+                         args.workers, with_target=False)
+    res = compare(net, evals)
+    summary = dict(train_n=args.n, samples=args.samples, steps=args.steps, batch=args.batch,
+                   data_s=t_data, train_s=t_train, losses=losses, eval_n=args.eval_n, eval=res,
+                   plain_ms_median=float(np.median([r["plain_ms"] for r in res])),
+                   warm_ms_median=float(np.median([r["warm_ms"] for r in res])))
+    with open(os.path.join(args.out, "summary.json"), "w") as f:
+        json.dump(summary, f, indent=1)
+    print(json.dumps({k: v for k, v in summary.items() if k not in ("losses", "eval")}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

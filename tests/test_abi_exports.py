@@ -5,14 +5,15 @@ import os
 import re
 
 from paper_2607_07687_amd import gmg as G
+from paper_2607_07687_amd import unet as UN
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared(header):
+def declared(header, prefix="gmg"):
     text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gmg_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_symbols_exported():
@@ -23,6 +24,24 @@ def test_header_symbols_exported():
         assert hasattr(lib, name), name
     # the binding wraps exactly the declared entry points
     assert sorted(G.exported_symbols()) == names
+
+
+def test_unet_header_symbols_exported():
+    names = declared("unet.h", "unet")
+    assert "unet_conv_fwd" in names and "unet_conv_wgrad" in names
+    lib = UN.load()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(UN.exported_symbols()) == names
+
+
+def test_unet_argument_errors_without_gpu():
+    lib = UN.load()
+    s = UN.shape(1, 4, 4, 4)
+    bad = UN.unet_act(None, 8, 0, 8)
+    assert lib.unet_conv_fwd(s, bad, None, None, 27, bad, None, 0, None) == UN.UNET_EINVAL
+    assert lib.unet_last_error().decode() != ""
+    assert lib.unet_pool_fwd(UN.shape(1, 3, 4, 4), bad, bad, None) == UN.UNET_EINVAL
 
 
 def test_default_params_without_gpu():

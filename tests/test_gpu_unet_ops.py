@@ -1,0 +1,227 @@
+"""GPU parity of the U-Net operations (libunet.so) against the FP64 U-Net
+oracle fed the same BF16-rounded inputs: the MFMA lane layout, convolution
+forward (FP32 and BF16 outputs), data and weight gradients, pooling,
+upsampling, ReLU backward, the 1x1x1 head, the masked MSE and Adam.
+
+Tolerances: FP32-output results differ from the oracle only by FP32
+accumulation order (1e-5 relative); BF16-output results also by the final
+rounding to BF16 (2^-8 relative per element)."""
+import numpy as np
+import pytest
+
+from oracle import unet_oracle as UO
+from paper_2607_07687_amd import unet as UN
+from tests.gpu_util import require_gpu, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return u
+
+
+def bf16_to_f64(u):
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def to_dev_bf16(a):
+    """FP64 array -> (device int16 tensor of BF16 bits, FP64 of the rounded values)."""
+    u = bf16_round(a)
+    return torch.from_numpy(u.view(np.int16).copy()).cuda(), bf16_to_f64(u)
+
+
+def from_dev_bf16(t):
+    return bf16_to_f64(t.cpu().numpy().view(np.uint16))
+
+
+def cl(x):
+    """[n][C][D][H][W] -> channels-last [n][D][H][W][C]."""
+    return np.ascontiguousarray(np.moveaxis(x, 1, -1))
+
+
+def cf(x):
+    return np.ascontiguousarray(np.moveaxis(x, -1, 1))
+
+
+def w_gpu(w):
+    """oracle [co][ci][3][3][3] -> [co][27][ci]"""
+    co, ci = w.shape[:2]
+    return np.ascontiguousarray(w.reshape(co, ci, -1).transpose(0, 2, 1))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_mfma_lane_layout():
+    require_gpu()
+    rng = np.random.default_rng(0)
+    A = rng.integers(-4, 5, (16, 32)).astype(np.float64)
+    B = rng.integers(-4, 5, (32, 16)).astype(np.float64)
+    Ad, _ = to_dev_bf16(A)
+    Bd, _ = to_dev_bf16(B)
+    out = torch.zeros(256, dtype=torch.float32, device="cuda")
+    UN.unet_mfma_selfcheck(Ad, Bd, out)
+    assert np.array_equal(out.cpu().numpy().reshape(16, 16), (A @ B).astype(np.float32))
+
+
+CONV_CASES = [(2, 8, 16, (5, 6, 7)), (1, 16, 32, (4, 4, 9)), (2, 32, 64, (3, 5, 4)),
+              (1, 64, 128, (4, 3, 3)), (1, 128, 16, (2, 3, 4))]
+
+
+@pytest.mark.parametrize("n,cin,cout,dhw", CONV_CASES)
+def test_conv_forward(n, cin, cout, dhw):
+    require_gpu()
+    say(f"conv fwd {n} {cin}->{cout} {dhw}")
+    rng = np.random.default_rng(cin + cout)
+    x = rng.standard_normal((n, cin) + dhw)
+    w = rng.standard_normal((cout, cin, 3, 3, 3)) / np.sqrt(27 * cin)
+    b = rng.standard_normal(cout) * 0.1
+    xd, x64 = to_dev_bf16(cl(x))
+    wd, w64 = to_dev_bf16(w_gpu(w))
+    bd = torch.from_numpy(b.astype(np.float32)).cuda()
+    w64o = w64.reshape(cout, 27, cin).transpose(0, 2, 1).reshape(cout, cin, 3, 3, 3)
+    want = np.stack([UO.conv3d(cf(x64)[i], w64o, b.astype(np.float32)) for i in range(n)])
+    s = UN.shape(n, *dhw)
+    yf = torch.zeros((n,) + dhw + (cout,), dtype=torch.float32, device="cuda")
+    UN.unet_conv_fwd(s, UN.act(xd, cin, 0, cin), wd, bd, 27, UN.act(None, cout, 0, cout), yf, 0)
+    assert rel(cf(yf.cpu().numpy().astype(np.float64)), want) <= 1e-5
+    # BF16 output with ReLU, written into channel slice [cout, 2 cout) of a wider row
+    yb = torch.zeros((n,) + dhw + (2 * cout,), dtype=torch.int16, device="cuda")
+    UN.unet_conv_fwd(s, UN.act(xd, cin, 0, cin), wd, bd, 27, UN.act(yb, 2 * cout, cout, cout),
+                     None, 1)
+    got = cf(from_dev_bf16(yb)[..., cout:])
+    wr = np.maximum(want, 0.0)
+    assert np.all(np.abs(got - wr) <= 2.0 ** -8 * np.abs(wr) + 1e-5 * np.abs(wr).max())
+    assert np.all(from_dev_bf16(yb)[..., :cout] == 0.0)
+
+
+@pytest.mark.parametrize("n,cin,cout,dhw", [c for c in CONV_CASES if c[1] >= 16])
+def test_conv_dgrad_and_wgrad(n, cin, cout, dhw):
+    require_gpu()
+    say(f"conv bwd {n} {cin}->{cout} {dhw}")
+    rng = np.random.default_rng(7 + cin)
+    x = rng.standard_normal((n, cin) + dhw)
+    w = rng.standard_normal((cout, cin, 3, 3, 3)) / np.sqrt(27 * cin)
+    dy = rng.standard_normal((n, cout) + dhw)
+    xd, x64 = to_dev_bf16(cl(x))
+    wd, w64 = to_dev_bf16(w_gpu(w))
+    dyd, dy64 = to_dev_bf16(cl(dy))
+    w64o = w64.reshape(cout, 27, cin).transpose(0, 2, 1).reshape(cout, cin, 3, 3, 3)
+    dxs, dws, dbs = [], 0.0, 0.0
+    for i in range(n):
+        dx_i, dw_i, db_i = UO.conv3d_backward(cf(x64)[i], w64o, cf(dy64)[i])
+        dxs.append(dx_i)
+        dws = dws + dw_i
+        dbs = dbs + db_i
+    s = UN.shape(n, *dhw)
+    dx = torch.zeros((n,) + dhw + (cin,), dtype=torch.int16, device="cuda")
+    wflip = torch.empty(cout * 27 * cin, dtype=torch.int16, device="cuda")
+    UN.unet_conv_dgrad(s, UN.act(dyd, cout, 0, cout), wd, 27, UN.act(dx, cin, 0, cin), wflip)
+    want = np.stack(dxs)
+    got = cf(from_dev_bf16(dx))
+    assert np.all(np.abs(got - want) <= 2.0 ** -8 * np.abs(want) + 1e-5 * np.abs(want).max())
+    ws = torch.empty(UN.unet_wgrad_workspace(s, cin, cout, 27) // 4 + 1, dtype=torch.float32,
+                     device="cuda")
+    dw = torch.zeros(cout * 27 * cin, dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    UN.unet_conv_wgrad(s, UN.act(xd, cin, 0, cin), UN.act(dyd, cout, 0, cout), 27, dw, db, ws)
+    got_w = dw.cpu().numpy().astype(np.float64).reshape(cout, 27, cin).transpose(0, 2, 1)
+    assert rel(got_w.reshape(cout, cin, 3, 3, 3), dws) <= 1e-5
+    assert rel(db.cpu().numpy().astype(np.float64), dbs) <= 1e-5
+
+
+def test_pool_upsample_relu_bwd():
+    require_gpu()
+    rng = np.random.default_rng(3)
+    n, c, dhw = 2, 16, (4, 6, 8)
+    x = rng.standard_normal((n, c) + dhw)
+    xd, x64 = to_dev_bf16(cl(x))
+    fine = UN.shape(n, *dhw)
+    coarse = UN.shape(n, 2, 3, 4)
+    yp = torch.zeros((n, 2, 3, 4, c), dtype=torch.int16, device="cuda")
+    UN.unet_pool_fwd(fine, UN.act(xd, c, 0, c), UN.act(yp, c, 0, c))
+    want = np.stack([UO.avgpool2(cf(x64)[i]) for i in range(n)])
+    got = cf(from_dev_bf16(yp))
+    assert np.all(np.abs(got - want) <= 2.0 ** -8 * np.abs(want) + 1e-7)
+    # upsample of the pooled values, and the adjoint sums
+    yu = torch.zeros((n,) + dhw + (c,), dtype=torch.int16, device="cuda")
+    UN.unet_up_fwd(coarse, UN.act(yp, c, 0, c), UN.act(yu, c, 0, c))
+    assert np.array_equal(cf(from_dev_bf16(yu)), np.stack([UO.upsample2(g) for g in got]))
+    dyd, dy64 = to_dev_bf16(cl(rng.standard_normal((n, c) + dhw)))
+    du = torch.zeros((n, 2, 3, 4, c), dtype=torch.int16, device="cuda")
+    UN.unet_up_bwd(coarse, UN.act(dyd, c, 0, c), UN.act(du, c, 0, c))
+    want = np.stack([UO.upsample2_backward(cf(dy64)[i]) for i in range(n)])
+    assert np.all(np.abs(cf(from_dev_bf16(du)) - want) <= 2.0 ** -8 * np.abs(want) + 1e-6)
+    dp = torch.zeros((n,) + dhw + (c,), dtype=torch.int16, device="cuda")
+    UN.unet_pool_bwd(fine, UN.act(du, c, 0, c), UN.act(dp, c, 0, c), 0)
+    want = np.stack([UO.avgpool2_backward(cf(from_dev_bf16(du))[i]) for i in range(n)])
+    assert np.array_equal(cf(from_dev_bf16(dp)), want)
+    # ReLU backward keeps dy where y > 0
+    ro = torch.zeros_like(xd)
+    UN.unet_relu_bwd(fine, UN.act(xd, c, 0, c), UN.act(dyd, c, 0, c), UN.act(ro, c, 0, c))
+    want = np.stack([UO.relu_backward(cf(x64)[i], cf(dy64)[i]) for i in range(n)])
+    assert np.array_equal(cf(from_dev_bf16(ro)), want)
+
+
+def test_head_mse_adam():
+    require_gpu()
+    rng = np.random.default_rng(4)
+    n, c, dhw = 2, 16, (3, 4, 5)
+    x = rng.standard_normal((n, c) + dhw)
+    xd, x64 = to_dev_bf16(cl(x))
+    w = rng.standard_normal(c).astype(np.float32)
+    b = np.float32(0.3)
+    s = UN.shape(n, *dhw)
+    wd = torch.from_numpy(w).cuda()
+    bd = torch.tensor([b], dtype=torch.float32, device="cuda")
+    y = torch.zeros((n,) + dhw, dtype=torch.float32, device="cuda")
+    UN.unet_head_fwd(s, UN.act(xd, c, 0, c), wd, bd, y)
+    w5 = w.astype(np.float64).reshape(1, c, 1, 1, 1)
+    want = np.stack([UO.conv3d(cf(x64)[i], w5, np.array([float(b)]))[0] for i in range(n)])
+    assert rel(y.cpu().numpy().astype(np.float64), want) <= 1e-6
+    tgt = rng.standard_normal((n,) + dhw).astype(np.float32)
+    mask = (rng.uniform(size=(n,) + dhw) > 0.3).astype(np.uint8)
+    dpred = torch.zeros_like(y)
+    stats = torch.zeros(2 + 512, dtype=torch.float64, device="cuda")
+    loss = UN.unet_mse(s, y, torch.from_numpy(tgt).cuda(), torch.from_numpy(mask).cuda(), dpred,
+                       stats)
+    yl = y.cpu().numpy().astype(np.float64)
+    lo, dlo = UO.mse(yl, tgt.astype(np.float64), mask.astype(bool))
+    assert abs(loss - lo) <= 1e-9 * lo
+    assert rel(dpred.cpu().numpy().astype(np.float64), dlo) <= 1e-6
+    ws = torch.empty(UN.unet_head_workspace(s, c) // 4 + 1, dtype=torch.float32, device="cuda")
+    dw = torch.zeros(c, dtype=torch.float32, device="cuda")
+    db = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dx = torch.zeros_like(xd)
+    UN.unet_head_bwd(s, UN.act(xd, c, 0, c), wd, dpred, UN.act(dx, c, 0, c), dw, db, ws)
+    dp64 = dpred.cpu().numpy().astype(np.float64)
+    gx, gw, gb = 0.0, 0.0, 0.0
+    dxs = []
+    for i in range(n):
+        dx_i, dw_i, db_i = UO.conv3d_backward(cf(x64)[i], w5, dp64[i][None])
+        dxs.append(dx_i)
+        gw, gb = gw + dw_i, gb + db_i
+    assert rel(dw.cpu().numpy().astype(np.float64), gw.reshape(c)) <= 1e-5
+    assert abs(float(db.item()) - float(gb[0])) <= 1e-5 * abs(float(gb[0])) + 1e-7
+    want = np.stack(dxs)
+    assert np.all(np.abs(cf(from_dev_bf16(dx)) - want) <= 2.0 ** -8 * np.abs(want) + 1e-7)
+    # Adam: two steps against the oracle's
+    p0 = rng.standard_normal(1000)
+    g1, g2 = rng.standard_normal(1000), rng.standard_normal(1000)
+    master = torch.from_numpy(p0.astype(np.float32)).cuda()
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    out16 = torch.zeros(1000, dtype=torch.int16, device="cuda")
+    po = {"p": p0.astype(np.float32).astype(np.float64)}
+    st = {}
+    for t, g in ((1, g1), (2, g2)):
+        gd = torch.from_numpy(g.astype(np.float32)).cuda()
+        UN.unet_adam(master, m, v, gd, out16, 1e-3, t)
+        UO.adam_step(po, {"p": g.astype(np.float32).astype(np.float64)}, st, 1e-3)
+    assert rel(master.cpu().numpy().astype(np.float64) - p0, po["p"] - p0) <= 1e-4
+    assert np.array_equal(out16.cpu().numpy().view(np.uint16), bf16_round(master.cpu().numpy()))
