@@ -256,8 +256,39 @@ gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* cons
                               double rtol, int32_t max_outer, int32_t max_inner,
                               double inner_rtol, gmg_ir_info* infos);
 
+/* Tune the z-chunk of the batched fused sweep once per distinct level shape
+ * of the batch (timed with HIP events on the problems' own inner buffers),
+ * apply it to every problem and rebuild the descriptor tables; the recorded
+ * graph is dropped.  Results do not depend on the choice.  Synchronises. */
+gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps);
+
 /* Free the batch and all its problems.  NULL is accepted. */
 gmg_status gmg_batch_destroy(gmg_batch* b);
+
+/* Tile choice of the fused red-black sweep per level, as measured by
+ * gmg_autotune: rows per tile (ty, 4 or 8) and z-planes per workgroup
+ * (kchunk), with the mean sweep time of the chosen and the default shape. */
+typedef struct gmg_tune_report {
+  int32_t nlevels;
+  int32_t ty[32], kchunk[32];
+  int32_t ty_default[32], kchunk_default[32];
+  double us[32], us_default[32];
+} gmg_tune_report;
+
+/* Time `reps` fused sweeps of every level for each candidate tile shape
+ * (ty in {8, 4}, kchunk in {2, 4, ..., 64} up to nz; FP64 cycles: ty 4) with
+ * HIP events on the handle's stream, and keep the fastest per level.  x and
+ * sigma are level-0 device arrays (dtype == cycle_dtype) used as the sweep's
+ * input (x is overwritten with smoothed values; coarse levels use internal
+ * buffers).  Recorded graphs are dropped.  report (host) may be NULL.  The
+ * results do not depend on the tile choice.  Synchronises. */
+gmg_status gmg_autotune(gmg_handle* h, void* x, const void* sigma, int32_t reps,
+                        gmg_tune_report* report);
+
+/* Apply a known tile choice to one level (e.g. from a cache of earlier
+ * gmg_autotune runs).  GMG_EINVAL for ty not in {4, 8} (4 with FP64 cycles)
+ * or kchunk outside [1, nz]. */
+gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk);
 
 /* Thread-local description of the last error ("" if none). */
 const char* gmg_last_error(void);

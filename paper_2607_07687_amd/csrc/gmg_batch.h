@@ -582,6 +582,76 @@ gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32
   return GMG_OK;
 }
 
+gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps) {
+  if (!b || reps < 1) return fail(GMG_EINVAL, "bad batch autotune arguments");
+  // one timing per distinct level shape; the batched sweep uses ty = 8
+  std::vector<std::array<int, 4>> done_keys;  // nx, ny, nz, kchunk
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int kcs[6] = {2, 4, 8, 16, 32, 64};
+  for (int p = 0; p < b->n; ++p) {
+    gmg_handle* h = b->h[p];
+    for (int l = 0; l < h->nlev; ++l) {
+      Level& lv = h->lev[l];
+      int found = -1;
+      for (size_t q = 0; q < done_keys.size(); ++q)
+        if (done_keys[q][0] == lv.g.nx && done_keys[q][1] == lv.g.ny && done_keys[q][2] == lv.g.nz)
+          found = (int)q;
+      if (found >= 0) {
+        lv.kchunk = done_keys[found][3];
+        continue;
+      }
+      float* a = (l == 0) ? h->e32 : (float*)lv.x[0];
+      float* c = (l == 0) ? (float*)h->w[0] : (float*)lv.x[1];
+      const float* sg = (l == 0) ? h->b32 : (const float*)lv.sigma;
+      const Roles<float> X{{a, c, a}, nullptr};
+      float best = 1e30f;
+      int bkc = lv.kchunk;
+      for (int q = 0; q < 6; ++q) {
+        const int kc = kcs[q];
+        if (kc > lv.g.nz) continue;
+        auto run = [&]() {
+          if (b->storage == GMG_BF16)
+            launch_sweep<float, uint16_t, 8>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
+          else
+            launch_sweep<float, float, 8>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
+        };
+        run();
+        HIP_TRY(hipEventRecord(e0, h->s));
+        for (int r = 0; r < reps; ++r) run();
+        HIP_TRY(hipEventRecord(e1, h->s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          bkc = kc;
+        }
+      }
+      lv.kchunk = bkc;
+      done_keys.push_back({lv.g.nx, lv.g.ny, lv.g.nz, bkc});
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipGetLastError());
+  // rebuild the descriptor tables with the new z-chunks; drop the graph
+  (void)hipFree(b->lv);
+  (void)hipFree(b->ov);
+  (void)hipFree(b->sweep_tiles);
+  (void)hipFree(b->rest_tiles);
+  (void)hipFree(b->res_tiles);
+  b->lv = b->ov = nullptr;
+  b->sweep_tiles = b->rest_tiles = b->res_tiles = nullptr;
+  if (b->graph.exec) {
+    HIP_TRY(hipGraphExecDestroy(b->graph.exec));
+    b->graph.exec = nullptr;
+  }
+  b->key.clear();
+  return (b->storage == GMG_BF16) ? batch_build_tables<uint16_t>(b) : batch_build_tables<float>(b);
+}
+
 gmg_status gmg_batch_destroy(gmg_batch* b) {
   if (b) (void)hipStreamSynchronize(b->s);
   free_batch(b);

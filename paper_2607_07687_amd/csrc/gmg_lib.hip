@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstddef>
@@ -500,6 +501,7 @@ struct Level {
   void* x[2];      // cycle dtype ping-pong iterates (levels >= 1)
   void* sigma;
   int kchunk;      // z-planes per workgroup of the fused sweep
+  int ty;          // tile height of the fused sweep (rows of 64 cells)
 };
 
 size_t dsize(int dt) { return dt == GMG_F64 ? 8 : (dt == GMG_BF16 ? 2 : 4); }
@@ -598,23 +600,34 @@ static Roles<T> level_roles(gmg_handle* h, int l, T* x0, const int* sel) {
 // accepted iterate (role 0) is never written; coarse levels alternate 0 <-> 1
 static int next_role(int l, int r) { return l == 0 ? (r == 1 ? 2 : 1) : 1 - r; }
 
-template <typename T, typename TL>
-static void enq_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
-                      const T* xc, const int* done) {
-  constexpr int TY = SweepTY<T>::v;
+template <typename T, typename TL, int TY>
+static void launch_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
+                         const T* xc, const int* done, int kchunk) {
   const Level& lv = h->lev[l];
   const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
   const dim3 grid((lv.g.nx + SW_TX - 1) / SW_TX, (lv.g.ny + TY - 1) / TY,
-                  (lv.g.nz + lv.kchunk - 1) / lv.kchunk);
+                  (lv.g.nz + kchunk - 1) / kchunk);
   const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
   if (lv.g.nx % 2 == 0)
     hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 2>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,
-                       sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, lv.kchunk,
+                       sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, kchunk,
                        &h->st->omega, done);
   else
     hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 1>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,
-                       sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, lv.kchunk,
+                       sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, kchunk,
                        &h->st->omega, done);
+}
+
+// One fused sweep of level l with the level's tile choice (TY 4 or 8; FP64
+// sweeps always use TY 4 for their LDS budget).
+template <typename T, typename TL>
+static void enq_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
+                      const T* xc, const int* done) {
+  const Level& lv = h->lev[l];
+  if (sizeof(T) == 8 || lv.ty == 4)
+    launch_sweep<T, TL, 4>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk);
+  else
+    launch_sweep<T, TL, 8>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk);
 }
 
 template <typename T, typename TL>
@@ -836,8 +849,8 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
       HIP_TRY(hipMalloc(&lv.x[1], lv.g.n * cs));
       HIP_TRY(hipMalloc(&lv.sigma, lv.g.n * cs));
     }
-    lv.kchunk = sweep_kchunk(lv.g, p->cycle_dtype == GMG_F64 ? SweepTY<double>::v
-                                                              : SweepTY<float>::v);
+    lv.ty = p->cycle_dtype == GMG_F64 ? SweepTY<double>::v : SweepTY<float>::v;
+    lv.kchunk = sweep_kchunk(lv.g, lv.ty);
   }
   maxpart = nblocks(red_grid(h->lev[0].g));
   h->maxpart = maxpart;
@@ -961,6 +974,72 @@ static gmg_status ir_outer_step(gmg_handle* h, double* x, const double* sigma, i
                      (const SolveState*)h->st);
   HIP_TRY(hipGetLastError());
   return GMG_OK;
+}
+
+// Forget recorded graphs (they embed the tile choice of every launch).
+static gmg_status drop_graphs(gmg_handle* h) {
+  if (h->cyc.exec) HIP_TRY(hipGraphExecDestroy(h->cyc.exec));
+  if (h->irs.exec) HIP_TRY(hipGraphExecDestroy(h->irs.exec));
+  h->cyc.exec = h->irs.exec = nullptr;
+  return GMG_OK;
+}
+
+template <typename T, typename TL>
+static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int reps,
+                                gmg_tune_report* rep) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int tys[2] = {8, 4};
+  const int kcs[6] = {2, 4, 8, 16, 32, 64};
+  for (int l = 0; l < h->nlev; ++l) {
+    Level& lv = h->lev[l];
+    T* a = (l == 0) ? (T*)x : (T*)lv.x[0];
+    T* b = (l == 0) ? (T*)h->w[0] : (T*)lv.x[1];
+    const T* sg = (l == 0) ? (const T*)sigma : (const T*)lv.sigma;
+    const Roles<T> X{{a, b, a}, nullptr};
+    rep->ty_default[l] = lv.ty;
+    rep->kchunk_default[l] = lv.kchunk;
+    float best = 1e30f, deft = 0.f;
+    int bty = lv.ty, bkc = lv.kchunk;
+    for (int it = -1; it < 2 * 6; ++it) {
+      // it == -1 times the default choice first
+      const int ty = (it < 0) ? lv.ty : tys[it / 6];
+      const int kc = (it < 0) ? lv.kchunk : kcs[it % 6];
+      if (sizeof(T) == 8 && ty != 4) continue;
+      if (kc > lv.g.nz) continue;
+      auto run = [&]() {
+        if (ty == 4)
+          launch_sweep<T, TL, 4>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
+        else
+          launch_sweep<T, TL, 8>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
+      };
+      run();  // warm-up
+      HIP_TRY(hipEventRecord(e0, h->s));
+      for (int r = 0; r < reps; ++r) run();
+      HIP_TRY(hipEventRecord(e1, h->s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (it < 0) deft = ms;
+      if (ms < best) {
+        best = ms;
+        bty = ty;
+        bkc = kc;
+      }
+    }
+    lv.ty = bty;
+    lv.kchunk = bkc;
+    rep->ty[l] = bty;
+    rep->kchunk[l] = bkc;
+    rep->us[l] = 1e3 * best;
+    rep->us_default[l] = 1e3 * deft;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipGetLastError());
+  return drop_graphs(h);
 }
 
 extern "C" {
@@ -1295,6 +1374,33 @@ gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rt
     for (int m = 0; m < std::min(r.outer, GMG_MAX_HISTORY); ++m) info->inner_cycles[m] = r.inner[m];
   }
   if (r.status != 0) return fail(GMG_ENOCONV, "max_outer reached before rtol");
+  return GMG_OK;
+}
+
+gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk) {
+  if (!h) return fail(GMG_EINVAL, "NULL handle");
+  if (level < 0 || level >= h->nlev) return fail(GMG_EINVAL, "level out of range");
+  if ((ty != 4 && ty != 8) || (h->p.cycle_dtype == GMG_F64 && ty != 4))
+    return fail(GMG_EINVAL, "ty must be 4 or 8 (4 for FP64 cycles)");
+  if (kchunk < 1 || kchunk > h->lev[level].g.nz) return fail(GMG_EINVAL, "kchunk out of range");
+  h->lev[level].ty = ty;
+  h->lev[level].kchunk = kchunk;
+  return drop_graphs(h);
+}
+
+gmg_status gmg_autotune(gmg_handle* h, void* x, const void* sigma, int32_t reps,
+                        gmg_tune_report* report) {
+  if (!h || !x || !sigma || reps < 1) return fail(GMG_EINVAL, "bad autotune arguments");
+  if (h->p.dtype != h->p.cycle_dtype)
+    return fail(GMG_EINVAL, "gmg_autotune needs dtype == cycle_dtype (level-0 arrays)");
+  gmg_tune_report local;
+  gmg_tune_report* rep = report ? report : &local;
+  std::memset(rep, 0, sizeof(*rep));
+  rep->nlevels = h->nlev;
+  gmg_status st = GMG_OK;
+  DISPATCH_CYCLE(h, { st = autotune_impl<T, TL>(h, x, sigma, reps, rep); });
+  if (st != GMG_OK) return st;
+  HIP_TRY(hipStreamSynchronize(h->s));
   return GMG_OK;
 }
 

@@ -54,6 +54,13 @@ class gmg_ir_info(ctypes.Structure):
                 ("inner_cycles", ctypes.c_int32 * GMG_MAX_HISTORY)]
 
 
+class gmg_tune_report(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int32), ("ty", ctypes.c_int32 * 32),
+                ("kchunk", ctypes.c_int32 * 32), ("ty_default", ctypes.c_int32 * 32),
+                ("kchunk_default", ctypes.c_int32 * 32), ("us", ctypes.c_double * 32),
+                ("us_default", ctypes.c_double * 32)]
+
+
 class GMGError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -101,6 +108,11 @@ _SIGS = [
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                           ctypes.POINTER(gmg_ir_info)]),
     ("gmg_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("gmg_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("gmg_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.POINTER(gmg_tune_report)]),
+    ("gmg_set_tiles", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32]),
     ("gmg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -377,6 +389,29 @@ def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inne
     if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
         _check(st)
     return [_ir_dict(infos[p]) for p in range(b.n)]
+
+
+def gmg_autotune(h, x, sigma, reps=5):
+    """Time the sweep tile candidates of every level and keep the fastest.
+    Returns per-level dicts (shape, ty, kchunk, us, defaults)."""
+    rep = gmg_tune_report()
+    _check(load().gmg_autotune(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), int(reps),
+                               ctypes.byref(rep)))
+    out = []
+    for l in range(rep.nlevels):
+        n, _ = gmg_level_shape(h, l)
+        out.append(dict(level=l, n=n, ty=rep.ty[l], kchunk=rep.kchunk[l], us=rep.us[l],
+                        ty_default=rep.ty_default[l], kchunk_default=rep.kchunk_default[l],
+                        us_default=rep.us_default[l]))
+    return out
+
+
+def gmg_set_tiles(h, level, ty, kchunk):
+    _check(load().gmg_set_tiles(h.ptr, int(level), int(ty), int(kchunk)))
+
+
+def gmg_batch_autotune(b, reps=5):
+    _check(load().gmg_batch_autotune(b.ptr, int(reps)))
 
 
 def gmg_last_error():

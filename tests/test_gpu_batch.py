@@ -88,3 +88,21 @@ def test_batch_argument_errors():
     prm.nu_coarse = 3
     with pytest.raises(G.GMGError):
         G.gmg_batch_setup([prm], [dev(L, "f64")])
+
+
+def test_batch_autotune_keeps_results_bitwise():
+    require_gpu()
+    specs = P.batch_specs(count=4, seed=5)
+    probs = [P.sphere_box(sp["n"], sp["centre"], sp["radius"], "uniform", sp["seed"])
+             for sp in specs]
+    Ls = [dev(L, "f64") for L, _, _ in probs]
+    ss = [dev(s, "f64") for _, s, _ in probs]
+    b = G.gmg_batch_setup([_params(L, per, "f32") for L, _, per in probs], Ls)
+    xs = [torch.zeros_like(s) for s in ss]
+    i0 = G.gmg_batch_solve_ir(b, xs, ss)
+    G.gmg_batch_autotune(b, reps=2)
+    ys = [torch.zeros_like(s) for s in ss]
+    i1 = G.gmg_batch_solve_ir(b, ys, ss)
+    assert [i["history"] for i in i0] == [i["history"] for i in i1]
+    assert all(torch.equal(a, c) for a, c in zip(xs, ys))
+    b.close()

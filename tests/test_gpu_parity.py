@@ -351,3 +351,31 @@ def test_graph_replays_match_direct_launches(prec):
     assert torch.equal(x, x2) and r2["history"] == r3["history"]
     hg.close()
     he.close()
+
+
+def test_autotune_keeps_results_bitwise(tmp_path):
+    from paper_2607_07687_amd import autotune as AT
+    L, s, per = P.sphere_box((96, 64, 48), (40.0, 32.0, 24.0), 8.0, "uniform", 6)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f32")
+    x0 = torch.zeros_like(sd)
+    r0 = G.gmg_solve(h, x0, sd, 1e-6, 60)
+    scratch = torch.zeros_like(sd)
+    rep = AT.tune(h, scratch, sd, cache=str(tmp_path / "tiles.json"), reps=3)
+    say("tiles " + ", ".join(f"L{r['level']}:{r['ty']}x{r['kchunk']}" for r in rep))
+    assert len(rep) == len(levels)
+    for r in rep:
+        assert r["ty"] in (4, 8) and r["kchunk"] >= 1
+        assert r["us"] <= r["us_default"] * 1.05 + 1.0
+    x1 = torch.zeros_like(sd)
+    r1 = G.gmg_solve(h, x1, sd, 1e-6, 60)
+    assert torch.equal(x0, x1) and r0["history"] == r1["history"]
+    # cached choices are applied on a fresh handle
+    h2 = G.gmg_setup(h.params, Ld)
+    rep2 = AT.tune(h2, scratch, sd, cache=str(tmp_path / "tiles.json"))
+    assert all(r["cached"] for r in rep2)
+    with pytest.raises(G.GMGError):
+        G.gmg_set_tiles(h2, 0, 6, 4)
+    with pytest.raises(G.GMGError):
+        G.gmg_set_tiles(h2, 0, 8, 1000)
+    h.close()
+    h2.close()
