@@ -57,6 +57,94 @@ def cpu_baseline():
                       f"host has {os.cpu_count()} logical CPUs"}
 
 
+def timed(fn, reps=3):
+    import torch
+    ts, out = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(ts)), out
+
+
+def extra_configs():
+    """The other workloads, each on one GPU: the 32^3 periodic FP64 solve to
+    1e-10, anisotropic vs isotropic coarsening on the 512 x 192 x 192 sphere
+    channel, and 64 uneven problems refined to 1e-10 in one graph launch."""
+    import torch
+    from paper_2607_07687_amd import gmg as G
+    from paper_2607_07687_amd import problems as P
+    out = {}
+    # 32^3 triple-periodic TGV, FP64, to 1e-10
+    L, s, per = P.tgv_periodic(32, seed=0)
+    h = G.gmg_setup(G.gmg_default_params((32, 32, 32), per, G.GMG_F64),
+                    torch.from_numpy(L).cuda())
+    sd = torch.from_numpy(s).cuda()
+    x = torch.zeros_like(sd)
+
+    def run():
+        x.zero_()
+        return G.gmg_solve(h, x, sd, 1e-10, 100)
+    run()
+    ms, res = timed(run, 5)
+    out["tgv32_fp64"] = {"time_to_1e-10_ms": ms, "cycles": res["cycles"], "status": res["status"]}
+    h.close()
+    log(f"tgv32: {out['tgv32_fp64']}")
+    # 512 x 192 x 192 sphere channel: anisotropic vs isotropic coarsening.
+    # Its smooth Taylor-Green right-hand side leaves an FP32 residual floor
+    # near 7e-6, so cycles are counted to 1e-5
+    L, s, per = P.sphere_channel(seed=2)
+    Ld = torch.from_numpy(L.astype(np.float32)).cuda()
+    sd = torch.from_numpy(s.astype(np.float32)).cuda()
+    del L, s
+    ch = {}
+    for name, aniso in (("aniso", 1), ("iso", 0)):
+        h = G.gmg_setup(G.gmg_default_params((512, 192, 192), per, G.GMG_F32,
+                                             anisotropic=aniso), Ld)
+        x = torch.zeros_like(sd)
+
+        def run():
+            x.zero_()
+            return G.gmg_solve(h, x, sd, 1e-5, 300)
+        run()
+        ms, res = timed(run, 3)
+        ch[name] = {"levels": G.gmg_num_levels(h), "rtol": 1e-5, "cycles": res["cycles"],
+                    "status": res["status"], "time_ms": ms,
+                    "final_rel": res["history"][-1] if res["history"] else None}
+        h.close()
+    out["channel512x192x192_fp32"] = ch
+    log(f"channel: {ch}")
+    del Ld, sd
+    # 64 uneven problems, FP64 refinement to 1e-10, one graph launch
+    probs = P.batch_problems(64, seed=3)
+    Ls = [torch.from_numpy(L).cuda() for L, _, _ in probs]
+    ss = [torch.from_numpy(s).cuda() for _, s, _ in probs]
+    prms = [G.gmg_default_params((L.shape[3], L.shape[2], L.shape[1]), per, G.GMG_F64,
+                                 cycle_dtype=G.GMG_F32) for L, _, per in probs]
+    cells = int(sum(L[0].size for L, _, _ in probs))
+    del probs
+    b = G.gmg_batch_setup(prms, Ls)
+    G.gmg_batch_autotune(b, reps=3)
+    xs = [torch.zeros_like(s) for s in ss]
+
+    def run():
+        for t in xs:
+            t.zero_()
+        return G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=30, max_inner=8)
+    run()  # records the graph
+    ms, infos = timed(run, 3)
+    out["batch64_ir_fp64"] = {"problems": 64, "cells": cells, "time_to_1e-10_ms": ms,
+                              "all_ok": all(i["status"] == "GMG_OK" for i in infos),
+                              "max_outer": max(i["outer"] for i in infos),
+                              "worst_final_rel": max(i["history"][-1] for i in infos),
+                              "graph_launches": 1}
+    b.close()
+    log(f"batch: {out['batch64_ir_fp64']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +152,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-runs", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only run a 256 MiB device copy (counter calibration) and 4 level-0 "
+                         "fused sweeps at 256^3, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -71,6 +163,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_2607_07687_amd import autotune as AT
     from paper_2607_07687_amd import gmg as G
     from paper_2607_07687_amd import problems as P
 
@@ -90,8 +183,20 @@ def main():
     setup_ms = (time.perf_counter() - t0) * 1e3
     nlev = G.gmg_num_levels(h)
     x = torch.zeros_like(sd)
+    if args.kernel_probe:
+        a = torch.ones(64 * 2 ** 20, dtype=torch.float32, device=dev)  # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        G.gmg_smooth(h, 0, x, sd, 4)
+        torch.cuda.synchronize()
+        log("kernel probe done: copy of 256 MiB, 4 level-0 sweeps")
+        h.close()
+        return
 
     # warm-up, then K timed cycles of the adaptive solve
+    tiles = AT.tune(h, x, sd, cache=None)  # timed sweep tiles per level (setup, untimed)
+    log("tiles " + ", ".join(f"L{t['level']}:{t['ty']}x{t['kchunk']}" for t in tiles))
+    x.zero_()
     G.gmg_solve(h, x, sd, 0.0, max(1, args.warmup))
     x.zero_()
     torch.cuda.synchronize()
@@ -153,12 +258,16 @@ def main():
         "cycles_to_tol": int(np.median(cyc)),
         "final_rel_residual": rn / sn,
         "setup_ms": setup_ms,
-        "roofline": {"bound": "hbm", "kernel": "k_rb_sweep<float,float,8> (level-0 fused sweep)",
+        "tiles": [{"level": t["level"], "ty": t["ty"], "kchunk": t["kchunk"]} for t in tiles],
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": sweep_ms * 1e3,
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if not args.no_extras:
+        out["other_configs"] = extra_configs()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

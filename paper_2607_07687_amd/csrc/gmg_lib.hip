@@ -530,12 +530,19 @@ long long nblocks(dim3 d) { return (long long)d.x * d.y * d.z; }
 template <typename T> struct SweepTY { static constexpr int v = 8; };
 template <> struct SweepTY<double> { static constexpr int v = 4; };
 
-// z-chunk of the fused sweep: aim for >= 1024 workgroups, at least 4 planes.
-int sweep_kchunk(const Geom& g, int ty) {
+// z-chunk of the fused sweep: split z so that the workgroups fill whole
+// rounds of the resident slots (256 CUs x workgroups per CU that fit the
+// LDS budget of 160 KB), which avoids a partly filled last round; at least
+// 2 planes per chunk.
+constexpr int kCUs = 256;
+int sweep_kchunk(const Geom& g, int ty, int elem_bytes) {
   const long long tiles = (long long)((g.nx + SW_TX - 1) / SW_TX) * ((g.ny + ty - 1) / ty);
-  int kc = g.nz;
-  while (kc > 4 && tiles * ((g.nz + kc - 1) / kc) < 1024) kc = (kc + 1) / 2;
-  return kc;
+  const size_t lds = (size_t)elem_bytes * SW_EX * 3 * ((ty + 4) + 3 * (ty + 2) + (ty + 3) + (ty + 2));
+  const long long per_cu = std::max<long long>(1, (long long)(160 * 1024 / lds));
+  const long long slots = kCUs * per_cu;
+  const long long chunks = std::max<long long>(1, slots / std::max<long long>(1, tiles));
+  int kc = (int)((g.nz + chunks - 1) / chunks);
+  return std::max(std::min(2, g.nz), kc);
 }
 
 }  // namespace
@@ -850,7 +857,7 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
       HIP_TRY(hipMalloc(&lv.sigma, lv.g.n * cs));
     }
     lv.ty = p->cycle_dtype == GMG_F64 ? SweepTY<double>::v : SweepTY<float>::v;
-    lv.kchunk = sweep_kchunk(lv.g, lv.ty);
+    lv.kchunk = sweep_kchunk(lv.g, lv.ty, p->cycle_dtype == GMG_F64 ? 8 : 4);
   }
   maxpart = nblocks(red_grid(h->lev[0].g));
   h->maxpart = maxpart;

@@ -309,6 +309,56 @@ __device__ __forceinline__ void red_phase(SweepSmem<T, TY>& sm, int i0, int j0, 
   }
 }
 
+// One plane step k of the sweep: red update of plane k+1, black update and
+// store of plane k (k >= k0), then the plane held in `cur` (plane k+3, loaded
+// two steps earlier) goes to the LDS slot plane k used, while `nxt` receives
+// plane k+4.  Two register sets alternate, so each load has two steps of
+// compute to arrive.
+template <typename T, typename TL, int TY, int VEC>
+__device__ __forceinline__ void sweep_step(SweepSmem<T, TY>& sm, const SweepArgs<T, TL, TY, VEC>& a,
+                                           T* __restrict__ W, int i0, int j0, int k0, int k1, int k,
+                                           T omega, PlaneRegs<T, TY, VEC>& cur,
+                                           PlaneRegs<T, TY, VEC>& nxt,
+                                           const LoadPlan<SweepCfg<TY, VEC>::NS>& ps,
+                                           const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
+                                           const LoadPlan<SweepCfg<TY, VEC>::NY>& py) {
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+  const int px = tid & 31, ty = tid >> 5;
+  const int j = j0 + ty;
+  const int ib = i0 + 2 * px;
+  if (k + 4 <= k1 + 1) fetch_plane<T, TL, TY, VEC>(nxt, a, k + 4, ps, pf, py);
+  red_phase<T, TY>(sm, i0, j0, k + 1, omega);
+  __syncthreads();
+  if (k >= k0) {
+    const int d = ring3(k), dm = ring3(k - 1), dp = ring3(k + 1);
+    const int ob = (i0 + j + k + 1) & 1;  // black offset within the pair
+    const int exb = 2 + 2 * px + ob, exr = 2 + 2 * px + (ob ^ 1);
+    const T vb = black_update<T, TY>(sm, dm, d, dp, ty + 1, exb, omega);
+    const T vr = sm.r[d][ty + 1][exr];
+    T w[2];
+    w[ob] = vb;
+    w[ob ^ 1] = vr;
+    if (j < g.ny) {
+      const long long idx = (long long)k * g.sz + (long long)j * g.sy + ib;
+      if constexpr (VEC == 2) {
+        if (ib + 1 < g.nx) {
+          if constexpr (sizeof(T) == 4)
+            *reinterpret_cast<float2*>(W + idx) = make_float2(w[0], w[1]);
+          else
+            *reinterpret_cast<double2*>(W + idx) = make_double2(w[0], w[1]);
+        }
+      } else {
+        if (ib < g.nx) W[idx] = w[0];
+        if (ib + 1 < g.nx) W[idx + 1] = w[1];
+      }
+    }
+  }
+  __syncthreads();
+  if (k + 3 <= k1 + 1) store_plane<T, TY, VEC>(sm, ring3(k + 3), cur, ps, pf, py);
+  __syncthreads();
+}
+
 // Sweep of the tile with origin (i0, j0) over the z-planes [k0, k1).
 template <typename T, typename TL, int TY, int VEC>
 __device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
@@ -317,7 +367,6 @@ __device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
                                               T omega) {
   using C = SweepCfg<TY, VEC>;
   const Geom& g = a.g;
-  const int tid = threadIdx.x;
 
   LoadPlan<C::NS> ps;
   LoadPlan<C::NF> pf;
@@ -326,48 +375,32 @@ __device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
   make_plan<TY, VEC, C::NF>(pf, g, i0, j0 - 1, C::RF);
   make_plan<TY, VEC, C::NY>(py, g, i0, j0 - 1, C::RY);
 
-  PlaneRegs<T, TY, VEC> rg;
-  for (int p = k0 - 2; p <= k0; ++p) {
-    fetch_plane<T, TL, TY, VEC>(rg, a, p, ps, pf, py);
-    store_plane<T, TY, VEC>(sm, ring3(p), rg, ps, pf, py);
-  }
+  // Prologue: establish, for k = k0, that LDS holds planes k .. k+2, the red
+  // values of planes k-1 and k are computed, and plane k+3 is in flight.
+  PlaneRegs<T, TY, VEC> ra, rb;
+  fetch_plane<T, TL, TY, VEC>(ra, a, k0 - 2, ps, pf, py);
+  fetch_plane<T, TL, TY, VEC>(rb, a, k0 - 1, ps, pf, py);
+  store_plane<T, TY, VEC>(sm, ring3(k0 - 2), ra, ps, pf, py);
+  store_plane<T, TY, VEC>(sm, ring3(k0 - 1), rb, ps, pf, py);
+  fetch_plane<T, TL, TY, VEC>(ra, a, k0, ps, pf, py);
+  fetch_plane<T, TL, TY, VEC>(rb, a, k0 + 1, ps, pf, py);
+  store_plane<T, TY, VEC>(sm, ring3(k0), ra, ps, pf, py);
   __syncthreads();
-
-  const int px = tid & 31, ty = tid >> 5;
-  const int j = j0 + ty;
-  const int ib = i0 + 2 * px;
-  for (int k = k0 - 2; k < k1; ++k) {
-    const bool pre = (k + 3 <= k1 + 1);
-    if (pre) fetch_plane<T, TL, TY, VEC>(rg, a, k + 3, ps, pf, py);  // in flight meanwhile
-    red_phase<T, TY>(sm, i0, j0, k + 1, omega);
-    __syncthreads();
-    if (k >= k0) {
-      const int d = ring3(k), dm = ring3(k - 1), dp = ring3(k + 1);
-      const int ob = (i0 + j + k + 1) & 1;  // black offset within the pair
-      const int exb = 2 + 2 * px + ob, exr = 2 + 2 * px + (ob ^ 1);
-      const T vb = black_update<T, TY>(sm, dm, d, dp, ty + 1, exb, omega);
-      const T vr = sm.r[d][ty + 1][exr];
-      T w[2];
-      w[ob] = vb;
-      w[ob ^ 1] = vr;
-      if (j < g.ny) {
-        const long long idx = (long long)k * g.sz + (long long)j * g.sy + ib;
-        if constexpr (VEC == 2) {
-          if (ib + 1 < g.nx) {
-            if constexpr (sizeof(T) == 4)
-              *reinterpret_cast<float2*>(W + idx) = make_float2(w[0], w[1]);
-            else
-              *reinterpret_cast<double2*>(W + idx) = make_double2(w[0], w[1]);
-          }
-        } else {
-          if (ib < g.nx) W[idx] = w[0];
-          if (ib + 1 < g.nx) W[idx + 1] = w[1];
-        }
-      }
-    }
-    __syncthreads();
-    if (pre) store_plane<T, TY, VEC>(sm, ring3(k + 3), rg, ps, pf, py);
-    __syncthreads();
+  red_phase<T, TY>(sm, i0, j0, k0 - 1, omega);  // reads planes k0-2 .. k0
+  __syncthreads();
+  store_plane<T, TY, VEC>(sm, ring3(k0 + 1), rb, ps, pf, py);  // slot of plane k0-2
+  fetch_plane<T, TL, TY, VEC>(ra, a, k0 + 2, ps, pf, py);
+  __syncthreads();
+  red_phase<T, TY>(sm, i0, j0, k0, omega);  // reads planes k0-1 .. k0+1
+  __syncthreads();
+  store_plane<T, TY, VEC>(sm, ring3(k0 + 2), ra, ps, pf, py);  // slot of plane k0-1
+  fetch_plane<T, TL, TY, VEC>(ra, a, k0 + 3, ps, pf, py);
+  __syncthreads();
+  int k;
+  for (k = k0; k < k1; k += 2) {
+    sweep_step<T, TL, TY, VEC>(sm, a, W, i0, j0, k0, k1, k, omega, ra, rb, ps, pf, py);
+    if (k + 1 < k1)
+      sweep_step<T, TL, TY, VEC>(sm, a, W, i0, j0, k0, k1, k + 1, omega, rb, ra, ps, pf, py);
   }
 }
 

@@ -122,7 +122,7 @@ class UNet:
         B["stats"] = torch.zeros(2 + 512, dtype=torch.float64, device=self.dev)
         wsz, fl = 0, 0
         for name, ci, co, taps in self.layers:
-            lvl = int(name[-2]) if name != "head" else 0
+            lvl = int("".join(ch for ch in name if ch.isdigit())) if name != "head" else 0
             s = UN.shape(*sh[lvl])
             if name == "head":
                 wsz = max(wsz, UN.unet_head_workspace(s, ci))

@@ -36,11 +36,11 @@ def test_batch_equals_single_solves(storage):
     b = G.gmg_batch_setup(params, Ls)
     xs = [torch.zeros_like(s) for s in ss]
     say(f"batch of {len(probs)} ({storage})")
-    infos = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=6, max_inner=8)
+    infos = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=30, max_inner=8)
     for p, ((L, s, per), prm) in enumerate(zip(probs, params)):
         h = G.gmg_setup(prm, Ls[p])
         x1 = torch.zeros_like(ss[p])
-        r1 = G.gmg_solve_ir(h, x1, ss[p], rtol=1e-10, max_outer=6, max_inner=8)
+        r1 = G.gmg_solve_ir(h, x1, ss[p], rtol=1e-10, max_outer=30, max_inner=8)
         say(f"  p{p} n={prm.n[0]}x{prm.n[1]}x{prm.n[2]} outer {infos[p]['outer']} "
             f"final {infos[p]['history'][-1]:.2e}")
         assert infos[p]["status"] == "GMG_OK"
@@ -51,7 +51,7 @@ def test_batch_equals_single_solves(storage):
     # replay of the kept graph from fresh zero guesses
     for x in xs:
         x.zero_()
-    infos2 = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=6, max_inner=8)
+    infos2 = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=30, max_inner=8)
     assert [i["history"] for i in infos2] == [i["history"] for i in infos]
     b.close()
 
@@ -65,9 +65,9 @@ def test_batch_matches_oracle_subset():
     ss = [dev(s, "f64") for _, s, _ in probs]
     b = G.gmg_batch_setup([_params(L, per, "f32") for L, _, per in probs], Ls)
     xs = [torch.zeros_like(s) for s in ss]
-    infos = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=6, max_inner=8)
+    infos = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=30, max_inner=8)
     for p, (L, s, per) in enumerate(probs):
-        ro = O.solve_ir(L, per, np.zeros_like(s), s, rtol=1e-10, max_outer=6, max_inner=8,
+        ro = O.solve_ir(L, per, np.zeros_like(s), s, rtol=1e-10, max_outer=30, max_inner=8,
                         inner_rtol=1e-4, inner_storage="f32")
         assert ro["status"] == "ok" and infos[p]["status"] == "GMG_OK"
         assert abs(infos[p]["outer"] - ro["outer"]) <= 1
@@ -99,10 +99,10 @@ def test_batch_autotune_keeps_results_bitwise():
     ss = [dev(s, "f64") for _, s, _ in probs]
     b = G.gmg_batch_setup([_params(L, per, "f32") for L, _, per in probs], Ls)
     xs = [torch.zeros_like(s) for s in ss]
-    i0 = G.gmg_batch_solve_ir(b, xs, ss)
+    i0 = G.gmg_batch_solve_ir(b, xs, ss, max_outer=30)
     G.gmg_batch_autotune(b, reps=2)
     ys = [torch.zeros_like(s) for s in ss]
-    i1 = G.gmg_batch_solve_ir(b, ys, ss)
+    i1 = G.gmg_batch_solve_ir(b, ys, ss, max_outer=30)
     assert [i["history"] for i in i0] == [i["history"] for i in i1]
     assert all(torch.equal(a, c) for a, c in zip(xs, ys))
     b.close()
