@@ -62,7 +62,7 @@ template <typename TL, int TY>
 __global__ __launch_bounds__(32 * TY) void k_b_sweep(const BLevel<TL>* __restrict__ lv,
                                                      const BTile* __restrict__ tiles, int rs,
                                                      int rd, int with_corr) {
-  const BTile t = tiles[blockIdx.x];
+  const BTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const BLevel<TL>& d = lv[t.d];
   if (*d.done) return;
   __shared__ SweepSmem<float, TY> sm;

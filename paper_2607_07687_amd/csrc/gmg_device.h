@@ -94,6 +94,18 @@ __device__ __forceinline__ T stencil_Ax(const Geom& g, const T* __restrict__ x,
   return ax;
 }
 
+// XCD-aware tile order.  The 8 XCDs of an MI355X each have their own L2 and
+// receive workgroups round-robin (workgroup b runs on XCD b % 8).  Mapping
+// hardware index b to logical tile t so that each XCD gets a contiguous range
+// of tiles makes x- and y-neighbouring tiles share an L2, which then serves
+// their halo re-reads.  A bijection on [0, nb).
+constexpr int kXCDs = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb / kXCDs, r = nb % kXCDs;
+  const int x = b % kXCDs, slot = b / kXCDs;
+  return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
 // Sum of v over a block of `nthreads` (multiple of 64, <= 1024) threads,
 // fixed order: wavefront shuffle tree, then wave partials in index order.
 // The result is valid in thread 0 only.

@@ -230,8 +230,12 @@ __global__ __launch_bounds__(32 * TY) void k_rb_sweep(Geom g, Roles<T> X, int rs
   if (stopped(done)) return;
   __shared__ SweepSmem<T, TY> sm;
   SweepArgs<T, TL, TY, VEC> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
-  const int k0 = blockIdx.z * kchunk;
-  rb_sweep_tile<T, TL, TY, VEC>(sm, a, X.get(rd), blockIdx.x * SW_TX, blockIdx.y * TY, k0,
+  // 1-D grid of tiles, x fastest, then y, then z-chunks, in XCD-aware order
+  const int ntx = (g.nx + SW_TX - 1) / SW_TX, nty = (g.ny + TY - 1) / TY;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int k0 = tz * kchunk;
+  rb_sweep_tile<T, TL, TY, VEC>(sm, a, X.get(rd), tx * SW_TX, ty * TY, k0,
                                 min(g.nz, k0 + kchunk), (T)(*omega_p));
 }
 
@@ -612,8 +616,8 @@ static void launch_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd
                          const T* xc, const int* done, int kchunk) {
   const Level& lv = h->lev[l];
   const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
-  const dim3 grid((lv.g.nx + SW_TX - 1) / SW_TX, (lv.g.ny + TY - 1) / TY,
-                  (lv.g.nz + kchunk - 1) / kchunk);
+  const dim3 grid(((lv.g.nx + SW_TX - 1) / SW_TX) * ((lv.g.ny + TY - 1) / TY) *
+                  ((lv.g.nz + kchunk - 1) / kchunk));
   const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
   if (lv.g.nx % 2 == 0)
     hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 2>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,

@@ -171,6 +171,49 @@ def compare(net, samples, rtol=1e-6, reps=5, max_cycles=100):
     return res
 
 
+def conv_throughput(n=128, reps=5):
+    """Measured TFLOP/s of the convolution kernels at the U-Net's per-level
+    shapes for one n^3 sample (forward, data and weight gradient)."""
+    import torch
+    out = []
+    chans = [(8, 16, n), (16, 16, n), (32, 16, n), (16, 32, n // 2), (32, 32, n // 2),
+             (32, 64, n // 4), (64, 64, n // 4), (64, 128, n // 8), (128, 128, n // 8),
+             (128, 64, n // 4)]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for cin, cout, m in chans:
+        s = UN.shape(1, m, m, m)
+        x = torch.zeros((m, m, m, cin), dtype=torch.int16, device="cuda")
+        y = torch.zeros((m, m, m, cout), dtype=torch.int16, device="cuda")
+        w = torch.zeros(cout * 27 * cin, dtype=torch.int16, device="cuda")
+        b = torch.zeros(cout, dtype=torch.float32, device="cuda")
+        flops = 2.0 * 27 * cin * cout * m ** 3
+        res = {"cin": cin, "cout": cout, "n": m}
+        ws = torch.empty(UN.unet_wgrad_workspace(s, cin, cout, 27) // 4 + 1, dtype=torch.float32,
+                         device="cuda")
+        dw = torch.zeros(cout * 27 * cin, dtype=torch.float32, device="cuda")
+        wf = torch.empty_like(w)
+        ops = {"fwd": lambda: UN.unet_conv_fwd(s, UN.act(x, cin, 0, cin), w, b, 27,
+                                               UN.act(y, cout, 0, cout), None, 1),
+               "wgrad": lambda: UN.unet_conv_wgrad(s, UN.act(x, cin, 0, cin),
+                                                   UN.act(y, cout, 0, cout), 27, dw, b, ws)}
+        if cin % 16 == 0:
+            ops["dgrad"] = lambda: UN.unet_conv_dgrad(s, UN.act(y, cout, 0, cout), w, 27,
+                                                      UN.act(x, cin, 0, cin), wf)
+        for name, fn in ops.items():
+            fn()
+            ev0.record()
+            for _ in range(reps):
+                fn()
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / reps
+            res[name + "_tflops"] = flops / (ms * 1e-3) / 1e12
+            res[name + "_ms"] = ms
+        out.append(res)
+        print(res, flush=True)
+    return out
+
+
 def main():
     import torch
     ap = argparse.ArgumentParser()
@@ -183,11 +226,17 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", default="gpurun_out/warmstart")
+    ap.add_argument("--conv-throughput", action="store_true")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     G.load()
     UN.load()
     assert torch.cuda.is_available()
+    if args.conv_throughput:
+        res = conv_throughput(args.n)
+        with open(os.path.join(args.out, "conv_throughput.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        return
     t0 = time.perf_counter()
     train_set = make_samples((args.n,) * 3, range(10000, 10000 + args.samples), args.workers)
     t_data = time.perf_counter() - t0
