@@ -85,7 +85,10 @@ typedef struct gmg_params {
   int32_t graphs;        /* 1: replay the solve's V-cycle (and refinement step)
                             as a captured HIP graph (default); 0: launch each
                             kernel directly.  Results are identical.           */
-  int32_t reserved;      /* must be 0                                          */
+  int32_t tail_cells;    /* levels >= 1 with at most this many cells (and all
+                            coarser ones) are cycled by one workgroup in one
+                            launch (same arithmetic as the grid-wide kernels);
+                            0 = off, at most 32768 (default 4096)             */
   double omega0;         /* relaxation factor at the start of a solve (1.0)   */
   double omega_min;      /* lower bound (0.1)                                 */
   double omega_max;      /* upper bound (1.0)                                 */

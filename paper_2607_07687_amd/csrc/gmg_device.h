@@ -94,6 +94,26 @@ __device__ __forceinline__ T stencil_Ax(const Geom& g, const T* __restrict__ x,
   return ax;
 }
 
+// Relaxed Gauss-Seidel update of one cell from its six neighbour values
+// (e, w: x+1, x-1; n, s: y+1, y-1; t, b: z+1, z-1), its six faces and sigma:
+// x + omega (sigma - (A x)_off) / D with D = -(sum of faces); a cell with D = 0
+// is left unchanged.  Every smoother calls this one function, so all of them
+// round identically.
+template <typename T>
+__device__ __forceinline__ T relax_cell(T xc, T xe, T xw, T xn, T xs, T xt, T xb, T lxm, T lxp,
+                                        T lym, T lyp, T lzm, T lzp, T sg, T omega) {
+  T ax = T(0);
+  ax += lxp * (xe - xc);
+  ax += lxm * (xw - xc);
+  ax += lyp * (xn - xc);
+  ax += lym * (xs - xc);
+  ax += lzp * (xt - xc);
+  ax += lzm * (xb - xc);
+  const T s = ((lxm + lxp) + (lym + lyp)) + (lzm + lzp);
+  if (s == T(0)) return xc;
+  return xc + omega * (sg - ax) / (-s);
+}
+
 // XCD-aware tile order.  The 8 XCDs of an MI355X each have their own L2 and
 // receive workgroups round-robin (workgroup b runs on XCD b % 8).  Mapping
 // hardware index b to logical tile t so that each XCD gets a contiguous range

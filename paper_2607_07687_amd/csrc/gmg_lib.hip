@@ -23,6 +23,7 @@
 
 #include "gmg_kernels.h"
 #include "gmg_sweep.h"
+#include "gmg_tail.h"
 
 using namespace gmg;
 
@@ -495,6 +496,7 @@ __global__ __launch_bounds__(BT) void k_ir_update(Geom g, double* __restrict__ x
 namespace {
 
 constexpr int kMaxLevels = 32;
+constexpr int kTailMaxCells = 32768;
 constexpr int kResChunk = 16;  // z-planes per block in the norm reductions
 
 struct Level {
@@ -563,6 +565,7 @@ struct gmg_handle {
   hipStream_t s;
   int nlev;
   Level lev[kMaxLevels];
+  int tail;      // first level cycled by k_tail (nlev: none)
   void* L0x;     // exact FP64 level-0 faces (dtype F64 with F32 cycles)
   void* w[2];    // level-0 work iterates (cycle dtype); the caller's x is the third
   double* partials;  // 2 * maxpart
@@ -651,6 +654,62 @@ static void enq_restrict(gmg_handle* h, int l, const Roles<T>& X, int role, cons
                      (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c, done);
 }
 
+// LDS bytes the tail needs when it starts at level lt.
+template <typename T, typename TL>
+static long long tail_bytes(const gmg_handle* h, int lt) {
+  long long b = 0;
+  for (int l = lt; l < h->nlev; ++l) b += tail_level_bytes<T, TL>(h->lev[l].g.n);
+  return b;
+}
+
+// Levels lt .. nlev-1 in one single-workgroup launch (gmg_tail.h).
+template <typename T, typename TL>
+static void enq_tail(gmg_handle* h, int lt, const int* done) {
+  TailArgs<T, TL> a{};
+  a.nl = h->nlev - lt;
+  a.nu_pre = h->p.nu_pre;
+  a.nu_post = h->p.nu_post;
+  a.nu_coarse = h->p.nu_coarse;
+  int off = 0;
+  for (int q = 0; q < a.nl; ++q) {
+    const Level& lv = h->lev[lt + q];
+    TailLevel<T, TL>& t = a.lv[q];
+    t.g = lv.g;
+    t.x = (T*)lv.x[0];
+    t.sigma = (T*)lv.sigma;
+    t.L = (const TL*)lv.L;
+    t.active = lv.active;
+    t.cx = lv.c[0] ? lv.c[0] : 1;
+    t.cy = lv.c[1] ? lv.c[1] : 1;
+    t.cz = lv.c[2] ? lv.c[2] : 1;
+    const long long n = lv.g.n;
+    t.ox = off;
+    t.os = t.ox + tail_round16(n * (long long)sizeof(T));
+    t.oL = t.os + tail_round16(n * (long long)sizeof(T));
+    t.oa = t.oL + tail_round16(3 * n * (long long)sizeof(TL));
+    off = t.oa + tail_round16(n);
+  }
+  hipLaunchKernelGGL((k_tail<T, TL>), dim3(1), dim3(kTailThreads), off, h->s, a, &h->st->omega,
+                     done);
+}
+
+// First level of the tail: the first level >= 1 from which every level has
+// at most tail_cells cells and all of them fit the tail's LDS budget and
+// level count (nlev: no tail).  Also lifts the kernel's dynamic-LDS limit.
+template <typename T, typename TL>
+static int plan_tail(gmg_handle* h) {
+  for (int l = 1; l < h->nlev; ++l) {
+    if (h->lev[l].g.n > h->p.tail_cells || h->nlev - l > kTailMax ||
+        tail_bytes<T, TL>(h, l) > kTailLds)
+      continue;
+    if (hipFuncSetAttribute((const void*)k_tail<T, TL>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds) != hipSuccess)
+      return h->nlev;
+    return l;
+  }
+  return h->nlev;
+}
+
 // V-cycle from level 0.  X0 is the level-0 role-0 buffer (with `sel`, the
 // roles rotate on the device).  Returns the level-0 role of the result.
 template <typename T, typename TL>
@@ -658,8 +717,9 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
   const int nl = h->nlev;
   const gmg_params& p = h->p;
   int role[kMaxLevels];
+  const int lt = h->tail;  // levels lt .. nl-1 run in one k_tail launch
   // descend: pre-smooth, then restrict the residual (coarse x starts at 0)
-  for (int l = 0; l < nl; ++l) {
+  for (int l = 0; l < lt; ++l) {
     const Roles<T> X = level_roles<T>(h, l, X0, sel);
     const T* sg = (l == 0) ? sigma0 : (const T*)h->lev[l].sigma;
     const bool coarsest = (l == nl - 1);
@@ -674,8 +734,13 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     if (coarsest) break;
     enq_restrict<T, TL>(h, l, X, r, sg, (T*)h->lev[l + 1].sigma, (T*)h->lev[l + 1].x[0], done);
   }
+  if (lt < nl) {
+    enq_tail<T, TL>(h, lt, done);
+    role[lt] = 0;  // the tail smooths in place in x[0]
+  }
   // ascend: prolong + correct (folded into the first post-sweep), post-smooth
-  for (int l = nl - 2; l >= 0; --l) {
+  const int top = (lt < nl) ? lt - 1 : nl - 2;
+  for (int l = top; l >= 0; --l) {
     const Roles<T> X = level_roles<T>(h, l, X0, sel);
     const T* sg = (l == 0) ? sigma0 : (const T*)h->lev[l].sigma;
     const Level& lv = h->lev[l];
@@ -760,6 +825,8 @@ static gmg_status validate(const gmg_params* p) {
   if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_coarse < 0 || p->nu_pre > 64 ||
       p->nu_post > 64 || p->nu_coarse > 256)
     return fail(GMG_EINVAL, "bad sweep counts");
+  if (p->tail_cells < 0 || p->tail_cells > kTailMaxCells)
+    return fail(GMG_EINVAL, "tail_cells must be in [0, 32768]");
   if (!(p->omega0 > 0) || !(p->omega_min > 0) || !(p->omega_max >= p->omega_min) ||
       !(p->theta_dec > 0) || !(p->theta_inc > 0) || !std::isfinite(p->omega_max) ||
       !std::isfinite(p->omega0) || !std::isfinite(p->theta_inc))
@@ -898,6 +965,7 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
   else if (p->l_storage == GMG_BF16) enq_build_levels<uint16_t>(h);
   else enq_build_levels<float>(h);
   HIP_TRY(hipGetLastError());
+  DISPATCH_CYCLE(h, { h->tail = plan_tail<T, TL>(h); });
   HIP_TRY(hipStreamSynchronize(h->s));
   return GMG_OK;
 }
@@ -1070,6 +1138,7 @@ gmg_status gmg_default_params(gmg_params* p) {
   p->nu_coarse = 4;
   p->rollback = 1;
   p->graphs = 1;
+  p->tail_cells = 4096;
   p->omega0 = 1.0;
   p->omega_min = 0.1;
   p->omega_max = 1.0;

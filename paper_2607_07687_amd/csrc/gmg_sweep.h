@@ -20,7 +20,9 @@
 // served by L2 / Infinity Cache.
 //
 // Optionally the prolongation + correction of the coarse-grid correction is
-// folded into the load: S(a) += x_c[a / c] on active cells before smoothing.
+// folded into the load: S(a) += x_c[a / c] on active cells before smoothing
+// (the coarse value and the mask are prefetched with the plane and added when
+// it is written to LDS).
 #pragma once
 
 #include "gmg_device.h"
@@ -146,6 +148,8 @@ template <typename T, int TY, int VEC>
 struct PlaneRegs {
   using C = SweepCfg<TY, VEC>;
   T s[C::NS][VEC], sg[C::NF][VEC], lx[C::NF][VEC], ly[C::NY][VEC], lz[C::NF][VEC];
+  T pc[C::NS][VEC];        // coarse correction of each S element (prolongation only)
+  uint32_t pa[C::NS];      // bit e set: element e is active and takes the correction
 };
 
 template <typename T, typename TL, int TY, int VEC>
@@ -174,16 +178,23 @@ __device__ __forceinline__ void fetch_plane(PlaneRegs<T, TY, VEC>& rg,
   for (int u = 0; u < C::NS; ++u) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) rg.s[u][e] = T(0);
+    rg.pa[u] = 0;
     if (ps.use[u] && ps.ii[u] >= 0 && ps.jj[u] >= 0 && kk >= 0) {
       const int ii = ps.ii[u], jj = ps.jj[u];
       const long long idx = po + (long long)jj * g.sy + ii;
       ldv<T, VEC>(a.S, idx, rg.s[u]);
       if (a.xc != nullptr) {
+        // Issued unconditionally (every in-domain cell has a coarse parent)
+        // and applied when the plane is written to LDS, so no load waits on
+        // another inside the prefetch.  Factors are 1 or 2: shift by c >> 1.
+        const long long cb = (long long)(kk >> (a.cz >> 1)) * a.gc.sz +
+                             (long long)(jj >> (a.cy >> 1)) * a.gc.sy;
+        if constexpr (VEC == 2)
+          rg.pa[u] = *reinterpret_cast<const uint16_t*>(a.active + idx);
+        else
+          rg.pa[u] = a.active[idx];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (a.active[idx + e])
-            rg.s[u][e] += a.xc[(long long)(kk / a.cz) * a.gc.sz + (long long)(jj / a.cy) * a.gc.sy +
-                               (ii + e) / a.cx];
+        for (int e = 0; e < VEC; ++e) rg.pc[u][e] = a.xc[cb + ((ii + e) >> (a.cx >> 1))];
       }
     }
   }
@@ -208,7 +219,7 @@ __device__ __forceinline__ void fetch_plane(PlaneRegs<T, TY, VEC>& rg,
 }
 
 template <typename T, int TY, int VEC>
-__device__ __forceinline__ void store_plane(SweepSmem<T, TY>& sm, int slot,
+__device__ __forceinline__ void store_plane(SweepSmem<T, TY>& sm, int slot, bool prol,
                                             const PlaneRegs<T, TY, VEC>& rg,
                                             const LoadPlan<SweepCfg<TY, VEC>::NS>& ps,
                                             const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
@@ -218,7 +229,11 @@ __device__ __forceinline__ void store_plane(SweepSmem<T, TY>& sm, int slot,
   for (int u = 0; u < C::NS; ++u)
     if (ps.use[u])
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) sm.s[slot][ps.row[u]][ps.col[u] + e] = rg.s[u][e];
+      for (int e = 0; e < VEC; ++e) {
+        // active-mask bytes: element e is byte e of pa (nonzero = active)
+        const bool corr = prol && ((rg.pa[u] >> (8 * e)) & 0xFFu) != 0;
+        sm.s[slot][ps.row[u]][ps.col[u] + e] = corr ? rg.s[u][e] + rg.pc[u][e] : rg.s[u][e];
+      }
 #pragma unroll
   for (int u = 0; u < C::NF; ++u)
     if (pf.use[u])
@@ -241,40 +256,22 @@ template <typename T, int TY>
 __device__ __forceinline__ T red_update(const SweepSmem<T, TY>& sm, int dm, int d, int dp, int sr,
                                         int ex, T omega) {
   const int fr = sr - 1;
-  const T xc = sm.s[d][sr][ex];
-  const T lxm = sm.lx[d][fr][ex], lxp = sm.lx[d][fr][ex + 1];
-  const T lym = sm.ly[d][fr][ex], lyp = sm.ly[d][fr + 1][ex];
-  const T lzm = sm.lz[d][fr][ex], lzp = sm.lz[dp][fr][ex];
-  T ax = T(0);
-  ax += lxp * (sm.s[d][sr][ex + 1] - xc);
-  ax += lxm * (sm.s[d][sr][ex - 1] - xc);
-  ax += lyp * (sm.s[d][sr + 1][ex] - xc);
-  ax += lym * (sm.s[d][sr - 1][ex] - xc);
-  ax += lzp * (sm.s[dp][sr][ex] - xc);
-  ax += lzm * (sm.s[dm][sr][ex] - xc);
-  const T s = ((lxm + lxp) + (lym + lyp)) + (lzm + lzp);
-  if (s == T(0)) return xc;
-  return xc + omega * (sm.sg[d][fr][ex] - ax) / (-s);
+  return relax_cell<T>(sm.s[d][sr][ex], sm.s[d][sr][ex + 1], sm.s[d][sr][ex - 1],
+                       sm.s[d][sr + 1][ex], sm.s[d][sr - 1][ex], sm.s[dp][sr][ex],
+                       sm.s[dm][sr][ex], sm.lx[d][fr][ex], sm.lx[d][fr][ex + 1],
+                       sm.ly[d][fr][ex], sm.ly[d][fr + 1][ex], sm.lz[d][fr][ex],
+                       sm.lz[dp][fr][ex], sm.sg[d][fr][ex], omega);
 }
 
 // Black update from the red values (rows of the red ring = face rows).
 template <typename T, int TY>
 __device__ __forceinline__ T black_update(const SweepSmem<T, TY>& sm, int dm, int d, int dp,
                                           int fr, int ex, T omega) {
-  const T xc = sm.s[d][fr + 1][ex];
-  const T lxm = sm.lx[d][fr][ex], lxp = sm.lx[d][fr][ex + 1];
-  const T lym = sm.ly[d][fr][ex], lyp = sm.ly[d][fr + 1][ex];
-  const T lzm = sm.lz[d][fr][ex], lzp = sm.lz[dp][fr][ex];
-  T ax = T(0);
-  ax += lxp * (sm.r[d][fr][ex + 1] - xc);
-  ax += lxm * (sm.r[d][fr][ex - 1] - xc);
-  ax += lyp * (sm.r[d][fr + 1][ex] - xc);
-  ax += lym * (sm.r[d][fr - 1][ex] - xc);
-  ax += lzp * (sm.r[dp][fr][ex] - xc);
-  ax += lzm * (sm.r[dm][fr][ex] - xc);
-  const T s = ((lxm + lxp) + (lym + lyp)) + (lzm + lzp);
-  if (s == T(0)) return xc;
-  return xc + omega * (sm.sg[d][fr][ex] - ax) / (-s);
+  return relax_cell<T>(sm.s[d][fr + 1][ex], sm.r[d][fr][ex + 1], sm.r[d][fr][ex - 1],
+                       sm.r[d][fr + 1][ex], sm.r[d][fr - 1][ex], sm.r[dp][fr][ex],
+                       sm.r[dm][fr][ex], sm.lx[d][fr][ex], sm.lx[d][fr][ex + 1],
+                       sm.ly[d][fr][ex], sm.ly[d][fr + 1][ex], sm.lz[d][fr][ex],
+                       sm.lz[dp][fr][ex], sm.sg[d][fr][ex], omega);
 }
 
 // Red phase for plane p: interior pairs (one red cell each) and the ring.
@@ -355,7 +352,7 @@ __device__ __forceinline__ void sweep_step(SweepSmem<T, TY>& sm, const SweepArgs
     }
   }
   __syncthreads();
-  if (k + 3 <= k1 + 1) store_plane<T, TY, VEC>(sm, ring3(k + 3), cur, ps, pf, py);
+  if (k + 3 <= k1 + 1) store_plane<T, TY, VEC>(sm, ring3(k + 3), a.xc != nullptr, cur, ps, pf, py);
   __syncthreads();
 }
 
@@ -380,20 +377,20 @@ __device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
   PlaneRegs<T, TY, VEC> ra, rb;
   fetch_plane<T, TL, TY, VEC>(ra, a, k0 - 2, ps, pf, py);
   fetch_plane<T, TL, TY, VEC>(rb, a, k0 - 1, ps, pf, py);
-  store_plane<T, TY, VEC>(sm, ring3(k0 - 2), ra, ps, pf, py);
-  store_plane<T, TY, VEC>(sm, ring3(k0 - 1), rb, ps, pf, py);
+  store_plane<T, TY, VEC>(sm, ring3(k0 - 2), a.xc != nullptr, ra, ps, pf, py);
+  store_plane<T, TY, VEC>(sm, ring3(k0 - 1), a.xc != nullptr, rb, ps, pf, py);
   fetch_plane<T, TL, TY, VEC>(ra, a, k0, ps, pf, py);
   fetch_plane<T, TL, TY, VEC>(rb, a, k0 + 1, ps, pf, py);
-  store_plane<T, TY, VEC>(sm, ring3(k0), ra, ps, pf, py);
+  store_plane<T, TY, VEC>(sm, ring3(k0), a.xc != nullptr, ra, ps, pf, py);
   __syncthreads();
   red_phase<T, TY>(sm, i0, j0, k0 - 1, omega);  // reads planes k0-2 .. k0
   __syncthreads();
-  store_plane<T, TY, VEC>(sm, ring3(k0 + 1), rb, ps, pf, py);  // slot of plane k0-2
+  store_plane<T, TY, VEC>(sm, ring3(k0 + 1), a.xc != nullptr, rb, ps, pf, py);  // slot of plane k0-2
   fetch_plane<T, TL, TY, VEC>(ra, a, k0 + 2, ps, pf, py);
   __syncthreads();
   red_phase<T, TY>(sm, i0, j0, k0, omega);  // reads planes k0-1 .. k0+1
   __syncthreads();
-  store_plane<T, TY, VEC>(sm, ring3(k0 + 2), ra, ps, pf, py);  // slot of plane k0-1
+  store_plane<T, TY, VEC>(sm, ring3(k0 + 2), a.xc != nullptr, ra, ps, pf, py);  // slot of plane k0-1
   fetch_plane<T, TL, TY, VEC>(ra, a, k0 + 3, ps, pf, py);
   __syncthreads();
   int k;

@@ -37,12 +37,19 @@ def _gen(args):
     return L.astype(np.float64), s.astype(np.float64), per
 
 
-def generate(n, seeds, workers=8):
-    """Host-side generation of the warm-start problems (process pool)."""
+def generate(n, seeds, workers=8, chunk=32):
+    """Host-side generation of the warm-start problems (process pool),
+    yielded in order chunk by chunk so that at most a few chunks of FP64
+    problems are held on the host at a time."""
+    seeds = list(seeds)
     if workers <= 1:
-        return [_gen((n, s)) for s in seeds]
+        for s in seeds:
+            yield _gen((n, s))
+        return
     with ProcessPoolExecutor(workers) as ex:
-        return list(ex.map(_gen, [(n, s) for s in seeds], chunksize=4))
+        for c0 in range(0, len(seeds), chunk):
+            part = [(n, s) for s in seeds[c0:c0 + chunk]]
+            yield from ex.map(_gen, part, chunksize=max(1, len(part) // workers))
 
 
 class Sample:
@@ -81,9 +88,12 @@ def solve_fp64(L, s, per):
 
 def make_samples(n, seeds, workers=8, with_target=True):
     out = []
+    t0 = time.perf_counter()
     for L, s, per in generate(n, seeds, workers):
         p = solve_fp64(L, s, per) if with_target else None
         out.append(Sample(L, s, per, p))
+        if len(out) % 100 == 0:
+            print(f"{len(out)} samples at {n} ({time.perf_counter() - t0:.1f}s)", flush=True)
     return out
 
 

@@ -379,3 +379,56 @@ def test_autotune_keeps_results_bitwise(tmp_path):
         G.gmg_set_tiles(h2, 0, 8, 1000)
     h.close()
     h2.close()
+
+
+# (name, n, periodic, anisotropic) for the single-workgroup tail
+TAIL_CASES = [
+    ("sphere_walls", (48, 24, 16), None, 1),
+    ("periodic_iso", (32, 32, 32), (True, True, True), 0),
+    ("channel_aniso", (64, 16, 12), (True, False, False), 1),
+    ("odd_coarsest", (60, 24, 24), (False, False, False), 1),
+]
+
+
+@pytest.mark.parametrize("prec,storage", [("f32", "f32"), ("f64", "f64"), ("f32", "bf16")])
+@pytest.mark.parametrize("case", TAIL_CASES, ids=lambda c: c[0])
+def test_tail_matches_grid_kernels(case, prec, storage):
+    # the coarse levels cycled by one workgroup give bitwise what the
+    # grid-wide kernels give, and the V-cycle still matches the oracle
+    name, n, per, aniso = case
+    if per is None:
+        L, s, per = P.sphere_box(n, tuple(0.4 * v for v in n), n[2] / 4, "uniform", 3)
+    else:
+        L, s, _ = P.random_problem(n, per, seed=zlib.crc32(name.encode()) % 1000,
+                                   contrast=2.0, holes=0.05)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, prec, storage, anisotropic=aniso,
+                                        tail_cells=32768)
+    p0 = G.gmg_default_params(h.params.n, per, h.params.dtype, l_storage=h.params.l_storage,
+                              anisotropic=aniso, tail_cells=0)
+    h0 = G.gmg_setup(p0, Ld)
+    say(f"{name} {prec}/{storage}: {len(levels)} levels")
+    xt, x0 = torch.zeros_like(sd), torch.zeros_like(sd)
+    G.gmg_vcycle(h, xt, sd)
+    G.gmg_vcycle(h0, x0, sd)
+    assert torch.equal(xt, x0)
+    xo = O.vcycle(levels, np.zeros_like(s64), s64, 1.0)
+    assert rel(host(xt), xo) <= TOL[prec if storage != "bf16" else "bf16"]
+    tol = 1e-8 if prec == "f64" else 1e-5
+    xt.zero_()
+    x0.zero_()
+    rt = G.gmg_solve(h, xt, sd, tol, 80)
+    r0 = G.gmg_solve(h0, x0, sd, tol, 80)
+    assert torch.equal(xt, x0)
+    assert rt["history"] == r0["history"] and rt["omegas"] == r0["omegas"]
+    h.close()
+    h0.close()
+
+
+def test_tail_cells_bounds():
+    require_gpu()
+    L = torch.ones((3, 8, 8, 8), dtype=torch.float32, device="cuda")
+    p = G.gmg_default_params((8, 8, 8), (False, False, False), tail_cells=32769)
+    with pytest.raises(G.GMGError) as e:
+        G.gmg_setup(p, L)
+    assert e.value.status == G.GMG_EINVAL
+    assert G.gmg_default_params((8, 8, 8), (False,) * 3).tail_cells == 4096
