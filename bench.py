@@ -29,8 +29,46 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_CELL = 24.0
 
 
+# hardware-counter summary of the level-0 sweep (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of `bench.py --kernel-probe`); it names the hash of the
+# sources the counted kernel was built from
+COUNTERS = os.path.join(ROOT, "profiles", "sweep256_fp32_counters.md")
+SWEEP_SOURCES = ["paper_2607_07687_amd/csrc/gmg_sweep.h", "paper_2607_07687_amd/csrc/gmg_device.h",
+                 "paper_2607_07687_amd/csrc/gmg_lib.hip", "paper_2607_07687_amd/build.py"]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per level-0 sweep launch from the committed counter runs:
+    FETCH_SIZE scaled by the copy-kernel calibration factor, plus WRITE_SIZE.
+    None when the summary is missing or the sweep's sources have changed
+    since the counters were taken."""
+    import re
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^- (\w+): ([0-9a-f.]+)\s*$", text, re.M))
+    try:
+        if vals["source_hash"] != sweep_source_hash():
+            return None
+        kib = float(vals["fetch_kib_per_launch"]) * float(vals["fetch_factor"]) + \
+            float(vals["write_kib_per_launch"]) * float(vals["write_factor"])
+    except (KeyError, ValueError):
+        return None
+    return kib * 1024.0
 
 
 def cpu_baseline():
@@ -262,7 +300,8 @@ def main():
         "roofline": {"bound": "hbm",
                      "kernel": f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (counters)",
                      "avg_launch_us": sweep_ms * 1e3,
                      "alg_bytes_per_launch": alg_bytes},
     }

@@ -109,6 +109,10 @@ unet_status unet_adam(int64_t n, float* master, float* m, float* v, const float*
 /* out[i] = a * in[i] (FP32; turns the network's p / s back into p). */
 unet_status unet_scale(int64_t n, const float* in, float a, float* out, void* stream);
 
+/* out[i] = a * (double)in[i] (FP64 out: the network's p / s as the initial
+ * guess of the FP64 refinement solve). */
+unet_status unet_scale_f64(int64_t n, const float* in, double a, double* out, void* stream);
+
 /* FP32 -> BF16 (round to nearest even) and BF16 -> FP32 conversion. */
 unet_status unet_to_bf16(int64_t n, const float* in, void* out, void* stream);
 unet_status unet_from_bf16(int64_t n, const void* in, float* out, void* stream);

@@ -377,7 +377,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
         for (int ty = 0; ty < L.g.ny; ty += TY)
           for (int tx = 0; tx < L.g.nx; tx += SW_TX)
             sw[l].push_back(BTile{di, tx, ty, kz, std::min(L.g.nz, kz + L.kchunk), 0});
-      // restriction tiles (fine 64 x 4 tiles, one coarse plane each)
+      // restriction tiles (fine BX x BY tiles, one coarse plane each)
       if (!coarsest)
         for (int K = 0; K < h->lev[l + 1].g.nz; ++K)
           for (int ty = 0; ty < L.g.ny; ty += BY)

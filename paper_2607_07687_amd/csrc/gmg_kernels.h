@@ -51,6 +51,6 @@ struct OmegaRule {
   int rollback;
 };
 
-constexpr int BX = 64, BY = 4, BT = BX * BY;  // cell-kernel block: one wave per row
+constexpr int BX = 128, BY = 2, BT = BX * BY;  // cell-kernel block: two waves per row
 
 }  // namespace gmg

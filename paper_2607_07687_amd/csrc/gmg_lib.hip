@@ -73,26 +73,71 @@ struct Roles {
   }
 };
 
+// Walk column (i, j) over the z-planes [k0, k1) and call f(idx, ax, D) for
+// each cell with ax = (A x)(cell) and D its diagonal, computed with the same
+// arithmetic, term by term, as stencil_Ax.  The x and y neighbour offsets are
+// fixed for the column, and the z-neighbours and z-faces roll through
+// registers as the walk goes up.
+template <typename T, typename TL, typename F>
+__device__ __forceinline__ void walk_column(const Geom& g, const T* __restrict__ x,
+                                            const TL* __restrict__ L, int i, int j, int k0, int k1,
+                                            F&& f) {
+  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
+  const Nb nx = neighbours(i, g.nx, g.px, 1);
+  const Nb ny = neighbours(j, g.ny, g.py, g.sy);
+  const TL* __restrict__ Ly = L + g.n;
+  const TL* __restrict__ Lz = L + 2 * g.n;
+  const long long base = (long long)j * g.sy + i;
+  const long long top = (long long)(g.nz - 1) * g.sz;
+  long long idx = (long long)k0 * g.sz + base;
+  T xc = x[idx];
+  T xb = (k0 > 0) ? x[idx - g.sz] : (g.pz ? x[top + base] : xc);  // z low neighbour
+  T lzm = ldL<T>(Lz, idx);
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k, idx += g.sz) {
+    // z high neighbour and face: next plane, wrap, or (wall) self with face 0
+    const bool zin = k + 1 < g.nz;
+    const long long hi = zin ? idx + g.sz : base;
+    const T xt = (zin || g.pz) ? x[hi] : xc;
+    const T lzp = (zin || g.pz) ? ldL<T>(Lz, hi) : T(0);
+    T ax = T(0), s = T(0);
+    {
+      const T lm = ldL<T>(L, idx);
+      const T lp = nx.hi_ok ? ldL<T>(L, idx + nx.hi) : T(0);
+      ax += lp * (x[idx + nx.hi] - xc);
+      ax += lm * (x[idx + nx.lo] - xc);
+      s += lm + lp;
+    }
+    {
+      const T lm = ldL<T>(Ly, idx);
+      const T lp = ny.hi_ok ? ldL<T>(Ly, idx + ny.hi) : T(0);
+      ax += lp * (x[idx + ny.hi] - xc);
+      ax += lm * (x[idx + ny.lo] - xc);
+      s += lm + lp;
+    }
+    ax += lzp * (xt - xc);
+    ax += lzm * (xb - xc);
+    s += lzm + lzp;
+    f(idx, ax, -s);
+    xb = xc;
+    xc = xt;
+    lzm = lzp;
+  }
+}
+
 // r = sigma - A x on active cells (0 elsewhere) for column (i, j) over the
 // z-planes [k0, k1); optional store of r; returns the column's sum of r^2.
 template <typename T, typename TL>
 __device__ __forceinline__ double residual_column(const Geom& g, const T* __restrict__ x,
                                                   const T* __restrict__ sigma,
-                                                  const TL* __restrict__ L, T* r, int i, int j,
-                                                  int k0, int k1) {
+                                                  const TL* __restrict__ L, T* __restrict__ r,
+                                                  int i, int j, int k0, int k1) {
   double acc = 0.0;
-  if (i < g.nx && j < g.ny) {
-#pragma unroll 4
-    for (int k = k0; k < k1; ++k) {
-      const long long idx = (long long)k * g.sz + (long long)j * g.sy + i;
-      const T xc = x[idx];
-      T D;
-      const T ax = stencil_Ax<T, TL>(g, x, L, idx, i, j, k, xc, D);
-      const T rv = (D != T(0)) ? sigma[idx] - ax : T(0);
-      if (r) r[idx] = rv;
-      acc += (double)rv * (double)rv;
-    }
-  }
+  walk_column<T, TL>(g, x, L, i, j, k0, k1, [&](long long idx, T ax, T D) {
+    const T rv = (D != T(0)) ? sigma[idx] - ax : T(0);
+    if (r) r[idx] = rv;
+    acc += (double)rv * (double)rv;
+  });
   return acc;
 }
 
@@ -137,7 +182,7 @@ __global__ __launch_bounds__(BT) void k_masked_sumsq(Geom g, const T* __restrict
     partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
 
-// Fused residual + restriction, one thread per FINE cell of the 64 x 4 tile
+// Fused residual + restriction, one thread per FINE cell of the BX x BY tile
 // at (i0, j0): each thread sums the residuals of its column over the cz fine
 // planes of coarse plane K; x-pairs are combined by a lane shuffle and y-pairs
 // through LDS; the thread at each block's origin writes sigma_c and zeroes x_c.
@@ -151,16 +196,9 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BX], const Geom& gf,
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
   T acc = T(0);
-  if (i < gf.nx && j < gf.ny) {
-    for (int sz = 0; sz < cz; ++sz) {
-      const int k = K * cz + sz;
-      const long long idx = (long long)k * gf.sz + (long long)j * gf.sy + i;
-      const T xc = x[idx];
-      T D;
-      const T ax = stencil_Ax<T, TL>(gf, x, L, idx, i, j, k, xc, D);
-      if (D != T(0)) acc += sigma[idx] - ax;
-    }
-  }
+  walk_column<T, TL>(gf, x, L, i, j, K * cz, K * cz + cz, [&](long long idx, T ax, T D) {
+    if (D != T(0)) acc += sigma[idx] - ax;
+  });
   if (cx == 2) acc += __shfl_xor(acc, 1, 64);
   if (cy == 2) {
     rows[ty][tx] = acc;

@@ -508,6 +508,12 @@ __global__ void k_scale(long long n, const float* __restrict__ in, float a, floa
   if (i < n) out[i] = a * in[i];
 }
 
+__global__ void k_scale_f64(long long n, const float* __restrict__ in, double a,
+                            double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * (double)in[i];
+}
+
 __global__ void k_to_bf16(long long n, const float* __restrict__ in, uint16_t* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = f2bf(in[i]);
@@ -795,6 +801,14 @@ unet_status unet_scale(int64_t n, const float* in, float a, float* out, void* st
   if (n <= 0 || !in || !out) return ufail(UNET_EINVAL, "bad args");
   hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, (long long)n, in, a,
                      out);
+  UHIP(hipGetLastError());
+  return UNET_OK;
+}
+
+unet_status unet_scale_f64(int64_t n, const float* in, double a, double* out, void* stream) {
+  if (n <= 0 || !in || !out) return ufail(UNET_EINVAL, "bad args");
+  hipLaunchKernelGGL(k_scale_f64, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, (long long)n,
+                     in, a, out);
   UHIP(hipGetLastError());
   return UNET_OK;
 }

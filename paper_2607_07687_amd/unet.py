@@ -52,6 +52,7 @@ _SIGS = [
                                 ctypes.POINTER(ctypes.c_double), _V]),
     ("unet_adam", ctypes.c_int, [ctypes.c_int64, _V, _V, _V, _V, _V, _F, _F, _F, _F, _I, _V]),
     ("unet_scale", ctypes.c_int, [ctypes.c_int64, _V, _F, _V, _V]),
+    ("unet_scale_f64", ctypes.c_int, [ctypes.c_int64, _V, ctypes.c_double, _V, _V]),
     ("unet_to_bf16", ctypes.c_int, [ctypes.c_int64, _V, _V, _V]),
     ("unet_from_bf16", ctypes.c_int, [ctypes.c_int64, _V, _V, _V]),
     ("unet_pack_input", ctypes.c_int, [unet_shape, _V, _V, ctypes.POINTER(ctypes.c_float), _V, _V]),
@@ -172,6 +173,10 @@ def unet_adam(master, m, v, g, bf16_out, lr, t, beta1=0.9, beta2=0.999, eps=1e-8
 
 def unet_scale(x, a, out):
     _check(load().unet_scale(x.numel(), _p(x), float(a), _p(out), _stream()))
+
+
+def unet_scale_f64(x, a, out):
+    _check(load().unet_scale_f64(x.numel(), _p(x), float(a), _p(out), _stream()))
 
 
 def unet_to_bf16(x, out):

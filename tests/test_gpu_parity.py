@@ -2,8 +2,8 @@
 C ABI: hierarchy and face restriction, residual, red-black smoothing,
 fused residual + restriction, prolongation + correction, one V-cycle, and the
 adaptive solve (history, relaxation decisions, result).  Sizes span several
-64 x 4 tiles with ragged tails, both boundary kinds, inactive cells, FP32,
-FP64 and BF16 face storage."""
+128 x 2 cell-kernel tiles and 64 x TY sweep tiles with ragged tails, both
+boundary kinds, inactive cells, FP32, FP64 and BF16 face storage."""
 import zlib
 
 import numpy as np

@@ -225,3 +225,15 @@ def test_head_mse_adam():
         UO.adam_step(po, {"p": g.astype(np.float32).astype(np.float64)}, st, 1e-3)
     assert rel(master.cpu().numpy().astype(np.float64) - p0, po["p"] - p0) <= 1e-4
     assert np.array_equal(out16.cpu().numpy().view(np.uint16), bf16_round(master.cpu().numpy()))
+
+
+def test_scale_to_fp32_and_fp64():
+    require_gpu()
+    v = np.random.default_rng(8).standard_normal(1000).astype(np.float32)
+    vd = torch.from_numpy(v).cuda()
+    o32 = torch.zeros_like(vd)
+    o64 = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    UN.unet_scale(vd, 2.5, o32)
+    UN.unet_scale_f64(vd, 0.1, o64)
+    assert np.array_equal(o32.cpu().numpy(), (np.float32(2.5) * v).astype(np.float32))
+    assert np.array_equal(o64.cpu().numpy(), 0.1 * v.astype(np.float64))
