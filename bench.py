@@ -33,8 +33,9 @@ SWEEP_BYTES_PER_CELL = 24.0
 # WRITE_SIZE runs of `bench.py --kernel-probe`); it names the hash of the
 # sources the counted kernel was built from
 COUNTERS = os.path.join(ROOT, "profiles", "sweep256_fp32_counters.md")
+# everything the level-0 sweep kernel is compiled from (kernel, helpers, flags)
 SWEEP_SOURCES = ["paper_2607_07687_amd/csrc/gmg_sweep.h", "paper_2607_07687_amd/csrc/gmg_device.h",
-                 "paper_2607_07687_amd/csrc/gmg_lib.hip", "paper_2607_07687_amd/build.py"]
+                 "paper_2607_07687_amd/build.py"]
 
 
 def log(msg):
@@ -71,27 +72,27 @@ def measured_traffic():
     return kib * 1024.0
 
 
-def cpu_baseline():
-    """The CPU oracle, untuned, on a bounded sample: one V-cycle plus the
-    residual norm of the same workload recipe at 128^3 (sphere diameter 32 at
-    the centre, uniform face velocity seed 1), scaled by the cell ratio to
-    256^3."""
+def cpu_baseline(cycles=2):
+    """The CPU oracle, untuned, on a bounded sample of the benchmark workload
+    itself: `cycles` V-cycles, each followed by the residual norm, on the
+    same 256^3 sphere problem rounded to FP32 (hierarchy built untimed)."""
     from oracle import gmg_oracle as O
     from paper_2607_07687_amd import problems as P
 
-    n = 128
-    L, s, per = P.sphere_box((n, n, n), (n / 2,) * 3, n / 8, "uniform", 1)
+    L, s, per = P.sphere_256(seed=1)
     L = L.astype(np.float32).astype(np.float64)
     s = s.astype(np.float32).astype(np.float64)
     levels = O.build_hierarchy(L, per, storage="f32")
+    del L
+    x = np.zeros_like(s)
     t0 = time.perf_counter()
-    x = O.vcycle(levels, np.zeros_like(s), s, 1.0)
-    O.norm2(O.residual(x, s, levels[0]["L"], per))
+    for _ in range(cycles):
+        x = O.vcycle(levels, x, s, 1.0)
+        O.norm2(O.residual(x, s, levels[0]["L"], per))
     dt = time.perf_counter() - t0
-    scale = (n ** 3) / (256 ** 3)
-    return {"value": scale / dt, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 oracle V-cycle + residual norm at 128^3 (same recipe), "
-                      f"{dt:.1f} s, scaled by 1/8 to 256^3; NumPy elementwise, one thread; "
+    return {"value": cycles / dt, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cycles} oracle V-cycles, each with its residual norm, on the 256^3 "
+                      f"benchmark problem: {dt:.1f} s; NumPy elementwise, one thread; "
                       f"host has {os.cpu_count()} logical CPUs"}
 
 

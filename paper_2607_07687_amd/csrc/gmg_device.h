@@ -126,6 +126,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
 }
 
+__device__ __forceinline__ bool stopped(const int* done) { return done != nullptr && *done; }
+
+// Iterate buffers of a level by role.  Level 0 has three buffers whose roles
+// rotate on the device: role 0 is the accepted iterate, roles 1 and 2 are the
+// cycle's ping-pong work buffers; with a selector, buffer (*sel + role) % 3
+// plays `role`.  Coarse levels (and calls without a selector) use the
+// buffers directly by role.
+template <typename T>
+struct Roles {
+  T* p[3];
+  const int* sel;
+  __device__ __forceinline__ T* get(int role) const {
+    const int base = (sel != nullptr) ? *sel : 0;
+    return p[(base + role) % 3];
+  }
+};
+
 // Sum of v over a block of `nthreads` (multiple of 64, <= 1024) threads,
 // fixed order: wavefront shuffle tree, then wave partials in index order.
 // The result is valid in thread 0 only.

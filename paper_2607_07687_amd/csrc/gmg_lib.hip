@@ -56,23 +56,6 @@ static gmg_status fail(gmg_status s, const std::string& msg) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool stopped(const int* done) { return done != nullptr && *done; }
-
-// Iterate buffers of a level by role.  Level 0 has three buffers whose roles
-// rotate on the device: role 0 is the accepted iterate, roles 1 and 2 are the
-// cycle's ping-pong work buffers; with a selector, buffer (*sel + role) % 3
-// plays `role`.  Coarse levels (and calls without a selector) use the
-// buffers directly by role.
-template <typename T>
-struct Roles {
-  T* p[3];
-  const int* sel;
-  __device__ __forceinline__ T* get(int role) const {
-    const int base = (sel != nullptr) ? *sel : 0;
-    return p[(base + role) % 3];
-  }
-};
-
 // Walk column (i, j) over the z-planes [k0, k1) and call f(idx, ax, D) for
 // each cell with ax = (A x)(cell) and D its diagonal, computed with the same
 // arithmetic, term by term, as stencil_Ax.  The x and y neighbour offsets are
@@ -255,27 +238,6 @@ __global__ __launch_bounds__(BT) void k_copy_role(Geom g, Roles<T> X, int rs, in
   if (i >= g.nx || j >= g.ny) return;
   const long long idx = (long long)blockIdx.z * g.sz + (long long)j * g.sy + i;
   dst[idx] = src[idx];
-}
-
-// Fused red-black sweep X[rd] = sweep(X[rs] (+ P x_c)), see gmg_sweep.h.
-template <typename T, typename TL, int TY, int VEC>
-__global__ __launch_bounds__(32 * TY) void k_rb_sweep(Geom g, Roles<T> X, int rs, int rd,
-                                                      const T* __restrict__ sigma,
-                                                      const TL* __restrict__ L,
-                                                      const T* __restrict__ xc,
-                                                      const uint8_t* __restrict__ active, Geom gc,
-                                                      int cx, int cy, int cz, int kchunk,
-                                                      const double* omega_p, const int* done) {
-  if (stopped(done)) return;
-  __shared__ SweepSmem<T, TY> sm;
-  SweepArgs<T, TL, TY, VEC> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
-  // 1-D grid of tiles, x fastest, then y, then z-chunks, in XCD-aware order
-  const int ntx = (g.nx + SW_TX - 1) / SW_TX, nty = (g.ny + TY - 1) / TY;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-  const int k0 = tz * kchunk;
-  rb_sweep_tile<T, TL, TY, VEC>(sm, a, X.get(rd), tx * SW_TX, ty * TY, k0,
-                                min(g.nz, k0 + kchunk), (T)(*omega_p));
 }
 
 // Level-0 face copy from the caller's dtype into storage, zeroing the low

@@ -402,3 +402,25 @@ __device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
 }
 
 }  // namespace gmg
+
+// The fused sweep kernel: X[rd] = sweep(X[rs] (+ P x_c)), at global scope
+// so that its symbol carries no namespace.
+template <typename T, typename TL, int TY, int VEC>
+__global__ __launch_bounds__(32 * TY) void k_rb_sweep(gmg::Geom g, gmg::Roles<T> X, int rs, int rd,
+                                                      const T* __restrict__ sigma,
+                                                      const TL* __restrict__ L,
+                                                      const T* __restrict__ xc,
+                                                      const uint8_t* __restrict__ active, gmg::Geom gc,
+                                                      int cx, int cy, int cz, int kchunk,
+                                                      const double* omega_p, const int* done) {
+  if (gmg::stopped(done)) return;
+  __shared__ gmg::SweepSmem<T, TY> sm;
+  gmg::SweepArgs<T, TL, TY, VEC> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
+  // 1-D grid of tiles, x fastest, then y, then z-chunks, in XCD-aware order
+  const int ntx = (g.nx + gmg::SW_TX - 1) / gmg::SW_TX, nty = (g.ny + TY - 1) / TY;
+  const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int k0 = tz * kchunk;
+  gmg::rb_sweep_tile<T, TL, TY, VEC>(sm, a, X.get(rd), tx * gmg::SW_TX, ty * TY, k0,
+                                     min(g.nz, k0 + kchunk), (T)(*omega_p));
+}
