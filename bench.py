@@ -108,6 +108,61 @@ def timed(fn, reps=3):
     return float(np.median(ts)), out
 
 
+def solver_comparison(rtol=1e-6, reps=3):
+    """The paper's solver table on synthetic stand-ins: generic PCG, GMG with
+    the PCG smoother and GMG with the adaptive red-black smoother, FP32 from
+    x = 0 to rtol, on walled boxes with a sphere at the table's grid sizes
+    4 * 2^(3p) (p = 5, 6: 2:1:2 boxes) and on the 256^3 benchmark problem.
+    Iterations are PCG iterations or V-cycles; cost is wall time per cell."""
+    import torch
+    from paper_2607_07687_amd import gmg as G
+    from paper_2607_07687_amd import problems as P
+    out = {}
+    for name, n in (("p5_64x32x64", (64, 32, 64)), ("p6_128x64x128", (128, 64, 128)),
+                    ("sphere256", (256, 256, 256))):
+        if n[0] == 256:
+            L, s, per = P.sphere_256(seed=1)
+        else:
+            L, s, per = P.sphere_box(n, tuple(v / 2 for v in n), n[1] / 4, "uniform", 1)
+        Ld = torch.from_numpy(L.astype(np.float32)).cuda()
+        sd = torch.from_numpy(s.astype(np.float32)).cuda()
+        del L, s
+        cells = n[0] * n[1] * n[2]
+        row = {}
+        for solver in ("PCG", "GMG-PCG", "GMG-RBGS"):
+            smoother = G.GMG_SMOOTH_PCG if solver == "GMG-PCG" else G.GMG_SMOOTH_RBGS
+            h = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F32, smoother=smoother), Ld)
+            x = torch.zeros_like(sd)
+
+            def run():
+                x.zero_()
+                if solver == "PCG":
+                    i = G.gmg_pcg(h, x, sd, rtol, 20000)
+                    return i["status"], i["iterations"]
+                i = G.gmg_solve(h, x, sd, rtol, 500)
+                return i["status"], i["cycles"]
+
+            run()  # capture / warm-up
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                status, its = run()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            rn, sn = G.gmg_residual(h, x, sd)
+            ms = 1e3 * float(np.median(ts))
+            row[solver] = {"iterations": its, "status": status, "final_rel": rn / sn, "ms": ms,
+                           "ns_per_cell": 1e6 * ms / cells}
+            h.close()
+        base = row["GMG-RBGS"]["ms"]
+        row["cost_ratio_vs_gmg_rbgs"] = {k: row[k]["ms"] / base for k in ("PCG", "GMG-PCG")}
+        out[name] = row
+        log(f"{name}: " + ", ".join(f"{k} {row[k]['iterations']} it {row[k]['ms']:.2f} ms"
+                                    for k in ("PCG", "GMG-PCG", "GMG-RBGS")))
+    return out
+
+
 def extra_configs():
     """The other workloads, each on one GPU: the 32^3 periodic FP64 solve to
     1e-10, anisotropic vs isotropic coarsening on the 512 x 192 x 192 sphere
@@ -308,6 +363,7 @@ def main():
     }
     if not args.no_extras:
         out["other_configs"] = extra_configs()
+        out["other_configs"]["solver_table"] = solver_comparison()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

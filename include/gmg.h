@@ -60,6 +60,8 @@ typedef enum gmg_status {
 
 typedef enum gmg_dtype { GMG_F32 = 0, GMG_F64 = 1, GMG_BF16 = 2 } gmg_dtype;
 
+typedef enum gmg_smoother { GMG_SMOOTH_RBGS = 0, GMG_SMOOTH_PCG = 1 } gmg_smoother;
+
 /* Solver parameters.  gmg_default_params fills the defaults noted here. */
 typedef struct gmg_params {
   int32_t n[3];          /* cells (nx, ny, nz)                                 */
@@ -89,6 +91,15 @@ typedef struct gmg_params {
                             coarser ones) are cycled by one workgroup in one
                             launch (same arithmetic as the grid-wide kernels);
                             0 = off, at most 32768 (default 4096)             */
+  int32_t smoother;      /* GMG_SMOOTH_RBGS (default): adaptive under-relaxed
+                            red-black Gauss-Seidel (Sec. 3.1).  GMG_SMOOTH_PCG:
+                            each smoothing step is a Jacobi-preconditioned CG
+                            run of nu_pre / nu_post / nu_coarse iterations,
+                            restarted from the current iterate (the GMG-PCG
+                            comparison of Sec. 3 and Table 1); omega is then
+                            unused, every cycle is accepted (no rollback) and
+                            no single-workgroup tail is used                  */
+  int32_t reserved;      /* must be 0                                          */
   double omega0;         /* relaxation factor at the start of a solve (1.0)   */
   double omega_min;      /* lower bound (0.1)                                 */
   double omega_max;      /* upper bound (1.0)                                 */
@@ -205,6 +216,32 @@ gmg_status gmg_vcycle(gmg_handle* h, void* x, const void* sigma,
 gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol,
                      int32_t max_cycles, gmg_solve_info* info);
 
+/* Filled by gmg_pcg.  history[k] is ||r||/||sigma|| of the recursive residual
+ * after iteration k (the first GMG_MAX_HISTORY iterations). */
+typedef struct gmg_pcg_info {
+  int32_t status;        /* GMG_OK or GMG_ENOCONV                              */
+  int32_t iterations;
+  double snorm;          /* ||sigma|| over active cells                        */
+  double rnorm0;         /* ||sigma - A x0||                                   */
+  double rnorm;          /* final recursive ||r||                              */
+  double history[GMG_MAX_HISTORY];
+} gmg_pcg_info;
+
+/* The general-purpose solver the paper compares GMG with (Sec. 3, Table 1):
+ * Jacobi-preconditioned conjugate gradient on level 0 of the handle, i.e.
+ * conjugate gradient on (-A) x = -sigma over the active cells with the
+ * preconditioner diag(-A).  x (dtype, in/out) is the initial guess and the
+ * result; sigma (dtype) as for gmg_solve.  Iterates until the recursive
+ * residual satisfies ||r||/||sigma|| <= rtol (rtol > 0) or max_iter
+ * iterations; the vectors are in the cycle precision (dtype == cycle_dtype
+ * required), the inner products FP64 on the device.  One iteration is a
+ * captured graph of four kernels replayed in rounds; the host reads back a
+ * small header between rounds.  Allocates the level-0 work vectors (six
+ * arrays) on first use.  info (host) may be NULL.  Returns GMG_ENOCONV if the
+ * tolerance was not reached (x holds the last iterate). */
+gmg_status gmg_pcg(gmg_handle* h, void* x, const void* sigma, double rtol, int32_t max_iter,
+                   gmg_pcg_info* info);
+
 /* Filled by gmg_solve_ir.  history[m] is ||sigma - A x||/||sigma|| (FP64,
  * exact faces) before outer step m, and after the last one. */
 typedef struct gmg_ir_info {
@@ -240,8 +277,9 @@ typedef struct gmg_batch gmg_batch;
 
 /* Set up a batch of nprob independent problems of (possibly) different sizes
  * for gmg_batch_solve_ir.  params: host array of nprob parameter sets, each
- * with dtype F64 and cycle_dtype F32, all sharing l_storage, the sweep counts
- * (with nu_coarse == nu_pre + nu_post) and the relaxation rule.  L: host array
+ * with dtype F64 and cycle_dtype F32, the red-black smoother, all sharing
+ * l_storage, the sweep counts (with nu_coarse == nu_pre + nu_post) and the
+ * relaxation rule.  L: host array
  * of nprob device pointers to FP64 faces ([3][nz][ny][nx] of each problem).
  * Each problem gets its own hierarchy as in gmg_setup; device descriptor
  * tables let one launch cover the same step of every problem.  The caller

@@ -537,6 +537,8 @@ gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32
     if (!L[p]) return fail(GMG_EINVAL, "NULL L in batch");
     if (q.dtype != GMG_F64 || q.cycle_dtype != GMG_F32)
       return fail(GMG_EINVAL, "batch problems need dtype F64 and cycle_dtype F32");
+    if (q.smoother != GMG_SMOOTH_RBGS)
+      return fail(GMG_EINVAL, "the batched solve uses the red-black smoother only");
     if (q.l_storage != p0.l_storage || q.nu_pre != p0.nu_pre || q.nu_post != p0.nu_post ||
         q.nu_coarse != p0.nu_coarse || q.rollback != p0.rollback || q.omega0 != p0.omega0 ||
         q.omega_min != p0.omega_min || q.omega_max != p0.omega_max ||

@@ -24,6 +24,7 @@
 #include "gmg_kernels.h"
 #include "gmg_sweep.h"
 #include "gmg_tail.h"
+#include "gmg_walk.h"
 
 using namespace gmg;
 
@@ -56,56 +57,14 @@ static gmg_status fail(gmg_status s, const std::string& msg) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Walk column (i, j) over the z-planes [k0, k1) and call f(idx, ax, D) for
-// each cell with ax = (A x)(cell) and D its diagonal, computed with the same
-// arithmetic, term by term, as stencil_Ax.  The x and y neighbour offsets are
-// fixed for the column, and the z-neighbours and z-faces roll through
-// registers as the walk goes up.
+// Walk column (i, j) of x over the z-planes [k0, k1), calling f(idx, ax, D)
+// per cell (gmg_walk.h).
 template <typename T, typename TL, typename F>
 __device__ __forceinline__ void walk_column(const Geom& g, const T* __restrict__ x,
                                             const TL* __restrict__ L, int i, int j, int k0, int k1,
                                             F&& f) {
-  if (i >= g.nx || j >= g.ny || k0 >= k1) return;
-  const Nb nx = neighbours(i, g.nx, g.px, 1);
-  const Nb ny = neighbours(j, g.ny, g.py, g.sy);
-  const TL* __restrict__ Ly = L + g.n;
-  const TL* __restrict__ Lz = L + 2 * g.n;
-  const long long base = (long long)j * g.sy + i;
-  const long long top = (long long)(g.nz - 1) * g.sz;
-  long long idx = (long long)k0 * g.sz + base;
-  T xc = x[idx];
-  T xb = (k0 > 0) ? x[idx - g.sz] : (g.pz ? x[top + base] : xc);  // z low neighbour
-  T lzm = ldL<T>(Lz, idx);
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k, idx += g.sz) {
-    // z high neighbour and face: next plane, wrap, or (wall) self with face 0
-    const bool zin = k + 1 < g.nz;
-    const long long hi = zin ? idx + g.sz : base;
-    const T xt = (zin || g.pz) ? x[hi] : xc;
-    const T lzp = (zin || g.pz) ? ldL<T>(Lz, hi) : T(0);
-    T ax = T(0), s = T(0);
-    {
-      const T lm = ldL<T>(L, idx);
-      const T lp = nx.hi_ok ? ldL<T>(L, idx + nx.hi) : T(0);
-      ax += lp * (x[idx + nx.hi] - xc);
-      ax += lm * (x[idx + nx.lo] - xc);
-      s += lm + lp;
-    }
-    {
-      const T lm = ldL<T>(Ly, idx);
-      const T lp = ny.hi_ok ? ldL<T>(Ly, idx + ny.hi) : T(0);
-      ax += lp * (x[idx + ny.hi] - xc);
-      ax += lm * (x[idx + ny.lo] - xc);
-      s += lm + lp;
-    }
-    ax += lzp * (xt - xc);
-    ax += lzm * (xb - xc);
-    s += lzm + lzp;
-    f(idx, ax, -s);
-    xb = xc;
-    xc = xt;
-    lzm = lzp;
-  }
+  walk_column_v<T, TL>(g, [&](long long q) { return x[q]; }, L, i, j, k0, k1,
+                       [&](long long idx, T ax, T D, T) { f(idx, ax, D); });
 }
 
 // r = sigma - A x on active cells (0 elsewhere) for column (i, j) over the
@@ -489,6 +448,8 @@ __global__ __launch_bounds__(BT) void k_ir_update(Geom g, double* __restrict__ x
   }
 }
 
+#include "gmg_pcg.h"
+
 // ---------------------------------------------------------------------------
 // Handle
 // ---------------------------------------------------------------------------
@@ -585,6 +546,13 @@ struct gmg_handle {
   CapturedSeq irs;   // one outer step of gmg_solve_ir
   int ir_inner;      // max_inner / inner_rtol recorded in irs
   double ir_inner_rtol;
+  // conjugate gradient (gmg_pcg on level 0; the PCG smoother on every level):
+  // r, z, two direction buffers, q = B p and s = diag(-A) per level, in the
+  // cycle precision, allocated on first use; one PCGState per level
+  void* pcg[kMaxLevels][6];
+  PCGState* pst;
+  PCGState* hpst;    // pinned host mirror of level 0's state
+  CapturedSeq pcgit; // one iteration of gmg_pcg
 };
 
 static const dim3 kBlock(BX, BY, 1);
@@ -662,6 +630,74 @@ static long long tail_bytes(const gmg_handle* h, int lt) {
   return b;
 }
 
+// Work vectors (r, z, two direction buffers, q, s = diag(-A)) and state of
+// the conjugate gradient on levels [0, nl), allocated on first use; s is
+// computed once from the level's faces.
+template <typename T, typename TL>
+static gmg_status ensure_pcg(gmg_handle* h, int nl) {
+  if (!h->pst) {
+    HIP_TRY(hipMalloc(&h->pst, kMaxLevels * sizeof(PCGState)));
+    HIP_TRY(hipMemsetAsync(h->pst, 0, kMaxLevels * sizeof(PCGState), h->s));
+    HIP_TRY(hipHostMalloc((void**)&h->hpst, sizeof(PCGState), hipHostMallocDefault));
+  }
+  for (int l = 0; l < nl; ++l) {
+    if (h->pcg[l][0]) continue;
+    const Level& lv = h->lev[l];
+    for (int b = 0; b < 6; ++b) HIP_TRY(hipMalloc(&h->pcg[l][b], lv.g.n * sizeof(T)));
+    hipLaunchKernelGGL((k_pcg_diag<T, TL>), cell_grid(lv.g), kBlock, 0, h->s, lv.g,
+                       (const TL*)lv.L, (T*)h->pcg[l][5]);
+    HIP_TRY(hipGetLastError());
+  }
+  return GMG_OK;
+}
+
+// Start of a PCG run on level l from X[rs]: r, z, p and the run's state.
+template <typename T, typename TL>
+static void enq_pcg_start(gmg_handle* h, int l, const Roles<T>& X, int rs, const T* sigma,
+                          double rtol, int max_it, const int* done) {
+  const Level& lv = h->lev[l];
+  const dim3 gr = red_grid(lv.g);
+  T* const* b = (T* const*)h->pcg[l];
+  hipLaunchKernelGGL((k_pcg_start<T, TL>), gr, kBlock, 0, h->s, lv.g, X, rs, sigma,
+                     (const TL*)lv.L, (const T*)b[5], b[0], b[1], b[2], h->partials,
+                     h->partials + h->maxpart, kResChunk, done);
+  hipLaunchKernelGGL(k_pcg_begin, dim3(1), dim3(256), 0, h->s, h->pst + l, h->partials,
+                     h->partials + h->maxpart, nblocks(gr), rtol, max_it, done);
+}
+
+// One PCG iteration on level l: X[dst] = X[src] + alpha p.  The direction
+// buffers alternate with the iteration's parity (the first iteration of a
+// run is even).
+template <typename T, typename TL>
+static void enq_pcg_iter(gmg_handle* h, int l, const Roles<T>& X, int src, int dst, int parity,
+                         const int* done) {
+  const Level& lv = h->lev[l];
+  const dim3 gr = red_grid(lv.g);
+  const long long np = nblocks(gr);
+  T* const* b = (T* const*)h->pcg[l];
+  PCGState* st = h->pst + l;
+  hipLaunchKernelGGL((k_pcg_pq<T, TL>), gr, kBlock, 0, h->s, lv.g, (const T*)b[1],
+                     (const T*)b[2 + parity], b[3 - parity], b[4], (const TL*)lv.L, st,
+                     h->partials, kResChunk, done);
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, h->s, st, h->partials, np, done);
+  hipLaunchKernelGGL((k_pcg_xr<T>), gr, kBlock, 0, h->s, lv.g, X, src, dst, (const T*)b[3 - parity],
+                     b[0], b[1], (const T*)b[4], (const T*)b[5], st, h->partials,
+                     h->partials + h->maxpart, kResChunk, done);
+  hipLaunchKernelGGL(k_pcg_next, dim3(1), dim3(256), 0, h->s, st, h->partials,
+                     h->partials + h->maxpart, np, done);
+}
+
+// The PCG smoother: `iters` iterations restarted from X[rs], result in X[rd]
+// (X[rs] itself when iters == 0).  Returns the role of the result.
+template <typename T, typename TL>
+static int enq_pcg_smooth(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd,
+                          const T* sigma, int iters, const int* done) {
+  if (iters <= 0) return rs;
+  enq_pcg_start<T, TL>(h, l, X, rs, sigma, 0.0, iters, done);
+  for (int it = 0; it < iters; ++it) enq_pcg_iter<T, TL>(h, l, X, it == 0 ? rs : rd, rd, it & 1, done);
+  return rd;
+}
+
 // Levels lt .. nlev-1 in one single-workgroup launch (gmg_tail.h).
 template <typename T, typename TL>
 static void enq_tail(gmg_handle* h, int lt, const int* done) {
@@ -698,6 +734,7 @@ static void enq_tail(gmg_handle* h, int lt, const int* done) {
 // level count (nlev: no tail).  Also lifts the kernel's dynamic-LDS limit.
 template <typename T, typename TL>
 static int plan_tail(gmg_handle* h) {
+  if (h->p.smoother == GMG_SMOOTH_PCG) return h->nlev;
   for (int l = 1; l < h->nlev; ++l) {
     if (h->lev[l].g.n > h->p.tail_cells || h->nlev - l > kTailMax ||
         tail_bytes<T, TL>(h, l) > kTailLds)
@@ -718,6 +755,7 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
   const gmg_params& p = h->p;
   int role[kMaxLevels];
   const int lt = h->tail;  // levels lt .. nl-1 run in one k_tail launch
+  const bool pcg = p.smoother == GMG_SMOOTH_PCG;
   // descend: pre-smooth, then restrict the residual (coarse x starts at 0)
   for (int l = 0; l < lt; ++l) {
     const Roles<T> X = level_roles<T>(h, l, X0, sel);
@@ -725,10 +763,14 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     const bool coarsest = (l == nl - 1);
     int r = 0;
     const int nsw = coarsest ? p.nu_coarse : p.nu_pre;
-    for (int s = 0; s < nsw; ++s) {
-      const int rd = next_role(l, r);
-      enq_sweep<T, TL>(h, l, X, r, rd, sg, nullptr, done);
-      r = rd;
+    if (pcg) {
+      r = enq_pcg_smooth<T, TL>(h, l, X, r, next_role(l, r), sg, nsw, done);
+    } else {
+      for (int s = 0; s < nsw; ++s) {
+        const int rd = next_role(l, r);
+        enq_sweep<T, TL>(h, l, X, r, rd, sg, nullptr, done);
+        r = rd;
+      }
     }
     role[l] = r;
     if (coarsest) break;
@@ -746,7 +788,7 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     const Level& lv = h->lev[l];
     const T* xc = (const T*)h->lev[l + 1].x[role[l + 1]];
     int r = role[l];
-    if (p.nu_post > 0) {
+    if (p.nu_post > 0 && !pcg) {
       for (int s = 0; s < p.nu_post; ++s) {
         const int rd = next_role(l, r);
         enq_sweep<T, TL>(h, l, X, r, rd, sg, s == 0 ? xc : nullptr, done);
@@ -758,6 +800,7 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
       hipLaunchKernelGGL((k_prolong<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, X, r, rd,
                          lv.active, xc, lc.g, lv.c[0], lv.c[1], lv.c[2], done);
       r = rd;
+      if (pcg) r = enq_pcg_smooth<T, TL>(h, l, X, r, next_role(l, r), sg, p.nu_post, done);
     }
     role[l] = r;
   }
@@ -827,6 +870,9 @@ static gmg_status validate(const gmg_params* p) {
     return fail(GMG_EINVAL, "bad sweep counts");
   if (p->tail_cells < 0 || p->tail_cells > kTailMaxCells)
     return fail(GMG_EINVAL, "tail_cells must be in [0, 32768]");
+  if (p->smoother != GMG_SMOOTH_RBGS && p->smoother != GMG_SMOOTH_PCG)
+    return fail(GMG_EINVAL, "smoother must be GMG_SMOOTH_RBGS or GMG_SMOOTH_PCG");
+  if (p->reserved != 0) return fail(GMG_EINVAL, "reserved must be 0");
   if (!(p->omega0 > 0) || !(p->omega_min > 0) || !(p->omega_max >= p->omega_min) ||
       !(p->theta_dec > 0) || !(p->theta_inc > 0) || !std::isfinite(p->omega_max) ||
       !std::isfinite(p->omega0) || !std::isfinite(p->theta_inc))
@@ -856,6 +902,11 @@ static void free_handle(gmg_handle* h) {
   (void)hipFree(h->e32);
   if (h->cyc.exec) (void)hipGraphExecDestroy(h->cyc.exec);
   if (h->irs.exec) (void)hipGraphExecDestroy(h->irs.exec);
+  if (h->pcgit.exec) (void)hipGraphExecDestroy(h->pcgit.exec);
+  for (int l = 0; l < kMaxLevels; ++l)
+    for (int b = 0; b < 6; ++b) (void)hipFree(h->pcg[l][b]);
+  (void)hipFree(h->pst);
+  if (h->hpst) (void)hipHostFree(h->hpst);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
 }
@@ -885,7 +936,10 @@ static void enq_build_levels(gmg_handle* h) {
 static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, gmg_handle* h) {
   h->p = *p;
   h->s = (hipStream_t)stream;
-  h->rule = OmegaRule{p->omega_min, p->omega_max, p->theta_dec, p->theta_inc, p->rollback};
+  // the PCG smoother has no relaxation factor, so a rejected cycle would
+  // repeat identically: every cycle is accepted
+  h->rule = OmegaRule{p->omega_min, p->omega_max, p->theta_dec, p->theta_inc,
+                      p->smoother == GMG_SMOOTH_PCG ? 0 : p->rollback};
   // level plan (Sec. 3.2)
   int n[3] = {p->n[0], p->n[1], p->n[2]};
   int nl = 0;
@@ -966,6 +1020,7 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
   else enq_build_levels<float>(h);
   HIP_TRY(hipGetLastError());
   DISPATCH_CYCLE(h, { h->tail = plan_tail<T, TL>(h); });
+  if (p->smoother == GMG_SMOOTH_PCG) DISPATCH_CYCLE(h, { GMG_TRY((ensure_pcg<T, TL>(h, h->nlev))); });
   HIP_TRY(hipStreamSynchronize(h->s));
   return GMG_OK;
 }
@@ -1059,7 +1114,8 @@ static gmg_status ir_outer_step(gmg_handle* h, double* x, const double* sigma, i
 static gmg_status drop_graphs(gmg_handle* h) {
   if (h->cyc.exec) HIP_TRY(hipGraphExecDestroy(h->cyc.exec));
   if (h->irs.exec) HIP_TRY(hipGraphExecDestroy(h->irs.exec));
-  h->cyc.exec = h->irs.exec = nullptr;
+  if (h->pcgit.exec) HIP_TRY(hipGraphExecDestroy(h->pcgit.exec));
+  h->cyc.exec = h->irs.exec = h->pcgit.exec = nullptr;
   return GMG_OK;
 }
 
@@ -1315,6 +1371,64 @@ gmg_status gmg_vcycle(gmg_handle* h, void* x, const void* sigma, double* rnorm_a
   HIP_TRY(hipGetLastError());
   if (rnorm_after) return gmg_residual(h, x, sigma, nullptr, rnorm_after, nullptr);
   return GMG_OK;
+}
+
+gmg_status gmg_pcg(gmg_handle* h, void* x, const void* sigma, double rtol, int32_t max_iter,
+                   gmg_pcg_info* info) {
+  if (!h || !x || !sigma) return fail(GMG_EINVAL, "NULL argument");
+  if (h->p.dtype != h->p.cycle_dtype) return fail(GMG_EINVAL, "gmg_pcg needs dtype == cycle_dtype");
+  if (!(rtol >= 0) || max_iter < 0) return fail(GMG_EINVAL, "bad rtol / max_iter");
+  const Level& lv = h->lev[0];
+  const long long np = nblocks(red_grid(lv.g));
+  DISPATCH_CYCLE(h, {
+    GMG_TRY((ensure_pcg<T, TL>(h, 1)));
+    T* xa = (T*)x;
+    const Roles<T> X{{xa, xa, xa}, nullptr};
+    const int* done = &h->pst->done;
+    hipLaunchKernelGGL((k_masked_sumsq<T>), red_grid(lv.g), kBlock, 0, h->s, lv.g,
+                       (const T*)sigma, lv.active, h->partials, kResChunk);
+    hipLaunchKernelGGL(k_pcg_snorm, dim3(1), dim3(256), 0, h->s, h->pst, h->partials, np);
+    enq_pcg_start<T, TL>(h, 0, X, 0, (const T*)sigma, rtol, max_iter, nullptr);
+    HIP_TRY(hipGetLastError());
+    // iterations in pairs (even, odd), so that every replay starts on an
+    // even iteration; kernels after the stopping test are no-ops
+    auto pair = [&]() -> gmg_status {
+      enq_pcg_iter<T, TL>(h, 0, X, 0, 0, 0, done);
+      enq_pcg_iter<T, TL>(h, 0, X, 0, 0, 1, done);
+      HIP_TRY(hipGetLastError());
+      return GMG_OK;
+    };
+    int launched = 0, chunk = 8;
+    while (true) {
+      HIP_TRY(hipMemcpyAsync(h->hpst, h->pst, offsetof(PCGState, hist), hipMemcpyDeviceToHost,
+                             h->s));
+      HIP_TRY(hipStreamSynchronize(h->s));
+      if (h->hpst->done || launched >= max_iter) break;
+      const int pairs = std::max(1, std::min(chunk, (max_iter - launched + 1) / 2));
+      if (h->p.graphs) {
+        hipGraphExec_t ex = nullptr;
+        GMG_TRY(captured(h, h->pcgit, xa, sigma, pair, &ex));
+        for (int c = 0; c < pairs; ++c) HIP_TRY(hipGraphLaunch(ex, h->s));
+      } else {
+        for (int c = 0; c < pairs; ++c) GMG_TRY(pair());
+      }
+      launched += 2 * pairs;
+      chunk = std::min(2 * chunk, 128);
+    }
+    HIP_TRY(hipMemcpyAsync(h->hpst, h->pst, sizeof(PCGState), hipMemcpyDeviceToHost, h->s));
+    HIP_TRY(hipStreamSynchronize(h->s));
+  });
+  const PCGState& s = *h->hpst;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = s.status;
+    info->iterations = s.it;
+    info->snorm = s.snorm;
+    info->rnorm0 = s.rnorm0;
+    info->rnorm = s.rnorm;
+    for (int k = 0; k < std::min(s.it, GMG_MAX_HISTORY); ++k) info->history[k] = s.hist[k];
+  }
+  return s.status == GMG_OK ? GMG_OK : fail(GMG_ENOCONV, "PCG did not reach the tolerance");
 }
 
 gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int32_t max_cycles,

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 GMG_OK, GMG_EINVAL, GMG_ESHAPE, GMG_ENOMEM, GMG_EHIP, GMG_ENOCONV = range(6)
 GMG_F32, GMG_F64, GMG_BF16 = 0, 1, 2
+GMG_SMOOTH_RBGS, GMG_SMOOTH_PCG = 0, 1
 GMG_MAX_HISTORY = 512
 STATUS_NAMES = {0: "GMG_OK", 1: "GMG_EINVAL", 2: "GMG_ESHAPE", 3: "GMG_ENOMEM",
                 4: "GMG_EHIP", 5: "GMG_ENOCONV"}
@@ -31,6 +32,7 @@ class gmg_params(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("nu_coarse", ctypes.c_int32), ("rollback", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
+                ("smoother", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
                 ("theta_inc", ctypes.c_double)]
@@ -44,6 +46,12 @@ class gmg_solve_info(ctypes.Structure):
                 ("history", ctypes.c_double * GMG_MAX_HISTORY),
                 ("omegas", ctypes.c_double * GMG_MAX_HISTORY),
                 ("accepted", ctypes.c_int32 * GMG_MAX_HISTORY)]
+
+
+class gmg_pcg_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("snorm", ctypes.c_double), ("rnorm0", ctypes.c_double),
+                ("rnorm", ctypes.c_double), ("history", ctypes.c_double * GMG_MAX_HISTORY)]
 
 
 class gmg_ir_info(ctypes.Structure):
@@ -97,6 +105,8 @@ _SIGS = [
     ("gmg_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_double, ctypes.c_int32,
                                  ctypes.POINTER(gmg_solve_info)]),
+    ("gmg_pcg", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_double, ctypes.c_int32, ctypes.POINTER(gmg_pcg_info)]),
     ("gmg_solve_ir", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_double, ctypes.POINTER(gmg_ir_info)]),
@@ -303,6 +313,20 @@ def gmg_solve(h, x, sigma, rtol, max_cycles, raise_noconv=False):
     if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
         _check(st)
     return info_dict(info)
+
+
+def gmg_pcg(h, x, sigma, rtol, max_iter, raise_noconv=False):
+    """Jacobi-preconditioned conjugate gradient on level 0 of the handle, in
+    place on x.  Returns dict(status, iterations, snorm, rnorm0, rnorm,
+    history)."""
+    info = gmg_pcg_info()
+    st = load().gmg_pcg(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), float(rtol), int(max_iter),
+                        ctypes.byref(info))
+    if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
+        _check(st)
+    n = min(info.iterations, GMG_MAX_HISTORY)
+    return dict(status=STATUS_NAMES[info.status], iterations=info.iterations, snorm=info.snorm,
+                rnorm0=info.rnorm0, rnorm=info.rnorm, history=list(info.history[:n]))
 
 
 def gmg_solve_ir(h, x, sigma, rtol=1e-10, max_outer=50, max_inner=8, inner_rtol=1e-4,

@@ -1,0 +1,149 @@
+"""GPU parity of the comparison solvers against the CPU oracle, through the C
+ABI: the Jacobi-preconditioned conjugate gradient (gmg_pcg) iterate by
+iterate and to a tolerance, and GMG with the PCG smoother (one V-cycle and
+the solve), FP64 and FP32, walls and periodic directions, inactive cells and
+ragged tiles."""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import gmg_oracle as O
+from oracle import pcg_oracle as PO
+from paper_2607_07687_amd import gmg as G
+from paper_2607_07687_amd import problems as P
+from tests.gpu_util import TOL, dev, host, rel, require_gpu, rounded, say, torch
+from tests.test_gpu_parity import build, rounding_floor
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("walls_ragged", (70, 9, 5), (False, False, False), 2.0, 0.1),
+    ("periodic_tiles", (132, 6, 8), (True, True, True), 1.0, 0.05),
+    ("mixed", (20, 20, 8), (True, False, False), 3.0, 0.15),
+]
+
+
+def case_inputs(case):
+    name, n, per, contrast, holes = case
+    return P.random_problem(n, per, seed=zlib.crc32(name.encode()) % 1000, contrast=contrast,
+                            holes=holes)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+def test_pcg_iterates_match_oracle(case, prec):
+    L, s, per = case_inputs(case)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, prec)
+    x0 = rounded(np.random.default_rng(4).standard_normal(s.shape), prec)
+    for k in (1, 3, 7):
+        xd = dev(x0, prec)
+        info = G.gmg_pcg(h, xd, sd, 0.0, k)
+        ref = PO.pcg(x0, s64, L64, per, k)
+        e = rel(host(xd), ref["x"])
+        say(f"{case[0]} {prec} k={k}: rel {e:.2e}")
+        assert info["iterations"] == k
+        assert e <= TOL[prec]
+        hist = np.array(info["history"])
+        want = np.array(ref["history"])
+        assert np.all(np.abs(hist - want) <= TOL[prec] * np.maximum(want, 1e-300) + 1e-12)
+    h.close()
+
+
+@pytest.mark.parametrize("prec,rtol", [("f64", 1e-9), ("f32", 1e-5)])
+def test_pcg_solve_to_tolerance(prec, rtol):
+    L, s, per = P.sphere_box((48, 24, 16), (20.0, 12.0, 8.0), 5.0, "uniform", 9)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, prec)
+    xd = torch.zeros_like(sd)
+    info = G.gmg_pcg(h, xd, sd, rtol, 2000)
+    ref = PO.pcg_solve(L64, per, np.zeros_like(s64), s64, rtol, 2000)
+    say(f"PCG {prec}: {info['iterations']} iterations (oracle {ref['iterations']})")
+    assert info["status"] == "GMG_OK" and ref["status"] == "ok"
+    slack = 1 if prec == "f64" else max(2, ref["iterations"] // 10)
+    assert abs(info["iterations"] - ref["iterations"]) <= slack
+    if prec == "f64":  # same iterates up to rounding
+        act = levels[0]["active"]
+        d = host(xd) - ref["x"]
+        d = d[act] - d[act].mean()  # walls: defined up to a constant
+        assert np.linalg.norm(d) <= 1e-8 * np.linalg.norm(ref["x"][act])
+    # FP32: two solutions at residual rtol may differ by up to cond(A) * rtol,
+    # so the check is the true residual of the GPU result itself
+    true = O.norm2(O.residual(host(xd), s64, L64, per)) / ref["snorm"]
+    assert true <= 5 * rtol
+    h.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gmg_pcg_vcycle_matches_oracle(prec):
+    L, s, per = P.sphere_box((48, 24, 16), (20.0, 12.0, 8.0), 5.0, "uniform", 9)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, prec, smoother=G.GMG_SMOOTH_PCG)
+    xd = torch.zeros_like(sd)
+    G.gmg_vcycle(h, xd, sd)
+    xo = PO.vcycle_pcg(levels, np.zeros_like(s64), s64)
+    e = rel(host(xd), xo)
+    say(f"GMG-PCG V-cycle {prec}: rel {e:.2e}")
+    assert e <= TOL[prec]
+    h.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+def test_gmg_pcg_vcycle_small_cases(case):
+    L, s, per = case_inputs(case)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f64", smoother=G.GMG_SMOOTH_PCG,
+                                        nu_pre=1, nu_post=3, nu_coarse=5)
+    xd = torch.zeros_like(sd)
+    G.gmg_vcycle(h, xd, sd)
+    xo = PO.vcycle_pcg(levels, np.zeros_like(s64), s64, 1, 3, 5)
+    assert rel(host(xd), xo) <= TOL["f64"]
+    h.close()
+
+
+def test_gmg_pcg_solve_matches_oracle():
+    L, s, per = P.sphere_box((48, 24, 16), (20.0, 12.0, 8.0), 5.0, "uniform", 9)
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f64", smoother=G.GMG_SMOOTH_PCG)
+    xd = torch.zeros_like(sd)
+    info = G.gmg_solve(h, xd, sd, 1e-8, 100)
+    ref = PO.solve_gmg_pcg(levels, np.zeros_like(s64), s64, 1e-8, 100)
+    say(f"GMG-PCG solve: {info['cycles']} cycles (oracle {ref['cycles']})")
+    assert info["status"] == "GMG_OK" and ref["status"] == "ok"
+    assert info["cycles"] == ref["cycles"]
+    assert info["accepted_cycles"] == info["cycles"]  # no rollback with the PCG smoother
+    # per-cycle tolerance plus the rounding floor of evaluating the residual
+    floor = rounding_floor(levels, ref, "f64")
+    for hg, ho in zip(info["history"], ref["history"]):
+        assert abs(hg - ho) <= TOL["f64"] * ho + floor
+    assert rel(host(xd), ref["x"]) <= 1e-9
+    h.close()
+
+
+def test_pcg_graph_replays_match_direct_launches():
+    L, s, per = P.sphere_box((64, 32, 32), (30.0, 16.0, 16.0), 6.0, "uniform", 4)
+    hg, Ld, sd, levels, L64, s64 = build(L, s, per, "f32")
+    he = G.gmg_setup(G.gmg_default_params((64, 32, 32), per, G.GMG_F32, graphs=0), Ld)
+    outs = []
+    for h in (hg, he, hg):
+        x = torch.zeros_like(sd)
+        info = G.gmg_pcg(h, x, sd, 1e-5, 1000)
+        torch.cuda.synchronize()
+        outs.append((x.clone(), info))
+    for x, info in outs[1:]:
+        assert torch.equal(x, outs[0][0])
+        assert info["history"] == outs[0][1]["history"]
+    hg.close()
+    he.close()
+
+
+def test_pcg_errors():
+    require_gpu()
+    L = torch.ones((3, 8, 8, 8), dtype=torch.float64, device="cuda")
+    p = G.gmg_default_params((8, 8, 8), (False,) * 3, G.GMG_F64, cycle_dtype=G.GMG_F32)
+    h = G.gmg_setup(p, L)
+    x = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(G.GMGError) as e:
+        G.gmg_pcg(h, x, x, 1e-6, 10)  # mixed precision handle: use gmg_solve_ir
+    assert e.value.status == G.GMG_EINVAL
+    h.close()
+    for bad in (dict(smoother=2), dict(reserved=1)):
+        with pytest.raises(G.GMGError) as e:
+            G.gmg_setup(G.gmg_default_params((8, 8, 8), (False,) * 3, **bad), L.float())
+        assert e.value.status == G.GMG_EINVAL
