@@ -174,14 +174,17 @@ def level_plan(n, periodic, anisotropic=True, min_coarse=4, max_levels=0):
     None on the coarsest) for every level."""
     plan = []
     n = tuple(int(v) for v in n)
+    # the problem's dimensions: a direction of extent 1 (a 2-D problem) is
+    # not one, and isotropic coarsening leaves it alone
+    dims = [d for d in range(3) if n[d] > 1]
     while True:
         ok = [can_coarsen(n[d], periodic[d], min_coarse) for d in range(3)]
         if anisotropic:
             c = tuple(2 if ok[d] else 1 for d in range(3))
             stop = not any(ok)
         else:
-            c = (2, 2, 2)
-            stop = not all(ok)
+            c = tuple(2 if d in dims else 1 for d in range(3))
+            stop = not dims or not all(ok[d] for d in dims)
         if max_levels and len(plan) + 1 >= max_levels:
             stop = True
         if stop:

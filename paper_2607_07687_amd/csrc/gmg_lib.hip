@@ -954,8 +954,19 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
       for (int d = 0; d < 3; ++d) c[d] = ok[d] ? 2 : 1;
       stop = !(ok[0] || ok[1] || ok[2]);
     } else {
-      c[0] = c[1] = c[2] = 2;
-      stop = !(ok[0] && ok[1] && ok[2]);
+      // every dimension of the problem together; a direction of extent 1 on
+      // the finest grid (2-D problems) is not a dimension and keeps factor 1
+      stop = true;
+      bool all_ok = true;
+      for (int d = 0; d < 3; ++d) {
+        const bool dim = p->n[d] > 1;
+        c[d] = dim ? 2 : 1;
+        if (dim) {
+          stop = false;
+          all_ok = all_ok && ok[d];
+        }
+      }
+      stop = stop || !all_ok;
     }
     if ((p->max_levels && nl + 1 >= p->max_levels) || nl + 1 >= kMaxLevels) stop = true;
     ++nl;
