@@ -163,6 +163,44 @@ def solver_comparison(rtol=1e-6, reps=3):
     return out
 
 
+def coarsening_sweep(m=64, aspects=(1, 2, 4, 8), rtol=1e-8, max_cycles=3000):
+    """Anisotropic against isotropic coarsening on impulsive-start problems
+    (unit inflow along x past a 2-D cylinder, a spanwise-periodic cylinder
+    and a sphere in boxes of aspect ratio N = aspect x 1 x 1): FP64 V(2,2)
+    cycles from x = 0 to rtol, and the wall time of each solve."""
+    import torch
+    from paper_2607_07687_amd import gmg as G
+    from paper_2607_07687_amd import problems as P
+    out = {}
+    for kind in P.IMPULSIVE_KINDS:
+        for N in aspects:
+            L, s, per = P.impulsive_problem(kind, N, m)
+            n = (L.shape[3], L.shape[2], L.shape[1])
+            Ld = torch.from_numpy(L).cuda()
+            sd = torch.from_numpy(s).cuda()
+            del L, s
+            row = {"n": list(n)}
+            for aniso in (1, 0):
+                h = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F64, anisotropic=aniso), Ld)
+                x = torch.zeros_like(sd)
+                G.gmg_solve(h, x, sd, rtol, 1)  # capture the cycle graph
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = G.gmg_solve(h, x, sd, rtol, max_cycles)
+                torch.cuda.synchronize()
+                row["aniso" if aniso else "iso"] = {
+                    "levels": G.gmg_num_levels(h), "cycles": info["cycles"],
+                    "status": info["status"], "ms": 1e3 * (time.perf_counter() - t0)}
+                h.close()
+            row["cycle_ratio_iso_over_aniso"] = row["iso"]["cycles"] / max(1, row["aniso"]["cycles"])
+            out[f"{kind}_N{N}"] = row
+            log(f"{kind} N={N} {tuple(n)}: aniso {row['aniso']['cycles']} cycles "
+                f"({row['aniso']['levels']} levels), iso {row['iso']['cycles']} "
+                f"({row['iso']['levels']} levels)")
+    return out
+
+
 def extra_configs():
     """The other workloads, each on one GPU: the 32^3 periodic FP64 solve to
     1e-10, anisotropic vs isotropic coarsening on the 512 x 192 x 192 sphere
@@ -364,6 +402,7 @@ def main():
     if not args.no_extras:
         out["other_configs"] = extra_configs()
         out["other_configs"]["solver_table"] = solver_comparison()
+        out["other_configs"]["coarsening_sweep"] = coarsening_sweep()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

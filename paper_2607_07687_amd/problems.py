@@ -84,6 +84,50 @@ def sphere_faces(n, periodic, centre, radius):
     return zero_wall_faces(L, periodic)
 
 
+def body_faces(n, periodic, centre, radius, axis=None):
+    """L_d = mu0(dist - R) at every face centre, dist being the distance to
+    the point `centre` (sphere, axis None) or to the line through `centre`
+    along direction `axis` (cylinder); wall faces zeroed."""
+    L = np.empty((3, n[2], n[1], n[0]), dtype=np.float64)
+    for d in range(3):
+        P = face_centres(n, d)
+        r2 = 0.0
+        for e in range(3):
+            if e != axis:
+                r2 = r2 + (P[e] - centre[e]) ** 2
+        L[d] = mu0(np.sqrt(r2) - radius)
+    return zero_wall_faces(L, periodic)
+
+
+IMPULSIVE_KINDS = ("cylinder2d", "cylinder3d", "sphere")
+
+
+def impulsive_problem(kind, aspect, m):
+    """Impulsive start of the flow past a body (the three cases of the
+    anisotropic-coarsening study, Sec. 3.2): unit velocity along x on every
+    face, sigma its flux divergence through L with the mean removed; it is
+    nonzero on the body's band and on the walled inlet and outlet planes,
+    whose pressure difference is the low axial mode.
+      cylinder2d: aspect*m x m x 1, walls, cylinder along z;
+      cylinder3d: aspect*m x m x m/2, periodic in z (spanwise), cylinder along z;
+      sphere:     aspect*m x m x m, walls.
+    Body diameter m/4, centred at x = m/2 and mid-height.  Returns
+    (L, sigma, periodic)."""
+    if kind == "cylinder2d":
+        n, per, axis = (aspect * m, m, 1), (False, False, False), 2
+    elif kind == "cylinder3d":
+        n, per, axis = (aspect * m, m, m // 2), (False, False, True), 2
+    elif kind == "sphere":
+        n, per, axis = (aspect * m, m, m), (False, False, False), None
+    else:
+        raise ValueError(kind)
+    centre = (m / 2, n[1] / 2, n[2] / 2)
+    L = body_faces(n, per, centre, m / 8, axis)
+    u = np.zeros_like(L)
+    u[0] = 1.0
+    return L, rhs_from_velocity(L, u, per), per
+
+
 def touched_cells(L, periodic):
     """Cells with at least one nonzero face among their six (low faces L_d[I]
     and high faces L_d[I + e_d], the latter wrapping when periodic)."""

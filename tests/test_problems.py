@@ -7,6 +7,7 @@ all lie at least one cell inside the sphere."""
 import math
 
 import numpy as np
+import pytest
 
 from paper_2607_07687_amd import problems as P
 
@@ -75,3 +76,24 @@ def test_batch_specs_fit():
         assert 4.0 <= sp["radius"] <= 12.0
         for d in range(3):
             assert sp["radius"] + 3 <= sp["centre"][d] <= n[d] - sp["radius"] - 3
+
+
+@pytest.mark.parametrize("kind", P.IMPULSIVE_KINDS)
+def test_impulsive_rhs_inlet_outlet_and_mirror_symmetry(kind):
+    m = 16
+    L, s, per = P.impulsive_problem(kind, 4, m)
+    nz, ny, nx = s.shape
+    assert abs(s.sum()) <= 1e-12 * np.abs(s).sum()
+    # far from the body the unit inflow enters through the closed inlet wall
+    # and leaves through the outlet: +1 and -1 on those planes, 0 between
+    far = slice(2 * m, nx - 1)
+    assert np.allclose(s[..., 0], 1.0, atol=1e-12)
+    assert np.allclose(s[..., -1], -1.0, atol=1e-12)
+    assert np.allclose(s[..., far], 0.0, atol=1e-12)
+    # the body's band term L(x + 1/2) - L(x - 1/2) is odd under the x-mirror
+    # through the body centre (x = m/2) and even under the y and z mirrors
+    near = s[..., 1:m - 1]
+    assert np.allclose(near, -near[..., ::-1], atol=1e-12)
+    assert np.allclose(s, s[:, ::-1, :], atol=1e-12)
+    assert np.allclose(s, s[::-1, :, :], atol=1e-12)
+    assert np.abs(near).max() > 0.1  # the body is resolved
