@@ -99,7 +99,15 @@ typedef struct gmg_params {
                             comparison of Sec. 3 and Table 1); omega is then
                             unused, every cycle is accepted (no rollback) and
                             no single-workgroup tail is used                  */
-  int32_t reserved;      /* must be 0                                          */
+  int32_t deferred_norm; /* 0 (default): a separate norm kernel after every
+                            cycle of gmg_solve.  1: the norm of a cycle's
+                            result is taken by the next cycle's first sweep
+                            and the decision made there (a conditional sweep
+                            redoes it when omega changes otherwise): one
+                            level-0 pass less per cycle and one extra buffer.
+                            Same decisions and iterates either way.  Needs
+                            dtype == cycle_dtype, the red-black smoother,
+                            nu_pre >= 1 and two levels; otherwise 0 is used.  */
   double omega0;         /* relaxation factor at the start of a solve (1.0)   */
   double omega_min;      /* lower bound (0.1)                                 */
   double omega_max;      /* upper bound (1.0)                                 */

@@ -128,16 +128,19 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 __device__ __forceinline__ bool stopped(const int* done) { return done != nullptr && *done; }
 
-// Iterate buffers of a level by role.  Level 0 has three buffers whose roles
-// rotate on the device: role 0 is the accepted iterate, roles 1 and 2 are the
-// cycle's ping-pong work buffers; with a selector, buffer (*sel + role) % 3
-// plays `role`.  Coarse levels (and calls without a selector) use the
-// buffers directly by role.
+// Iterate buffers of a level by role.  Level 0 has three or four buffers
+// whose roles change on the device: role 0 is the accepted iterate, the
+// others are the cycle's work buffers.  With a selector, buffer
+// (*sel + role) % 3 plays `role` (three buffers); with a map, buffer
+// map[role] does (four buffers).  Coarse levels (and calls without either)
+// use the buffers directly by role.
 template <typename T>
 struct Roles {
-  T* p[3];
+  T* p[4];
   const int* sel;
+  const int* map;
   __device__ __forceinline__ T* get(int role) const {
+    if (map != nullptr) return p[map[role]];
     const int base = (sel != nullptr) ? *sel : 0;
     return p[(base + role) % 3];
   }

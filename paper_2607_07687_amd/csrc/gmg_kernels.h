@@ -21,7 +21,14 @@ struct SolveState {
   int cur;         // 0: accepted iterate in buffer A, 1: in buffer B
   int done;        // 1 once converged or out of cycles
   int cycles, accepted, max_cycles, status;
-  int pad0, pad1;
+  // deferred decision (gmg_solve): the norm of a cycle's result is taken by
+  // the next cycle's first sweep, whose output is redone when the decision
+  // changes omega; level-0 roles through map (0 accepted, 1 candidate,
+  // 2 and 3 work)
+  int map[4];
+  int pending;     // a candidate awaits its decision
+  int redo;        // the speculative first sweep must be redone
+  double omega_spec;  // omega of the next cycle if the candidate is accepted
   double scr[4];   // scratch for one-off reductions (gmg_residual)
   double hist[GMG_MAX_HISTORY];
   double omegas[GMG_MAX_HISTORY];

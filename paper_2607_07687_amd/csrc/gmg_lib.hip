@@ -297,6 +297,12 @@ __global__ __launch_bounds__(256) void k_solve_init(const double* pa, long long 
     st->cycles = 0;
     st->accepted = 0;
     st->max_cycles = max_cycles;
+    st->map[0] = st->map[1] = 0;  // the first pass reads x0 itself as its input
+    st->map[2] = 1;
+    st->map[3] = 2;
+    st->pending = 0;
+    st->redo = 0;
+    st->omega_spec = omega0;
     const bool conv = (st->snorm == 0.0) || (st->rho <= rtol * st->snorm);
     st->status = conv ? 0 : 5;
     st->done = (conv || max_cycles <= 0) ? 1 : 0;
@@ -336,6 +342,60 @@ __global__ __launch_bounds__(256) void k_cycle_finish(const double* p, long long
     if (c < GMG_MAX_HISTORY) st->acc[c] = 1;
   }
   st->cycles = c + 1;
+  const bool conv = st->rho <= st->rtol * st->snorm;
+  if (conv) st->status = 0;
+  if (conv || st->cycles >= st->max_cycles) st->done = 1;
+}
+
+// Deferred decision of gmg_solve, after the first sweep of a cycle has taken
+// the norm of its input, the previous cycle's result (the candidate, role 1)
+// and speculatively swept it with the omega that acceptance would give.
+// Same rule as k_cycle_finish: growth lowers omega (and, with rollback,
+// discards the candidate), decay accepts it (map roles 0 and 1 swap) and
+// raises omega.  Whenever omega did not come out as assumed, `redo` asks for
+// the first sweep again from the accepted iterate.  The first pass of a
+// solve has no candidate: it only points role 1 at the fourth buffer.
+__global__ __launch_bounds__(256) void k_spec_finish(const double* p, long long n, SolveState* st,
+                                                     OmegaRule rule) {
+  if (st->done) return;
+  const double rr = reduce_partials(p, n);
+  if (threadIdx.x != 0) return;
+  if (!st->pending) {
+    st->pending = 1;
+    st->map[1] = 3;
+    st->redo = 0;
+    st->omega_spec = fmin(rule.omega_max, rule.theta_inc * st->omega);
+    return;
+  }
+  const double rn = sqrt(rr);
+  const int c = st->cycles;
+  if (c < GMG_MAX_HISTORY) {
+    st->hist[c] = (st->snorm > 0.0) ? rn / st->snorm : 0.0;
+    st->omegas[c] = st->omega;
+  }
+  st->last = rn;
+  if (rn > st->rho) {  // growth
+    st->omega = fmax(rule.omega_min, rule.theta_dec * st->omega);
+    if (c < GMG_MAX_HISTORY) st->acc[c] = rule.rollback ? 0 : 1;
+    if (!rule.rollback) {
+      const int a = st->map[0];
+      st->map[0] = st->map[1];
+      st->map[1] = a;
+      st->rho = rn;
+    }
+    st->redo = 1;
+  } else {  // decay (or a tie)
+    const int a = st->map[0];
+    st->map[0] = st->map[1];
+    st->map[1] = a;
+    st->rho = rn;
+    st->omega = fmin(rule.omega_max, rule.theta_inc * st->omega);
+    st->accepted += 1;
+    if (c < GMG_MAX_HISTORY) st->acc[c] = 1;
+    st->redo = (st->omega != st->omega_spec) ? 1 : 0;
+  }
+  st->cycles = c + 1;
+  st->omega_spec = fmin(rule.omega_max, rule.theta_inc * st->omega);
   const bool conv = st->rho <= st->rtol * st->snorm;
   if (conv) st->status = 0;
   if (conv || st->cycles >= st->max_cycles) st->done = 1;
@@ -528,7 +588,8 @@ struct gmg_handle {
   Level lev[kMaxLevels];
   int tail;      // first level cycled by k_tail (nlev: none)
   void* L0x;     // exact FP64 level-0 faces (dtype F64 with F32 cycles)
-  void* w[2];    // level-0 work iterates (cycle dtype); the caller's x is the third
+  void* w[3];    // level-0 work iterates (cycle dtype); the caller's x is the fourth
+  double* spec_part;  // first-sweep residual partials of the deferred decision
   double* partials;  // 2 * maxpart
   long long maxpart;
   SolveState* st;
@@ -563,7 +624,7 @@ static const dim3 kBlock(BX, BY, 1);
 
 template <typename T>
 static Roles<T> level_roles(gmg_handle* h, int l, T* x0, const int* sel) {
-  Roles<T> R;
+  Roles<T> R{};
   if (l == 0) {
     R.p[0] = x0;
     R.p[1] = (T*)h->w[0];
@@ -582,9 +643,17 @@ static Roles<T> level_roles(gmg_handle* h, int l, T* x0, const int* sel) {
 // accepted iterate (role 0) is never written; coarse levels alternate 0 <-> 1
 static int next_role(int l, int r) { return l == 0 ? (r == 1 ? 2 : 1) : 1 - r; }
 
+// Optional parts of a sweep launch: the input-residual partials, the omega
+// to use (default: the solve state's), and a gate flag.
+struct SweepOpt {
+  double* res_part = nullptr;
+  const double* omega = nullptr;
+  const int* gate = nullptr;
+};
+
 template <typename T, typename TL, int TY>
 static void launch_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
-                         const T* xc, const int* done, int kchunk) {
+                         const T* xc, const int* done, int kchunk, const SweepOpt& o = {}) {
   const Level& lv = h->lev[l];
   const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
   const dim3 grid(((lv.g.nx + SW_TX - 1) / SW_TX) * ((lv.g.ny + TY - 1) / TY) *
@@ -593,23 +662,29 @@ static void launch_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd
   if (lv.g.nx % 2 == 0)
     hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 2>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,
                        sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, kchunk,
-                       &h->st->omega, done);
+                       o.omega ? o.omega : &h->st->omega, done, o.res_part, o.gate);
   else
     hipLaunchKernelGGL((k_rb_sweep<T, TL, TY, 1>), grid, dim3(32 * TY), 0, h->s, lv.g, X, rs, rd,
                        sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, kchunk,
-                       &h->st->omega, done);
+                       o.omega ? o.omega : &h->st->omega, done, o.res_part, o.gate);
+}
+
+// Workgroups of a level's sweep launch (partials written with res_part).
+static long long sweep_blocks(const Level& lv, int ty) {
+  return (long long)((lv.g.nx + SW_TX - 1) / SW_TX) * ((lv.g.ny + ty - 1) / ty) *
+         ((lv.g.nz + lv.kchunk - 1) / lv.kchunk);
 }
 
 // One fused sweep of level l with the level's tile choice (TY 4 or 8; FP64
 // sweeps always use TY 4 for their LDS budget).
 template <typename T, typename TL>
 static void enq_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
-                      const T* xc, const int* done) {
+                      const T* xc, const int* done, const SweepOpt& o = {}) {
   const Level& lv = h->lev[l];
   if (sizeof(T) == 8 || lv.ty == 4)
-    launch_sweep<T, TL, 4>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk);
+    launch_sweep<T, TL, 4>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk, o);
   else
-    launch_sweep<T, TL, 8>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk);
+    launch_sweep<T, TL, 8>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk, o);
 }
 
 template <typename T, typename TL>
@@ -747,10 +822,22 @@ static int plan_tail(gmg_handle* h) {
   return h->nlev;
 }
 
+// Deferred decision of gmg_solve (see k_spec_finish): the cycle's first
+// sweep reads the candidate (level-0 role 1), writes role 2 and leaves the
+// partials of its input residual in `part`; level-0 roles go through the
+// solve state's map; the cycle's result is written to role 1.
+struct SpecPlan {
+  double* part;
+  long long np;
+};
+
 // V-cycle from level 0.  X0 is the level-0 role-0 buffer (with `sel`, the
-// roles rotate on the device).  Returns the level-0 role of the result.
+// roles rotate on the device).  With a SpecPlan (and the mapped level-0
+// roles R0), the first sweep is the speculative one and the decision on the
+// previous cycle follows it.  Returns the level-0 role of the result.
 template <typename T, typename TL>
-static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, const int* done) {
+static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, const int* done,
+                      const SpecPlan* sp = nullptr, const Roles<T>* R0 = nullptr) {
   const int nl = h->nlev;
   const gmg_params& p = h->p;
   int role[kMaxLevels];
@@ -758,12 +845,28 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
   const bool pcg = p.smoother == GMG_SMOOTH_PCG;
   // descend: pre-smooth, then restrict the residual (coarse x starts at 0)
   for (int l = 0; l < lt; ++l) {
-    const Roles<T> X = level_roles<T>(h, l, X0, sel);
+    const Roles<T> X = (l == 0 && R0) ? *R0 : level_roles<T>(h, l, X0, sel);
     const T* sg = (l == 0) ? sigma0 : (const T*)h->lev[l].sigma;
     const bool coarsest = (l == nl - 1);
     int r = 0;
     const int nsw = coarsest ? p.nu_coarse : p.nu_pre;
-    if (pcg) {
+    if (l == 0 && sp) {
+      SweepOpt first;
+      first.res_part = sp->part;
+      first.omega = &h->st->omega_spec;
+      enq_sweep<T, TL>(h, 0, X, 1, 2, sg, nullptr, done, first);
+      hipLaunchKernelGGL(k_spec_finish, dim3(1), dim3(256), 0, h->s, sp->part, sp->np, h->st,
+                         h->rule);
+      SweepOpt again;
+      again.gate = &h->st->redo;
+      enq_sweep<T, TL>(h, 0, X, 0, 2, sg, nullptr, done, again);
+      r = 2;
+      for (int s = 1; s < nsw; ++s) {
+        const int rd = (r == 2) ? 3 : 2;
+        enq_sweep<T, TL>(h, 0, X, r, rd, sg, nullptr, done);
+        r = rd;
+      }
+    } else if (pcg) {
       r = enq_pcg_smooth<T, TL>(h, l, X, r, next_role(l, r), sg, nsw, done);
     } else {
       for (int s = 0; s < nsw; ++s) {
@@ -783,12 +886,25 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
   // ascend: prolong + correct (folded into the first post-sweep), post-smooth
   const int top = (lt < nl) ? lt - 1 : nl - 2;
   for (int l = top; l >= 0; --l) {
-    const Roles<T> X = level_roles<T>(h, l, X0, sel);
+    const Roles<T> X = (l == 0 && R0) ? *R0 : level_roles<T>(h, l, X0, sel);
     const T* sg = (l == 0) ? sigma0 : (const T*)h->lev[l].sigma;
     const Level& lv = h->lev[l];
     const T* xc = (const T*)h->lev[l + 1].x[role[l + 1]];
     int r = role[l];
-    if (p.nu_post > 0 && !pcg) {
+    if (l == 0 && sp) {  // work roles 2 <-> 3, the last step writes the candidate role 1
+      if (p.nu_post > 0) {
+        for (int s = 0; s < p.nu_post; ++s) {
+          const int rd = (s == p.nu_post - 1) ? 1 : ((r == 2) ? 3 : 2);
+          enq_sweep<T, TL>(h, 0, X, r, rd, sg, s == 0 ? xc : nullptr, done);
+          r = rd;
+        }
+      } else {
+        const Level& lc = h->lev[1];
+        hipLaunchKernelGGL((k_prolong<T>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, X, r, 1,
+                           lv.active, xc, lc.g, lv.c[0], lv.c[1], lv.c[2], done);
+        r = 1;
+      }
+    } else if (p.nu_post > 0 && !pcg) {
       for (int s = 0; s < p.nu_post; ++s) {
         const int rd = next_role(l, r);
         enq_sweep<T, TL>(h, l, X, r, rd, sg, s == 0 ? xc : nullptr, done);
@@ -872,7 +988,8 @@ static gmg_status validate(const gmg_params* p) {
     return fail(GMG_EINVAL, "tail_cells must be in [0, 32768]");
   if (p->smoother != GMG_SMOOTH_RBGS && p->smoother != GMG_SMOOTH_PCG)
     return fail(GMG_EINVAL, "smoother must be GMG_SMOOTH_RBGS or GMG_SMOOTH_PCG");
-  if (p->reserved != 0) return fail(GMG_EINVAL, "reserved must be 0");
+  if (p->deferred_norm != 0 && p->deferred_norm != 1)
+    return fail(GMG_EINVAL, "deferred_norm must be 0 or 1");
   if (!(p->omega0 > 0) || !(p->omega_min > 0) || !(p->omega_max >= p->omega_min) ||
       !(p->theta_dec > 0) || !(p->theta_inc > 0) || !std::isfinite(p->omega_max) ||
       !std::isfinite(p->omega0) || !std::isfinite(p->theta_inc))
@@ -892,6 +1009,8 @@ static void free_handle(gmg_handle* h) {
   (void)hipFree(h->L0x);
   (void)hipFree(h->w[0]);
   (void)hipFree(h->w[1]);
+  (void)hipFree(h->w[2]);
+  (void)hipFree(h->spec_part);
   (void)hipFree(h->partials);
   (void)hipFree(h->st);
   if (h->hst) (void)hipHostFree(h->hst);
@@ -1000,6 +1119,12 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
   HIP_TRY(hipMalloc(&h->partials, 2 * maxpart * sizeof(double)));
   HIP_TRY(hipMalloc(&h->w[0], h->lev[0].g.n * cs));
   HIP_TRY(hipMalloc(&h->w[1], h->lev[0].g.n * cs));
+  if (p->dtype == p->cycle_dtype) {  // gmg_solve's deferred decision
+    const Geom& g0 = h->lev[0].g;
+    HIP_TRY(hipMalloc(&h->w[2], g0.n * cs));
+    const long long maxblk = (long long)((g0.nx + SW_TX - 1) / SW_TX) * ((g0.ny + 3) / 4) * g0.nz;
+    HIP_TRY(hipMalloc(&h->spec_part, maxblk * sizeof(double)));
+  }
   HIP_TRY(hipMalloc(&h->st, sizeof(SolveState)));
   HIP_TRY(hipHostMalloc((void**)&h->hst, sizeof(SolveState), hipHostMallocDefault));
   std::memset(h->hst, 0, sizeof(SolveState));
@@ -1079,11 +1204,25 @@ static gmg_status captured(gmg_handle* h, CapturedSeq& cs, const void* k0, const
   return GMG_OK;
 }
 
-// One cycle of the adaptive solve: V-cycle, residual norm, decision.
+// Whether gmg_solve defers each cycle's decision to the next cycle's first
+// sweep (red-black smoother, at least one pre-sweep and two levels).
+static bool spec_ok(const gmg_handle* h) {
+  return h->p.deferred_norm && h->p.smoother == GMG_SMOOTH_RBGS && h->p.nu_pre >= 1 &&
+         h->nlev >= 2 && h->w[2] && h->spec_part;
+}
+
 template <typename T, typename TL>
 static gmg_status enq_solve_cycle(gmg_handle* h, T* xa, const T* sigma) {
   const Level& lv = h->lev[0];
   const long long np = nblocks(red_grid(lv.g));
+  if (spec_ok(h)) {  // the cycle's norm is taken by the next cycle's first sweep
+    const SpecPlan sp{h->spec_part, sweep_blocks(lv, sizeof(T) == 8 ? 4 : lv.ty)};
+    const Roles<T> XM{{xa, (T*)h->w[0], (T*)h->w[1], (T*)h->w[2]}, nullptr, h->st->map};
+    enq_vcycle<T, TL>(h, xa, nullptr, sigma, &h->st->done, &sp, &XM);
+    HIP_TRY(hipGetLastError());
+    return GMG_OK;
+  }
+  // otherwise: V-cycle, residual norm, decision
   const Roles<T> XS{{xa, (T*)h->w[0], (T*)h->w[1]}, &h->st->cur};
   const int f = enq_vcycle<T, TL>(h, xa, &h->st->cur, sigma, &h->st->done);
   enq_resnorm<T, TL>(h, XS, f, sigma, (const TL*)lv.L, nullptr, 0, &h->st->done);
@@ -1206,6 +1345,7 @@ gmg_status gmg_default_params(gmg_params* p) {
   p->rollback = 1;
   p->graphs = 1;
   p->tail_cells = 4096;
+  p->deferred_norm = 0;
   p->omega0 = 1.0;
   p->omega_min = 0.1;
   p->omega_max = 1.0;
@@ -1449,6 +1589,7 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
   if (!(rtol >= 0) || max_cycles < 0) return fail(GMG_EINVAL, "bad rtol / max_cycles");
   const Level& lv = h->lev[0];
   const long long np = nblocks(red_grid(lv.g));
+  const bool spec = spec_ok(h);
   int rounds = 0;
   DISPATCH_CYCLE(h, {
     T* xa = (T*)x;
@@ -1465,7 +1606,8 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
       HIP_TRY(hipMemcpyAsync(h->hst, h->st, offsetof(SolveState, hist), hipMemcpyDeviceToHost,
                              h->s));
       HIP_TRY(hipStreamSynchronize(h->s));
-      if (h->hst->done || launched >= max_cycles) break;
+      // with the deferred decision the first pass decides nothing
+      if (h->hst->done || launched >= max_cycles + (spec ? 1 : 0)) break;
       if (launched > 0) {
         // size the next launch round from the observed contraction
         const double rho = h->hst->rho, tgt = rtol * h->hst->snorm;
@@ -1480,7 +1622,7 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
           chunk = 1;
         }
       }
-      chunk = std::min(chunk, max_cycles - launched);
+      chunk = std::min(chunk, max_cycles + (spec ? 1 : 0) - launched);
       if (h->p.graphs) {
         hipGraphExec_t ex = nullptr;
         GMG_TRY(captured(h, h->cyc, xa, sigma,
@@ -1494,10 +1636,15 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
     }
     HIP_TRY(hipMemcpyAsync(h->hst, h->st, sizeof(SolveState), hipMemcpyDeviceToHost, h->s));
     HIP_TRY(hipStreamSynchronize(h->s));
-    const int cur = h->hst->cur;
-    if (cur != 0)
-      HIP_TRY(hipMemcpyAsync(xa, h->w[cur - 1], lv.g.n * sizeof(T), hipMemcpyDeviceToDevice,
-                             h->s));
+    if (spec) {  // the accepted iterate is buffer map[0]: the caller's x or the fourth
+      if (h->hst->map[0] == 3)
+        HIP_TRY(hipMemcpyAsync(xa, h->w[2], lv.g.n * sizeof(T), hipMemcpyDeviceToDevice, h->s));
+    } else {
+      const int cur = h->hst->cur;
+      if (cur != 0)
+        HIP_TRY(hipMemcpyAsync(xa, h->w[cur - 1], lv.g.n * sizeof(T), hipMemcpyDeviceToDevice,
+                               h->s));
+    }
     HIP_TRY(hipStreamSynchronize(h->s));
   });
   const SolveState& s = *h->hst;

@@ -162,6 +162,7 @@ struct SweepArgs {
   const uint8_t* active;
   Geom gc;
   int cx, cy, cz;
+  double* res_part;  // non-null: FP64 partial of ||sigma - A S||^2 per workgroup
 };
 
 template <typename T, typename TL, int TY, int VEC>
@@ -274,6 +275,40 @@ __device__ __forceinline__ T black_update(const SweepSmem<T, TY>& sm, int dm, in
                        sm.lz[dp][fr][ex], sm.sg[d][fr][ex], omega);
 }
 
+// Squared residual sigma - A S of the input (active cells) at the thread's
+// x-pair of plane p, from the LDS rings (same term order as the updates).
+template <typename T, int TY>
+__device__ __forceinline__ double input_residual_sq(const SweepSmem<T, TY>& sm, const Geom& g,
+                                                   int i0, int j0, int p) {
+  const int tid = threadIdx.x;
+  const int px = tid & 31, ty = tid >> 5;
+  const int j = j0 + ty;
+  if (j >= g.ny) return 0.0;
+  const int d = ring3(p), dm = ring3(p - 1), dp = ring3(p + 1);
+  const int sr = ty + 2, fr = ty + 1;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int ex = 2 + 2 * px + e;
+    if (i0 + 2 * px + e >= g.nx) continue;
+    const T xc = sm.s[d][sr][ex];
+    const T lxm = sm.lx[d][fr][ex], lxp = sm.lx[d][fr][ex + 1];
+    const T lym = sm.ly[d][fr][ex], lyp = sm.ly[d][fr + 1][ex];
+    const T lzm = sm.lz[d][fr][ex], lzp = sm.lz[dp][fr][ex];
+    T ax = T(0);
+    ax += lxp * (sm.s[d][sr][ex + 1] - xc);
+    ax += lxm * (sm.s[d][sr][ex - 1] - xc);
+    ax += lyp * (sm.s[d][sr + 1][ex] - xc);
+    ax += lym * (sm.s[d][sr - 1][ex] - xc);
+    ax += lzp * (sm.s[dp][sr][ex] - xc);
+    ax += lzm * (sm.s[dm][sr][ex] - xc);
+    const T s = ((lxm + lxp) + (lym + lyp)) + (lzm + lzp);
+    const T r = (s != T(0)) ? sm.sg[d][fr][ex] - ax : T(0);
+    acc += (double)r * (double)r;
+  }
+  return acc;
+}
+
 // Red phase for plane p: interior pairs (one red cell each) and the ring.
 template <typename T, int TY>
 __device__ __forceinline__ void red_phase(SweepSmem<T, TY>& sm, int i0, int j0, int p, T omega) {
@@ -315,7 +350,7 @@ template <typename T, typename TL, int TY, int VEC>
 __device__ __forceinline__ void sweep_step(SweepSmem<T, TY>& sm, const SweepArgs<T, TL, TY, VEC>& a,
                                            T* __restrict__ W, int i0, int j0, int k0, int k1, int k,
                                            T omega, PlaneRegs<T, TY, VEC>& cur,
-                                           PlaneRegs<T, TY, VEC>& nxt,
+                                           PlaneRegs<T, TY, VEC>& nxt, double& racc,
                                            const LoadPlan<SweepCfg<TY, VEC>::NS>& ps,
                                            const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
                                            const LoadPlan<SweepCfg<TY, VEC>::NY>& py) {
@@ -326,6 +361,8 @@ __device__ __forceinline__ void sweep_step(SweepSmem<T, TY>& sm, const SweepArgs
   const int ib = i0 + 2 * px;
   if (k + 4 <= k1 + 1) fetch_plane<T, TL, TY, VEC>(nxt, a, k + 4, ps, pf, py);
   red_phase<T, TY>(sm, i0, j0, k + 1, omega);
+  // input residual of plane k+1 (its S neighbours k .. k+2 are all present)
+  if (a.res_part != nullptr && k + 1 < k1) racc += input_residual_sq<T, TY>(sm, g, i0, j0, k + 1);
   __syncthreads();
   if (k >= k0) {
     const int d = ring3(k), dm = ring3(k - 1), dp = ring3(k + 1);
@@ -389,22 +426,31 @@ __device__ __forceinline__ void rb_sweep_tile(SweepSmem<T, TY>& sm,
   fetch_plane<T, TL, TY, VEC>(ra, a, k0 + 2, ps, pf, py);
   __syncthreads();
   red_phase<T, TY>(sm, i0, j0, k0, omega);  // reads planes k0-1 .. k0+1
+  double racc = 0.0;
+  if (a.res_part != nullptr && k0 < k1) racc = input_residual_sq<T, TY>(sm, g, i0, j0, k0);
   __syncthreads();
   store_plane<T, TY, VEC>(sm, ring3(k0 + 2), a.xc != nullptr, ra, ps, pf, py);  // slot of plane k0-1
   fetch_plane<T, TL, TY, VEC>(ra, a, k0 + 3, ps, pf, py);
   __syncthreads();
   int k;
   for (k = k0; k < k1; k += 2) {
-    sweep_step<T, TL, TY, VEC>(sm, a, W, i0, j0, k0, k1, k, omega, ra, rb, ps, pf, py);
+    sweep_step<T, TL, TY, VEC>(sm, a, W, i0, j0, k0, k1, k, omega, ra, rb, racc, ps, pf, py);
     if (k + 1 < k1)
-      sweep_step<T, TL, TY, VEC>(sm, a, W, i0, j0, k0, k1, k + 1, omega, rb, ra, ps, pf, py);
+      sweep_step<T, TL, TY, VEC>(sm, a, W, i0, j0, k0, k1, k + 1, omega, rb, ra, racc, ps, pf,
+                                 py);
+  }
+  if (a.res_part != nullptr) {  // one FP64 partial per workgroup, fixed order
+    const double sum = block_sum(racc, threadIdx.x, C::NT);
+    if (threadIdx.x == 0) a.res_part[blockIdx.x] = sum;
   }
 }
 
 }  // namespace gmg
 
 // The fused sweep kernel: X[rd] = sweep(X[rs] (+ P x_c)), at global scope
-// so that its symbol carries no namespace.
+// so that its symbol carries no namespace.  With res_part it also leaves one
+// partial of ||sigma - A X[rs]||^2 per workgroup; with gate it runs only
+// when *gate is nonzero.
 template <typename T, typename TL, int TY, int VEC>
 __global__ __launch_bounds__(32 * TY) void k_rb_sweep(gmg::Geom g, gmg::Roles<T> X, int rs, int rd,
                                                       const T* __restrict__ sigma,
@@ -412,10 +458,12 @@ __global__ __launch_bounds__(32 * TY) void k_rb_sweep(gmg::Geom g, gmg::Roles<T>
                                                       const T* __restrict__ xc,
                                                       const uint8_t* __restrict__ active, gmg::Geom gc,
                                                       int cx, int cy, int cz, int kchunk,
-                                                      const double* omega_p, const int* done) {
+                                                      const double* omega_p, const int* done,
+                                                      double* res_part, const int* gate) {
   if (gmg::stopped(done)) return;
+  if (gate != nullptr && *gate == 0) return;  // a conditional sweep that is not needed
   __shared__ gmg::SweepSmem<T, TY> sm;
-  gmg::SweepArgs<T, TL, TY, VEC> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
+  gmg::SweepArgs<T, TL, TY, VEC> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz, res_part};
   // 1-D grid of tiles, x fastest, then y, then z-chunks, in XCD-aware order
   const int ntx = (g.nx + gmg::SW_TX - 1) / gmg::SW_TX, nty = (g.ny + TY - 1) / TY;
   const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);

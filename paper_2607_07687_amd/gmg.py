@@ -32,7 +32,7 @@ class gmg_params(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("nu_coarse", ctypes.c_int32), ("rollback", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
-                ("smoother", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("smoother", ctypes.c_int32), ("deferred_norm", ctypes.c_int32),
                 ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
                 ("theta_inc", ctypes.c_double)]

@@ -217,9 +217,10 @@ def _compare_solve(res_gpu, res_orc, prec, floor):
     assert np.allclose(res_gpu["omegas"], res_orc["omegas"])
 
 
-def test_solve_tgv32_fp64_to_1e10():
+@pytest.mark.parametrize("deferred", [0, 1])
+def test_solve_tgv32_fp64_to_1e10(deferred):
     L, s, per = P.tgv_periodic(32, seed=0)
-    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f64")
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f64", deferred_norm=deferred)
     xd = torch.zeros_like(sd)
     rg = G.gmg_solve(h, xd, sd, 1e-10, 100)
     ro = O.solve(levels, np.zeros_like(s64), s64, 1e-10, 100)
@@ -232,9 +233,10 @@ def test_solve_tgv32_fp64_to_1e10():
     h.close()
 
 
-def test_solve_sphere64_fp32_to_1e6():
+@pytest.mark.parametrize("deferred", [0, 1])
+def test_solve_sphere64_fp32_to_1e6(deferred):
     L, s, per = P.sphere_box((64, 64, 64), (32.0, 32.0, 32.0), 8.0, "uniform", 1)
-    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f32")
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f32", deferred_norm=deferred)
     xd = torch.zeros_like(sd)
     rg = G.gmg_solve(h, xd, sd, 1e-6, 60)
     ro = O.solve(levels, np.zeros_like(s64), s64, 1e-6, 60)
@@ -247,10 +249,11 @@ def test_solve_sphere64_fp32_to_1e6():
     h.close()
 
 
-def test_solve_rollback_decisions_match():
+@pytest.mark.parametrize("deferred", [0, 1])
+def test_solve_rollback_decisions_match(deferred):
     case = ("rollback", (16, 16, 16), (False, False, False), 4.0, 0.0)
     kw = dict(omega0=3.0, omega_max=3.0, theta_inc=1.0)
-    h, Ld, sd, levels, L64, s64 = setup_case(case, "f64", **kw)
+    h, Ld, sd, levels, L64, s64 = setup_case(case, "f64", deferred_norm=deferred, **kw)
     xd = torch.zeros_like(sd)
     rg = G.gmg_solve(h, xd, sd, 1e-9, 80)
     ro = O.solve(levels, np.zeros_like(s64), s64, 1e-9, 80, **kw)
@@ -260,11 +263,12 @@ def test_solve_rollback_decisions_match():
     h.close()
 
 
-def test_solve_edge_cases():
+@pytest.mark.parametrize("deferred", [0, 1])
+def test_solve_edge_cases(deferred):
     require_gpu()
     # sigma = 0: nothing to do
     L, s, per = P.tgv_periodic(8, seed=0)
-    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f64")
+    h, Ld, sd, levels, L64, s64 = build(L, s, per, "f64", deferred_norm=deferred)
     xd = torch.zeros_like(sd)
     rg = G.gmg_solve(h, xd, torch.zeros_like(sd), 1e-6, 5)
     assert rg["status"] == "GMG_OK" and rg["cycles"] == 0
@@ -325,13 +329,15 @@ def test_abi_errors():
     h.close()
 
 
+@pytest.mark.parametrize("deferred", [0, 1])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_graph_replays_match_direct_launches(prec):
+def test_graph_replays_match_direct_launches(prec, deferred):
     # the captured V-cycle is replayed many times per solve and reused across
     # solves; every replay must give exactly what direct launches give
     L, s, per = P.sphere_box((64, 32, 32), (30.0, 16.0, 16.0), 6.0, "uniform", 4)
-    hg, Ld, sd, levels, L64, s64 = build(L, s, per, prec, graphs=1)
-    he = G.gmg_setup(G.gmg_default_params((64, 32, 32), per, hg.params.dtype, graphs=0), Ld)
+    hg, Ld, sd, levels, L64, s64 = build(L, s, per, prec, graphs=1, deferred_norm=deferred)
+    he = G.gmg_setup(G.gmg_default_params((64, 32, 32), per, hg.params.dtype, graphs=0,
+                                          deferred_norm=deferred), Ld)
     outs = []
     for h in (hg, he, hg):
         x = torch.zeros_like(sd)
@@ -432,3 +438,25 @@ def test_tail_cells_bounds():
         G.gmg_setup(p, L)
     assert e.value.status == G.GMG_EINVAL
     assert G.gmg_default_params((8, 8, 8), (False,) * 3).tail_cells == 4096
+
+
+@pytest.mark.parametrize("rollback", [1, 0])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_deferred_norm_gives_the_same_solve(prec, rollback):
+    # the norm taken by the next cycle's first sweep leads to the same
+    # decisions and the same iterates as the separate norm kernel; only the
+    # summation order of the norm differs
+    case = ("rollback", (48, 32, 24), (False, True, False), 3.0, 0.05)
+    kw = dict(omega0=2.5, omega_max=2.5, theta_inc=1.0, rollback=rollback)
+    out = []
+    for deferred in (0, 1):
+        h, Ld, sd, levels, L64, s64 = setup_case(case, prec, deferred_norm=deferred, **kw)
+        x = torch.zeros_like(sd)
+        out.append((G.gmg_solve(h, x, sd, 1e-6 if prec == "f32" else 1e-10, 60), x.clone()))
+        h.close()
+    (r0, x0), (r1, x1) = out
+    say(f"deferred vs separate: {r1['cycles']} / {r0['cycles']} cycles, accepted {r1['accepted']}")
+    assert r0["cycles"] == r1["cycles"] and r0["accepted"] == r1["accepted"]
+    assert r0["omegas"] == r1["omegas"] and 0 in r0["accepted"] + [0] * (1 - rollback)
+    assert torch.equal(x0, x1)
+    assert np.allclose(r0["history"], r1["history"], rtol=1e-12 if prec == "f64" else 1e-5)

@@ -143,7 +143,7 @@ def test_pcg_errors():
         G.gmg_pcg(h, x, x, 1e-6, 10)  # mixed precision handle: use gmg_solve_ir
     assert e.value.status == G.GMG_EINVAL
     h.close()
-    for bad in (dict(smoother=2), dict(reserved=1)):
+    for bad in (dict(smoother=2), dict(deferred_norm=2)):
         with pytest.raises(G.GMGError) as e:
             G.gmg_setup(G.gmg_default_params((8, 8, 8), (False,) * 3, **bad), L.float())
         assert e.value.status == G.GMG_EINVAL
