@@ -392,7 +392,8 @@ def main():
         "setup_ms": setup_ms,
         "tiles": [{"level": t["level"], "ty": t["ty"], "kchunk": t["kchunk"]} for t in tiles],
         "roofline": {"bound": "hbm",
-                     "kernel": f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)",
+                     "kernel": (f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)"
+                                if tiles[0]["ty"] != 1 else "k_half_sweep<float,float> (level-0 split sweep)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (counters)",

@@ -314,9 +314,11 @@ gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps);
 /* Free the batch and all its problems.  NULL is accepted. */
 gmg_status gmg_batch_destroy(gmg_batch* b);
 
-/* Tile choice of the fused red-black sweep per level, as measured by
- * gmg_autotune: rows per tile (ty, 4 or 8) and z-planes per workgroup
- * (kchunk), with the mean sweep time of the chosen and the default shape. */
+/* Sweep choice per level, as measured by gmg_autotune: the fused sweep with
+ * ty = 4 or 8 rows per tile and kchunk z-planes per workgroup, or ty = 1:
+ * the sweep as two plain half-sweep launches (red, then black), faster where
+ * a level's plane march is latency-bound; with the mean sweep time of the
+ * chosen and the default choice. */
 typedef struct gmg_tune_report {
   int32_t nlevels;
   int32_t ty[32], kchunk[32];
@@ -324,8 +326,9 @@ typedef struct gmg_tune_report {
   double us[32], us_default[32];
 } gmg_tune_report;
 
-/* Time `reps` fused sweeps of every level for each candidate tile shape
- * (ty in {8, 4}, kchunk in {2, 4, ..., 64} up to nz; FP64 cycles: ty 4) with
+/* Time `reps` sweeps of every level for each candidate (fused with ty in
+ * {8, 4} and kchunk in {2, 4, ..., 64} up to nz, FP64 cycles: ty 4; and the
+ * split half-sweeps, ty 1) with
  * HIP events on the handle's stream, and keep the fastest per level.  x and
  * sigma are level-0 device arrays (dtype == cycle_dtype) used as the sweep's
  * input (x is overwritten with smoothed values; coarse levels use internal
@@ -334,9 +337,10 @@ typedef struct gmg_tune_report {
 gmg_status gmg_autotune(gmg_handle* h, void* x, const void* sigma, int32_t reps,
                         gmg_tune_report* report);
 
-/* Apply a known tile choice to one level (e.g. from a cache of earlier
- * gmg_autotune runs).  GMG_EINVAL for ty not in {4, 8} (4 with FP64 cycles)
- * or kchunk outside [1, nz]. */
+/* Apply a known sweep choice to one level (e.g. from a cache of earlier
+ * gmg_autotune runs).  GMG_EINVAL for ty not in {1, 4, 8} (1 or 4 with FP64
+ * cycles) or kchunk outside [1, nz].  With ty = 1 on level 0, gmg_solve does
+ * not use the deferred norm. */
 gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk);
 
 /* Thread-local description of the last error ("" if none). */

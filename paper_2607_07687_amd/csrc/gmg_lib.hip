@@ -509,6 +509,7 @@ __global__ __launch_bounds__(BT) void k_ir_update(Geom g, double* __restrict__ x
 }
 
 #include "gmg_pcg.h"
+#include "gmg_split.h"
 
 // ---------------------------------------------------------------------------
 // Handle
@@ -675,13 +676,30 @@ static long long sweep_blocks(const Level& lv, int ty) {
          ((lv.g.nz + lv.kchunk - 1) / lv.kchunk);
 }
 
-// One fused sweep of level l with the level's tile choice (TY 4 or 8; FP64
-// sweeps always use TY 4 for their LDS budget).
+// Red-black sweep of level l as a red and a black half-sweep launch.
+template <typename T, typename TL>
+static void launch_split(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
+                         const T* xc, const int* done) {
+  const Level& lv = h->lev[l];
+  const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
+  const dim3 grid(((lv.g.nx + 1) / 2 + BX - 1) / BX, (lv.g.ny + BY - 1) / BY, lv.g.nz);
+  const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
+  for (int colour = 0; colour < 2; ++colour)
+    hipLaunchKernelGGL((k_half_sweep<T, TL>), grid, kBlock, 0, h->s, lv.g, X, rs, rd, sigma,
+                       (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz, colour, &h->st->omega,
+                       done);
+}
+
+// One sweep of level l with the level's choice: the fused sweep with tiles
+// of TY 4 or 8 rows (FP64 sweeps always use TY 4 for their LDS budget), or
+// (ty 1) the split red and black launches.
 template <typename T, typename TL>
 static void enq_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
                       const T* xc, const int* done, const SweepOpt& o = {}) {
   const Level& lv = h->lev[l];
-  if (sizeof(T) == 8 || lv.ty == 4)
+  if (lv.ty == 1 && o.res_part == nullptr && o.gate == nullptr && o.omega == nullptr)
+    launch_split<T, TL>(h, l, X, rs, rd, sigma, xc, done);
+  else if (sizeof(T) == 8 || lv.ty != 8)
     launch_sweep<T, TL, 4>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk, o);
   else
     launch_sweep<T, TL, 8>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk, o);
@@ -1208,7 +1226,7 @@ static gmg_status captured(gmg_handle* h, CapturedSeq& cs, const void* k0, const
 // sweep (red-black smoother, at least one pre-sweep and two levels).
 static bool spec_ok(const gmg_handle* h) {
   return h->p.deferred_norm && h->p.smoother == GMG_SMOOTH_RBGS && h->p.nu_pre >= 1 &&
-         h->nlev >= 2 && h->w[2] && h->spec_part;
+         h->nlev >= 2 && h->w[2] && h->spec_part && h->lev[0].ty != 1;
 }
 
 template <typename T, typename TL>
@@ -1287,14 +1305,16 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
     rep->kchunk_default[l] = lv.kchunk;
     float best = 1e30f, deft = 0.f;
     int bty = lv.ty, bkc = lv.kchunk;
-    for (int it = -1; it < 2 * 6; ++it) {
-      // it == -1 times the default choice first
-      const int ty = (it < 0) ? lv.ty : tys[it / 6];
-      const int kc = (it < 0) ? lv.kchunk : kcs[it % 6];
-      if (sizeof(T) == 8 && ty != 4) continue;
+    for (int it = -1; it <= 2 * 6; ++it) {
+      // it == -1 times the default choice first, it == 12 the split sweep
+      const int ty = (it < 0) ? lv.ty : (it == 12 ? 1 : tys[it / 6]);
+      const int kc = (it < 0 || it == 12) ? lv.kchunk : kcs[it % 6];
+      if (sizeof(T) == 8 && ty == 8) continue;
       if (kc > lv.g.nz) continue;
       auto run = [&]() {
-        if (ty == 4)
+        if (ty == 1)
+          launch_split<T, TL>(h, l, X, 0, 1, sg, nullptr, nullptr);
+        else if (ty == 4)
           launch_sweep<T, TL, 4>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
         else
           launch_sweep<T, TL, 8>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
@@ -1732,8 +1752,8 @@ gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rt
 gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk) {
   if (!h) return fail(GMG_EINVAL, "NULL handle");
   if (level < 0 || level >= h->nlev) return fail(GMG_EINVAL, "level out of range");
-  if ((ty != 4 && ty != 8) || (h->p.cycle_dtype == GMG_F64 && ty != 4))
-    return fail(GMG_EINVAL, "ty must be 4 or 8 (4 for FP64 cycles)");
+  if ((ty != 1 && ty != 4 && ty != 8) || (h->p.cycle_dtype == GMG_F64 && ty == 8))
+    return fail(GMG_EINVAL, "ty must be 1 (split), 4 or 8 (1 or 4 for FP64 cycles)");
   if (kchunk < 1 || kchunk > h->lev[level].g.nz) return fail(GMG_EINVAL, "kchunk out of range");
   h->lev[level].ty = ty;
   h->lev[level].kchunk = kchunk;
