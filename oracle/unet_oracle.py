@@ -6,7 +6,7 @@ shares no code with the HIP kernels.
 The network predicts the pressure of the Poisson problem from (sigma / s, L_x,
 L_y, L_z), s = RMS of sigma over the active cells, so that GMG can start from
 its prediction instead of zero.  The paper has no network; its architecture
-is this build's reading (4 levels, 16 -> 128 channels, 3x3x3 convolutions with
+is the reading taken here (4 levels, 16 -> 128 channels, 3x3x3 convolutions with
 zero padding 1, ReLU, 2x2x2 average pooling, nearest x2 upsampling, skip
 concatenation, 1x1x1 head, MSE loss, Adam).
 

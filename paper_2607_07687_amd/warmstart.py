@@ -12,7 +12,7 @@ training with the project's kernels, and the timed comparison with plain GMG.
   final residual judges the prediction: if the warm-started solve misses the
   tolerance in its cycle budget, plain GMG from zero runs instead.
 
-Run on a GPU machine:  python -m paper_2607_07687_amd.warmstart --help
+Run on an MI355X:  python -m paper_2607_07687_amd.warmstart --help
 """
 from __future__ import annotations
 
@@ -255,7 +255,7 @@ def main():
     ap.add_argument("--batch", type=int, default=2)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--workers", type=int, default=8)
-    ap.add_argument("--out", default="gpurun_out/warmstart")
+    ap.add_argument("--out", default="warmstart_out")
     ap.add_argument("--conv-throughput", action="store_true")
     ap.add_argument("--params", default="", help="trained weights (.npy): evaluate only")
     args = ap.parse_args()
