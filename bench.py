@@ -24,46 +24,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GMG V-cycles/s + time to 1e-6 rel. residual at 256³ FP32; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell of one fused red-black sweep launch (FP32):
-# read x (4), sigma (4), the three face arrays (12); write x (4)
+# algorithmic bytes per cell of one launch of either level-0 smoothing
+# kernel (FP32): read x (4), sigma (4), the three face arrays (12); write x
+# (4).  The fused sweep does one sweep per launch, the two-sweep pass two.
 SWEEP_BYTES_PER_CELL = 24.0
 
-
-# hardware-counter summary of the level-0 sweep (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs of `bench.py --kernel-probe`); it names the hash of the
-# sources the counted kernel was built from
-COUNTERS = os.path.join(ROOT, "profiles", "sweep256_fp32_counters.md")
-# everything the level-0 sweep kernel is compiled from (kernel, helpers, flags)
-SWEEP_SOURCES = ["paper_2607_07687_amd/csrc/gmg_sweep.h", "paper_2607_07687_amd/csrc/gmg_device.h",
-                 "paper_2607_07687_amd/build.py"]
+# hardware-counter summaries of the level-0 smoothing kernels (rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs of `bench.py --kernel-probe`), each naming
+# the hash of the sources the counted kernel was built from, and everything
+# that kernel is compiled from (kernel, helpers, flags)
+_CSRC = "paper_2607_07687_amd/csrc/"
+KERNELS = {
+    "fused": (os.path.join(ROOT, "profiles", "sweep256_fp32_counters.md"),
+              [_CSRC + "gmg_sweep.h", _CSRC + "gmg_device.h", "paper_2607_07687_amd/build.py"]),
+    "pair": (os.path.join(ROOT, "profiles", "sweep2_256_fp32_counters.md"),
+             [_CSRC + "gmg_sweep2.h", _CSRC + "gmg_sweep.h", _CSRC + "gmg_device.h",
+              "paper_2607_07687_amd/build.py"]),
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def sweep_source_hash():
+def sweep_source_hash(kind="fused"):
     import hashlib
     h = hashlib.sha256()
-    for rel in SWEEP_SOURCES:
+    for rel in KERNELS[kind][1]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per level-0 sweep launch from the committed counter runs:
-    FETCH_SIZE scaled by the copy-kernel calibration factor, plus WRITE_SIZE.
-    None when the summary is missing or the sweep's sources have changed
-    since the counters were taken."""
+def measured_traffic(kind="fused"):
+    """HBM bytes per launch of a level-0 smoothing kernel from the committed
+    counter runs: FETCH_SIZE scaled by the copy-kernel calibration factor,
+    plus WRITE_SIZE.  None when the summary is missing or the kernel's
+    sources have changed since the counters were taken."""
     import re
     try:
-        text = open(COUNTERS).read()
+        text = open(KERNELS[kind][0]).read()
     except OSError:
         return None
     vals = dict(re.findall(r"^- (\w+): ([0-9a-f.]+)\s*$", text, re.M))
     try:
-        if vals["source_hash"] != sweep_source_hash():
+        if vals["source_hash"] != sweep_source_hash(kind):
             return None
         kib = float(vals["fetch_kib_per_launch"]) * float(vals["fetch_factor"]) + \
             float(vals["write_kib_per_launch"]) * float(vals["write_factor"])
@@ -286,8 +291,9 @@ def main():
     ap.add_argument("--tol-runs", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--kernel-probe", action="store_true",
-                    help="only run a 256 MiB device copy (counter calibration) and 4 level-0 "
-                         "fused sweeps at 256^3, for hardware-counter runs")
+                    help="only run a 256 MiB device copy (counter calibration), 4 level-0 "
+                         "sweeps at 256^3 as two two-sweep passes, then 4 as fused sweeps, "
+                         "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -320,14 +326,18 @@ def main():
         b = torch.empty_like(a)
         b.copy_(a)
         G.gmg_smooth(h, 0, x, sd, 4)
+        G.gmg_set_pair_sweeps(h, 0, 0)
+        G.gmg_smooth(h, 0, x, sd, 4)
         torch.cuda.synchronize()
-        log("kernel probe done: copy of 256 MiB, 4 level-0 sweeps")
+        log("kernel probe done: copy of 256 MiB, 2 two-sweep passes, 4 fused sweeps")
         h.close()
         return
 
     # warm-up, then K timed cycles of the adaptive solve
     tiles = AT.tune(h, x, sd, cache=None)  # timed sweep tiles per level (setup, untimed)
-    log("tiles " + ", ".join(f"L{t['level']}:{t['ty']}x{t['kchunk']}" for t in tiles))
+    log("tiles " + ", ".join(f"L{t['level']}:{t['ty']}x{t['kchunk']}" +
+                             (f"+pass{t['pair_kchunk']}" if t.get("pair_kchunk") else "")
+                             for t in tiles))
     x.zero_()
     G.gmg_solve(h, x, sd, 0.0, max(1, args.warmup))
     x.zero_()
@@ -353,22 +363,39 @@ def main():
     rn, sn = G.gmg_residual(h, x, sd)
     log(f"time to 1e-6: {sorted(ttt)} ms, cycles {cyc}, final rel {rn / sn:.3e}")
 
-    # dominant kernel: the level-0 fused red-black sweep (one launch per
-    # sweep), timed with HIP events on the stream the library launches on
-    # (torch's current stream); an even sweep count needs no copy-back
+    # dominant kernel: the level-0 smoothing launch the solve uses (the
+    # two-sweep pass, or the fused sweep where the tuner turned passes off),
+    # timed with HIP events on the stream the library launches on (torch's
+    # current stream); an even sweep count needs no copy-back.  The other
+    # kernel is timed the same way for comparison.
     sweeps = 20
     stream = torch.cuda.current_stream(dev)
-    G.gmg_smooth(h, 0, x, sd, 2)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    G.gmg_smooth(h, 0, x, sd, sweeps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    sweep_ms = e0.elapsed_time(e1) / sweeps
+
+    def launch_ms(per_launch):
+        G.gmg_smooth(h, 0, x, sd, 2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        G.gmg_smooth(h, 0, x, sd, sweeps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / (sweeps // per_launch)
+
+    pair_kc = tiles[0].get("pair_kchunk", 0)
+    pass_ms = launch_ms(2) if pair_kc else None
+    G.gmg_set_pair_sweeps(h, 0, 0)
+    fused_ms = launch_ms(1)
+    kind = "pair" if pair_kc else "fused"
+    launch = pass_ms if pair_kc else fused_ms
     cells = 256 ** 3
     alg_bytes = SWEEP_BYTES_PER_CELL * cells
-    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (launch * 1e-3) / 1e9
     h.close()
+    if pair_kc:
+        kname = "k_rb_sweep2<float,float,8> (level-0 two-sweep pass, 2 sweeps per launch)"
+    elif tiles[0]["ty"] != 1:
+        kname = f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)"
+    else:
+        kname = "k_half_sweep<float,float> (level-0 split sweep)"
 
     out = {
         "metric": METRIC,
@@ -390,15 +417,20 @@ def main():
         "cycles_to_tol": int(np.median(cyc)),
         "final_rel_residual": rn / sn,
         "setup_ms": setup_ms,
-        "tiles": [{"level": t["level"], "ty": t["ty"], "kchunk": t["kchunk"]} for t in tiles],
-        "roofline": {"bound": "hbm",
-                     "kernel": (f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)"
-                                if tiles[0]["ty"] != 1 else "k_half_sweep<float,float> (level-0 split sweep)"),
+        "tiles": [{"level": t["level"], "ty": t["ty"], "kchunk": t["kchunk"],
+                   "pass_kchunk": t.get("pair_kchunk", 0)} for t in tiles],
+        "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kind),
                      "traffic_unit": "HBM bytes per launch (counters)",
-                     "avg_launch_us": sweep_ms * 1e3,
+                     "avg_launch_us": launch * 1e3,
                      "alg_bytes_per_launch": alg_bytes},
+        "level0_smoothing": {
+            "two_sweep_pass_us": pass_ms * 1e3 if pass_ms else None,
+            "fused_sweep_us": fused_ms * 1e3,
+            "us_per_sweep": (pass_ms / 2 if pass_ms else fused_ms) * 1e3,
+            "fused_sweep_frac": alg_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fused_sweep_traffic": measured_traffic("fused")},
     }
     if not args.no_extras:
         out["other_configs"] = extra_configs()

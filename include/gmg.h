@@ -108,6 +108,15 @@ typedef struct gmg_params {
                             Same decisions and iterates either way.  Needs
                             dtype == cycle_dtype, the red-black smoother,
                             nu_pre >= 1 and two levels; otherwise 0 is used.  */
+  int32_t pair_sweeps;   /* 1 (default): where a level uses it, two
+                            consecutive red-black sweeps of one smoothing step
+                            run as one two-sweep pass (temporal blocking: the
+                            faces and sigma are read once for both sweeps),
+                            bitwise the same result.  On at level 0 by
+                            default; gmg_autotune and gmg_set_pair_sweeps
+                            choose per level.  Needs FP32 cycles, the
+                            red-black smoother and an even nx; the deferred
+                            norm's sweeps stay single.  0: separate sweeps.   */
   double omega0;         /* relaxation factor at the start of a solve (1.0)   */
   double omega_min;      /* lower bound (0.1)                                 */
   double omega_max;      /* upper bound (1.0)                                 */
@@ -181,7 +190,9 @@ gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma,
  * `level`, at the handle's current omega: each sweep updates every active
  * cell of colour (i+j+k) mod 2 == 0 at once, x(I) += omega r(I) / D(I) from
  * the residual before that half-sweep, then every active cell of colour 1.
- * x, sigma: device arrays of that level's shape in cycle_dtype.  Async. */
+ * Consecutive sweeps run as two-sweep passes where the level uses them
+ * (pair_sweeps), with the same result.  x, sigma: device arrays of that
+ * level's shape in cycle_dtype.  Async. */
 gmg_status gmg_smooth(gmg_handle* h, int32_t level, void* x,
                       const void* sigma, int32_t sweeps);
 
@@ -324,11 +335,15 @@ typedef struct gmg_tune_report {
   int32_t ty[32], kchunk[32];
   int32_t ty_default[32], kchunk_default[32];
   double us[32], us_default[32];
+  int32_t pair_kchunk[32];  /* z-chunk of the two-sweep pass kept, 0 = none  */
+  double us_pair[32];       /* best time of one two-sweep pass (0: not tried) */
 } gmg_tune_report;
 
 /* Time `reps` sweeps of every level for each candidate (fused with ty in
  * {8, 4} and kchunk in {2, 4, ..., 64} up to nz, FP64 cycles: ty 4; and the
- * split half-sweeps, ty 1) with
+ * split half-sweeps, ty 1), and where pair_sweeps allows, `reps` two-sweep
+ * passes with kchunk in {default, 4, 8, ..., 256} (a pass is kept if it beats
+ * two of the chosen sweeps), with
  * HIP events on the handle's stream, and keep the fastest per level.  x and
  * sigma are level-0 device arrays (dtype == cycle_dtype) used as the sweep's
  * input (x is overwritten with smoothed values; coarse levels use internal
@@ -342,6 +357,13 @@ gmg_status gmg_autotune(gmg_handle* h, void* x, const void* sigma, int32_t reps,
  * cycles) or kchunk outside [1, nz].  With ty = 1 on level 0, gmg_solve does
  * not use the deferred norm. */
 gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk);
+
+/* Run the smoothing steps of one level with two-sweep passes of kchunk
+ * z-planes per workgroup (kchunk = 0: separate sweeps).  GMG_EINVAL if the
+ * handle's parameters do not allow passes (pair_sweeps 0, FP64 cycles, the
+ * PCG smoother or an odd nx) or kchunk is outside [0, nz].  Results do not
+ * depend on the choice.  Recorded graphs are dropped. */
+gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t kchunk);
 
 /* Thread-local description of the last error ("" if none). */
 const char* gmg_last_error(void);

@@ -4,7 +4,8 @@ architecture, level shape and precision, stored as JSON.
     tiles = autotune.tune(h, x, sigma, dtype="f32", storage="f32",
                           cache="tiles.json")
 
-Levels whose key is already cached get the stored choice (gmg_set_tiles);
+Levels whose key is already cached get the stored choice (gmg_set_tiles,
+gmg_set_pair_sweeps);
 otherwise the library times the candidates (gmg_autotune) and the cache is
 updated.  The solver's results do not depend on the tile choice.
 """
@@ -34,13 +35,18 @@ def tune(h, x, sigma, dtype="f32", storage="f32", cache=None, reps=5):
             table = json.load(f)
     nl = G.gmg_num_levels(h)
     keys = [_key(arch, G.gmg_level_shape(h, l)[0], dtype, storage) for l in range(nl)]
-    if all(k in table for k in keys):
+    if all(k in table and "pair_kchunk" in table[k] for k in keys):
         for l, k in enumerate(keys):
             G.gmg_set_tiles(h, l, table[k]["ty"], table[k]["kchunk"])
+            try:
+                G.gmg_set_pair_sweeps(h, l, table[k]["pair_kchunk"])
+            except G.GMGError:  # this handle's parameters do not allow passes
+                G.gmg_set_pair_sweeps(h, l, 0)
         return [dict(level=l, **table[k], cached=True) for l, k in enumerate(keys)]
     res = G.gmg_autotune(h, x, sigma, reps)
     for r, k in zip(res, keys):
-        table[k] = dict(ty=r["ty"], kchunk=r["kchunk"], us=r["us"])
+        table[k] = dict(ty=r["ty"], kchunk=r["kchunk"], us=r["us"],
+                        pair_kchunk=r["pair_kchunk"], us_pair=r["us_pair"])
     if cache:
         d = os.path.dirname(cache)
         if d:

@@ -19,10 +19,12 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gmg_kernels.h"
 #include "gmg_sweep.h"
+#include "gmg_sweep2.h"
 #include "gmg_tail.h"
 #include "gmg_walk.h"
 
@@ -518,6 +520,7 @@ __global__ __launch_bounds__(BT) void k_ir_update(Geom g, double* __restrict__ x
 namespace {
 
 constexpr int kMaxLevels = 32;
+constexpr int kPairTY = 8;  // tile rows of the two-sweep pass
 constexpr int kTailMaxCells = 32768;
 constexpr int kResChunk = 16;  // z-planes per block in the norm reductions
 
@@ -530,6 +533,8 @@ struct Level {
   void* sigma;
   int kchunk;      // z-planes per workgroup of the fused sweep
   int ty;          // tile height of the fused sweep (rows of 64 cells)
+  int pair_kc;     // > 0: two consecutive sweeps run as one two-sweep pass
+                   // with this z-chunk; 0: separate sweeps
 };
 
 size_t dsize(int dt) { return dt == GMG_F64 ? 8 : (dt == GMG_BF16 ? 2 : 4); }
@@ -563,6 +568,24 @@ template <> struct SweepTY<double> { static constexpr int v = 4; };
 // LDS budget of 160 KB), which avoids a partly filled last round; at least
 // 2 planes per chunk.
 constexpr int kCUs = 256;
+// A level can run two consecutive sweeps as one pass: FP32 cycles of the
+// red-black smoother with at least one smoothing step of two sweeps, and an
+// even nx (the pass works on x-pairs).
+bool pair_capable(const gmg_params& p, const Geom& g) {
+  return p.pair_sweeps && p.cycle_dtype == GMG_F32 && p.smoother == GMG_SMOOTH_RBGS &&
+         g.nx % 2 == 0 && (p.nu_pre >= 2 || p.nu_post >= 2 || p.nu_coarse >= 2);
+}
+
+// z-chunk of the two-sweep pass: one workgroup per CU (its register
+// footprint allows one), as many chunks as fill the 256 CUs, at least 2
+// planes per chunk.
+int pair_kchunk(const Geom& g) {
+  const long long tiles = (long long)((g.nx + S2_TX - 1) / S2_TX) * ((g.ny + kPairTY - 1) / kPairTY);
+  const long long chunks = std::max<long long>(1, kCUs / std::max<long long>(1, tiles));
+  const int kc = (int)((g.nz + chunks - 1) / chunks);
+  return std::max(std::min(2, g.nz), kc);
+}
+
 int sweep_kchunk(const Geom& g, int ty, int elem_bytes) {
   const long long tiles = (long long)((g.nx + SW_TX - 1) / SW_TX) * ((g.ny + ty - 1) / ty);
   const size_t lds = (size_t)elem_bytes * SW_EX * 3 * ((ty + 4) + 3 * (ty + 2) + (ty + 3) + (ty + 2));
@@ -690,6 +713,24 @@ static void launch_split(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd
                        done);
 }
 
+// Two consecutive sweeps of level l as one two-sweep pass (FP32 cycles, even
+// nx): X[rd] = sweep(sweep(X[rs] (+ P x_c))), bitwise the result of two
+// sweeps; rd != rs.
+template <typename T, typename TL>
+static void launch_pair(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
+                        const T* xc, const int* done, int kchunk) {
+  if constexpr (std::is_same<T, float>::value) {
+    const Level& lv = h->lev[l];
+    const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
+    const dim3 grid(((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + kPairTY - 1) / kPairTY) *
+                    ((lv.g.nz + kchunk - 1) / kchunk));
+    const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
+    hipLaunchKernelGGL((k_rb_sweep2<T, TL, kPairTY>), grid, dim3(S2Cfg<kPairTY>::NTB), 0, h->s,
+                       lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz,
+                       kchunk, &h->st->omega, done);
+  }
+}
+
 // One sweep of level l with the level's choice: the fused sweep with tiles
 // of TY 4 or 8 rows (FP64 sweeps always use TY 4 for their LDS budget), or
 // (ty 1) the split red and black launches.
@@ -703,6 +744,28 @@ static void enq_sweep(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, c
     launch_sweep<T, TL, 4>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk, o);
   else
     launch_sweep<T, TL, 8>(h, l, X, rs, rd, sigma, xc, done, lv.kchunk, o);
+}
+
+// nu sweeps of level l from role r (the first with the folded correction
+// x_c), consecutive pairs as two-sweep passes where the level uses them;
+// each launch writes the other role.  Returns the role of the result.
+template <typename T, typename TL>
+static int enq_sweeps(gmg_handle* h, int l, const Roles<T>& X, int r, const T* sigma, const T* xc,
+                      const int* done, int nu) {
+  const Level& lv = h->lev[l];
+  for (int s = 0; s < nu;) {
+    const int rd = next_role(l, r);
+    const T* c = (s == 0) ? xc : nullptr;
+    if (nu - s >= 2 && lv.pair_kc > 0) {
+      launch_pair<T, TL>(h, l, X, r, rd, sigma, c, done, lv.pair_kc);
+      s += 2;
+    } else {
+      enq_sweep<T, TL>(h, l, X, r, rd, sigma, c, done);
+      s += 1;
+    }
+    r = rd;
+  }
+  return r;
 }
 
 template <typename T, typename TL>
@@ -887,11 +950,7 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     } else if (pcg) {
       r = enq_pcg_smooth<T, TL>(h, l, X, r, next_role(l, r), sg, nsw, done);
     } else {
-      for (int s = 0; s < nsw; ++s) {
-        const int rd = next_role(l, r);
-        enq_sweep<T, TL>(h, l, X, r, rd, sg, nullptr, done);
-        r = rd;
-      }
+      r = enq_sweeps<T, TL>(h, l, X, r, sg, nullptr, done, nsw);
     }
     role[l] = r;
     if (coarsest) break;
@@ -923,11 +982,7 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
         r = 1;
       }
     } else if (p.nu_post > 0 && !pcg) {
-      for (int s = 0; s < p.nu_post; ++s) {
-        const int rd = next_role(l, r);
-        enq_sweep<T, TL>(h, l, X, r, rd, sg, s == 0 ? xc : nullptr, done);
-        r = rd;
-      }
+      r = enq_sweeps<T, TL>(h, l, X, r, sg, xc, done, p.nu_post);
     } else {
       const int rd = (l == 0 && r == 0) ? 1 : r;  // never modify the accepted iterate
       const Level& lc = h->lev[l + 1];
@@ -1008,6 +1063,8 @@ static gmg_status validate(const gmg_params* p) {
     return fail(GMG_EINVAL, "smoother must be GMG_SMOOTH_RBGS or GMG_SMOOTH_PCG");
   if (p->deferred_norm != 0 && p->deferred_norm != 1)
     return fail(GMG_EINVAL, "deferred_norm must be 0 or 1");
+  if (p->pair_sweeps != 0 && p->pair_sweeps != 1)
+    return fail(GMG_EINVAL, "pair_sweeps must be 0 or 1");
   if (!(p->omega0 > 0) || !(p->omega_min > 0) || !(p->omega_max >= p->omega_min) ||
       !(p->theta_dec > 0) || !(p->theta_inc > 0) || !std::isfinite(p->omega_max) ||
       !std::isfinite(p->omega0) || !std::isfinite(p->theta_inc))
@@ -1131,6 +1188,9 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
     }
     lv.ty = p->cycle_dtype == GMG_F64 ? SweepTY<double>::v : SweepTY<float>::v;
     lv.kchunk = sweep_kchunk(lv.g, lv.ty, p->cycle_dtype == GMG_F64 ? 8 : 4);
+    // two-sweep passes: on by default at level 0, where a pass streams the
+    // largest arrays; the autotuner decides for the other levels
+    lv.pair_kc = (l == 0 && pair_capable(*p, lv.g)) ? pair_kchunk(lv.g) : 0;
   }
   maxpart = nblocks(red_grid(h->lev[0].g));
   h->maxpart = maxpart;
@@ -1340,6 +1400,32 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
     rep->kchunk[l] = bkc;
     rep->us[l] = 1e3 * best;
     rep->us_default[l] = 1e3 * deft;
+    // two-sweep pass: kept where one pass beats two of the chosen sweeps
+    rep->pair_kchunk[l] = 0;
+    rep->us_pair[l] = 0.0;
+    if (std::is_same<T, float>::value && pair_capable(h->p, lv.g)) {
+      const int pkcs[8] = {pair_kchunk(lv.g), 4, 8, 16, 32, 64, 128, 256};
+      float pbest = 1e30f;
+      int pkc = 0;
+      for (int kc : pkcs) {
+        if (kc > lv.g.nz) continue;
+        launch_pair<T, TL>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);  // warm-up
+        HIP_TRY(hipEventRecord(e0, h->s));
+        for (int r = 0; r < reps; ++r) launch_pair<T, TL>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
+        HIP_TRY(hipEventRecord(e1, h->s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        if (ms < pbest) {
+          pbest = ms;
+          pkc = kc;
+        }
+      }
+      lv.pair_kc = (pbest < 2.f * best) ? pkc : 0;
+      rep->pair_kchunk[l] = lv.pair_kc;
+      rep->us_pair[l] = 1e3 * pbest;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1366,6 +1452,7 @@ gmg_status gmg_default_params(gmg_params* p) {
   p->graphs = 1;
   p->tail_cells = 4096;
   p->deferred_norm = 0;
+  p->pair_sweeps = 1;
   p->omega0 = 1.0;
   p->omega_min = 0.1;
   p->omega_max = 1.0;
@@ -1474,14 +1561,12 @@ gmg_status gmg_smooth(gmg_handle* h, int32_t level, void* x, const void* sigma,
     return fail(GMG_EINVAL, "level-0 smoothing needs dtype == cycle_dtype");
   const Level& lv = h->lev[level];
   DISPATCH_CYCLE(h, {
-    // ping-pong between the caller's x and a work buffer of that level
+    // ping-pong between the caller's x (roles 0 and 2) and a work buffer of
+    // that level (role 1), consecutive sweeps as two-sweep passes where the
+    // level uses them
     T* work = (level == 0) ? (T*)h->w[0] : (T*)lv.x[1];
     Roles<T> X{{(T*)x, work, (T*)x}, nullptr};
-    int r = 0;
-    for (int s = 0; s < sweeps; ++s) {
-      enq_sweep<T, TL>(h, level, X, r, 1 - r, (const T*)sigma, nullptr, nullptr);
-      r = 1 - r;
-    }
+    const int r = enq_sweeps<T, TL>(h, level, X, 0, (const T*)sigma, nullptr, nullptr, sweeps);
     if (r == 1)
       HIP_TRY(hipMemcpyAsync(x, work, lv.g.n * sizeof(T), hipMemcpyDeviceToDevice, h->s));
   });
@@ -1757,6 +1842,18 @@ gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchun
   if (kchunk < 1 || kchunk > h->lev[level].g.nz) return fail(GMG_EINVAL, "kchunk out of range");
   h->lev[level].ty = ty;
   h->lev[level].kchunk = kchunk;
+  return drop_graphs(h);
+}
+
+gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t kchunk) {
+  if (!h) return fail(GMG_EINVAL, "handle is NULL");
+  if (level < 0 || level >= h->nlev) return fail(GMG_EINVAL, "level out of range");
+  if (kchunk != 0 && !pair_capable(h->p, h->lev[level].g))
+    return fail(GMG_EINVAL,
+                "two-sweep passes need pair_sweeps = 1, FP32 cycles, the red-black smoother "
+                "and an even nx");
+  if (kchunk < 0 || kchunk > h->lev[level].g.nz) return fail(GMG_EINVAL, "kchunk out of range");
+  h->lev[level].pair_kc = kchunk;
   return drop_graphs(h);
 }
 

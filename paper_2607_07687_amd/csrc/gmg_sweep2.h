@@ -1,0 +1,317 @@
+// Two red-black Gauss-Seidel sweeps in one pass (temporal blocking):
+// W = sweep(sweep(S)), for the nu = 2 pre- and post-smoothing of a level.
+//
+// A fused single sweep must read S, sigma and the three face arrays and
+// write W once per sweep.  Two consecutive sweeps of a V-cycle use the same
+// sigma, faces and omega, so one pass can do both and move those bytes once.
+//
+// Each workgroup owns a 64 x TY tile of (x, y) columns and a chunk of
+// z-planes.  One thread holds one x-pair column (two cells, one of each
+// colour on every plane) of the tile grown by four cells on each side, and
+// marches up the chunk.  A plane step k performs four half-sweeps, each one
+// plane behind the previous and one cell ring narrower:
+//
+//   stage 1  red cells of sweep 1 on plane k+3, tile + 3 cells
+//   stage 2  black cells of sweep 1 on plane k+2, tile + 2 cells
+//   stage 3  red cells of sweep 2 on plane k+1, tile + 1 cell
+//   stage 4  black cells of sweep 2 on plane k, the tile; plane k of W stored
+//
+// A cell's z-neighbours are in its own column, so the thread keeps the
+// inputs of five planes (S, sigma, faces) and the stage results of three
+// planes in registers.  x- and y-neighbours come from the neighbouring
+// threads through LDS: each step writes the values the next step's stages
+// read (S of the newest plane, and every stage's new results) into one half
+// of double-buffered LDS arrays and reads the half written by the previous
+// step, so a step needs one workgroup barrier.  High faces (Lx at x+1, Ly at
+// y+1) of the newest plane come through LDS the same way.
+//
+// Every update is relax_cell on the same operands as in two fused sweeps,
+// so the result is bitwise theirs.  Cells outside a wall hold zeros (their
+// faces are zero and relax_cell leaves them at their input).  Neighbouring
+// tiles recompute the grown rings redundantly; no workgroup reads another
+// one's output.
+//
+// Requires an even nx (x-pairs never straddle the domain edge).  Optionally
+// folds the prolongation + correction into the load of S, as the fused
+// sweep does.
+#pragma once
+
+#include "gmg_sweep.h"  // wrap_coord, 2-wide loads
+
+namespace gmg {
+
+constexpr int S2_TX = 64;  // tile width in x
+constexpr int S2_PX = 36;  // x-pairs per row of the grown region (64 + 2 x 4 cells)
+
+template <int TY>
+struct S2Cfg {
+  static constexpr int RY = TY + 8;                // rows of the grown region
+  static constexpr int NT = S2_PX * RY;            // threads holding a column
+  static constexpr int NTB = (NT + 63) / 64 * 64;  // workgroup size (whole waves)
+};
+
+template <typename T, int TY>
+struct S2Smem {
+  T s[2][TY + 8][2 * S2_PX];   // S of the newest plane
+  T ly[2][TY + 8][2 * S2_PX];  // Ly of the newest plane (high y-faces of the row below)
+  T lx0[2][TY + 8][S2_PX];     // Lx of each pair's first cell (high x-face of the pair before)
+  T r1[2][TY + 8][S2_PX];      // sweep-1 red value of each pair
+  T b1[2][TY + 8][S2_PX];      // sweep-1 black value of each pair
+  T r2[2][TY + 8][S2_PX];      // sweep-2 red value of each pair
+};
+
+// Inputs of one plane of a thread's pair column.
+template <typename T>
+struct S2Plane {
+  T s[2], sg[2], lx[2], ly[2], lz[2];
+  T lxh;     // Lx at x+2: high x-face of the pair's second cell
+  T lyh[2];  // Ly at y+1: high y-faces
+};
+
+// Global loads of one plane in flight (the prolongation operands separate,
+// so that no load waits on another).
+template <typename T>
+struct S2Load {
+  T s[2], sg[2], lx[2], ly[2], lz[2];
+  T pc[2];      // coarse value of each cell (prolongation)
+  uint32_t pa;  // active-mask bytes of the pair
+};
+
+template <typename T, typename TL>
+struct S2Args {
+  Geom g;
+  const T* S;
+  const T* sigma;
+  const TL* L;
+  const T* xc;
+  const uint8_t* active;
+  Geom gc;
+  int cx, cy, cz;
+};
+
+// Issue the loads of plane m for the column at in-plane offset `off` (-1:
+// outside a wall) with coarse in-plane offset `coff`.
+template <typename T, typename TL>
+__device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, int m, int off,
+                                         int coff) {
+  const Geom& g = a.g;
+  const int mm = wrap_coord(m, g.nz, g.pz);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) ld.s[e] = ld.sg[e] = ld.lx[e] = ld.ly[e] = ld.lz[e] = ld.pc[e] = T(0);
+  ld.pa = 0;
+  if (off < 0 || mm < 0) return;  // outside a wall: zeros
+  const long long idx = (long long)mm * g.sz + off;
+  ldv<T, 2>(a.S, idx, ld.s);
+  ldv<T, 2>(a.sigma, idx, ld.sg);
+  ldLv<T, 2>(a.L, idx, ld.lx);
+  ldLv<T, 2>(a.L + g.n, idx, ld.ly);
+  ldLv<T, 2>(a.L + 2 * g.n, idx, ld.lz);
+  if (a.xc != nullptr) {
+    // factors are 1 or 2; the pair's second cell has the next parent only
+    // when c_x = 1
+    const long long cb = (long long)(mm >> (a.cz >> 1)) * a.gc.sz + coff;
+    ld.pa = *reinterpret_cast<const uint16_t*>(a.active + idx);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) ld.pc[e] = a.xc[cb + (a.cx == 1 ? e : 0)];
+  }
+}
+
+// Loaded plane -> column registers (S corrected on active cells).
+template <typename T>
+__device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld, bool prol) {
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const bool corr = prol && ((ld.pa >> (8 * e)) & 0xFFu) != 0;
+    p.s[e] = corr ? ld.s[e] + ld.pc[e] : ld.s[e];
+    p.sg[e] = ld.sg[e];
+    p.lx[e] = ld.lx[e];
+    p.ly[e] = ld.ly[e];
+    p.lz[e] = ld.lz[e];
+    p.lyh[e] = T(0);
+  }
+  p.lxh = T(0);
+}
+
+// Element e (0 or 1, known only at run time) of a pair held in registers:
+// a select, since an indexed access would move the pair to scratch memory.
+template <typename T>
+__device__ __forceinline__ T pick(const T (&v)[2], int e) {
+  return e ? v[1] : v[0];
+}
+
+// Sweeps 1 and 2 of the tile with origin (i0, j0) over the z-planes [k0, k1).
+template <typename T, typename TL, int TY>
+__device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T, TL>& a,
+                                               T* __restrict__ W, int i0, int j0, int k0,
+                                               int k1, T omega) {
+  using C = S2Cfg<TY>;
+  const Geom& g = a.g;
+  const int t = threadIdx.x;
+  const bool col = t < C::NT;  // padding threads only join the barriers
+  const int p = col ? t % S2_PX : 0, r = col ? t / S2_PX : 0;
+  const int xa = i0 - 4 + 2 * p;  // x of the pair's first cell
+  const int y = j0 - 4 + r;
+  const int ii = wrap_coord(xa, g.nx, g.px), jj = wrap_coord(y, g.ny, g.py);
+  const int off = (col && ii >= 0 && jj >= 0) ? (int)(jj * g.sy) + ii : -1;
+  const int coff = (off >= 0) ? (int)((jj >> (a.cy >> 1)) * a.gc.sy) + (ii >> (a.cx >> 1)) : 0;
+  const bool prol = a.xc != nullptr;
+  // neighbour indices in LDS, clamped (clamped reads only feed cells outside
+  // the stage's region, whose results are never used)
+  const int pw = p > 0 ? p - 1 : 0, pe = p + 1 < S2_PX ? p + 1 : S2_PX - 1;
+  const int rs = r > 0 ? r - 1 : 0, rn = r + 1 < C::RY ? r + 1 : C::RY - 1;
+  // cell e of the pair lies in the tile grown by d cells
+  auto in_ring = [&](int e, int d) {
+    const int x = xa + e;
+    return x >= i0 - d && x < i0 + S2_TX + d && y >= j0 - d && y < j0 + TY + d;
+  };
+  const bool in3[2] = {in_ring(0, 3), in_ring(1, 3)}, in2[2] = {in_ring(0, 2), in_ring(1, 2)};
+  const bool in1[2] = {in_ring(0, 1), in_ring(1, 1)};
+  const bool out_ok = col && in_ring(0, 0) && y < g.ny && xa < g.nx;
+  // the pair's red element on plane m (colour by unwrapped coordinates; every
+  // periodic extent is even)
+  const int par = (xa + y) & 1;
+  auto red_e = [&](int m) { return (par + m) & 1; };
+
+  S2Plane<T> P0, P1, P2, P3, P4;  // planes k .. k+4 at step k
+  T r1a = T(0), r1b = T(0);       // sweep-1 red of planes k+1, k+2
+  T b1a = T(0), b1b = T(0);       // sweep-1 black of planes k, k+1
+  T r2a = T(0), r2b = T(0);       // sweep-2 red of planes k-1, k
+  S2Load<T> la, lb;
+  {
+    const S2Plane<T> z{};
+    P0 = P1 = P2 = z;
+  }
+  // prologue: planes k0-4 and k0-3 in registers, k0-2 in flight; the loop
+  // starts at step k0-7, whose P3, P4 are those planes
+  s2_fetch<T, TL>(la, a, k0 - 4, off, coff);
+  s2_fetch<T, TL>(lb, a, k0 - 3, off, coff);
+  s2_take<T>(P3, la, prol);
+  s2_take<T>(P4, lb, prol);
+  s2_fetch<T, TL>(la, a, k0 - 2, off, coff);
+  // step k0-8's exchange (S, Ly, Lx of plane k0-4 = P3) so that step k0-7
+  // can complete P3's high faces
+  {
+    const int q = (k0 - 8) & 1;
+    if (col) {
+      sm.s[q][r][2 * p] = P3.s[0];
+      sm.s[q][r][2 * p + 1] = P3.s[1];
+      sm.ly[q][r][2 * p] = P3.ly[0];
+      sm.ly[q][r][2 * p + 1] = P3.ly[1];
+      sm.lx0[q][r][p] = P3.lx[0];
+      sm.r1[q][r][p] = sm.b1[q][r][p] = sm.r2[q][r][p] = T(0);
+    }
+  }
+  __syncthreads();
+
+  auto step = [&](int k, S2Load<T>& cur, S2Load<T>& nxt) {
+    const int q = (k - 1) & 1, w = k & 1;
+    // issue the loads of plane k+6 (k+5 is in flight in `cur`)
+    if (k + 6 < k1 + 4) s2_fetch<T, TL>(nxt, a, k + 6, off, coff);
+    // complete plane k+3: high faces from the previous step's exchange
+    P3.lxh = sm.lx0[q][r][pe];
+    P3.lyh[0] = sm.ly[q][rn][2 * p];
+    P3.lyh[1] = sm.ly[q][rn][2 * p + 1];
+    T r1n = T(0), b1n = T(0), r2n = T(0);
+    // stage 1: sweep-1 red on plane k+3 from S
+    if (k + 3 >= k0 - 3 && k + 3 < k1 + 3) {
+      const int e = red_e(k + 3);
+      const T xe = e == 0 ? P3.s[1] : sm.s[q][r][2 * pe];
+      const T xw = e == 0 ? sm.s[q][r][2 * pw + 1] : P3.s[0];
+      const T v = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][rn][2 * p + e],
+                                sm.s[q][rs][2 * p + e], pick(P4.s, e), pick(P2.s, e),
+                                pick(P3.lx, e), e == 0 ? P3.lx[1] : P3.lxh, pick(P3.ly, e),
+                                pick(P3.lyh, e), pick(P3.lz, e), pick(P4.lz, e), pick(P3.sg, e),
+                                omega);
+      r1n = (e ? in3[1] : in3[0]) ? v : T(0);
+    }
+    // stage 2: sweep-1 black on plane k+2 from the sweep-1 red values
+    if (k + 2 >= k0 - 2 && k + 2 < k1 + 2) {
+      const int e = red_e(k + 2) ^ 1;
+      const T xe = e == 0 ? r1b : sm.r1[q][r][pe];
+      const T xw = e == 0 ? sm.r1[q][r][pw] : r1b;
+      const T v = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][rn][p], sm.r1[q][rs][p], r1n,
+                                r1a, pick(P2.lx, e), e == 0 ? P2.lx[1] : P2.lxh, pick(P2.ly, e),
+                                pick(P2.lyh, e), pick(P2.lz, e), pick(P3.lz, e), pick(P2.sg, e),
+                                omega);
+      b1n = (e ? in2[1] : in2[0]) ? v : T(0);
+    }
+    // stage 3: sweep-2 red on plane k+1 from the sweep-1 values
+    if (k + 1 >= k0 - 1 && k + 1 < k1 + 1) {
+      const int e = red_e(k + 1);
+      const T xe = e == 0 ? b1b : sm.b1[q][r][pe];
+      const T xw = e == 0 ? sm.b1[q][r][pw] : b1b;
+      const T v = relax_cell<T>(r1a, xe, xw, sm.b1[q][rn][p], sm.b1[q][rs][p], b1n, b1a,
+                                pick(P1.lx, e), e == 0 ? P1.lx[1] : P1.lxh, pick(P1.ly, e),
+                                pick(P1.lyh, e), pick(P1.lz, e), pick(P2.lz, e), pick(P1.sg, e),
+                                omega);
+      r2n = (e ? in1[1] : in1[0]) ? v : T(0);
+    }
+    // stage 4: sweep-2 black on plane k; store plane k of W
+    if (k >= k0 && k < k1) {
+      const int e = red_e(k) ^ 1;
+      const T xe = e == 0 ? r2b : sm.r2[q][r][pe];
+      const T xw = e == 0 ? sm.r2[q][r][pw] : r2b;
+      const T b2 = relax_cell<T>(b1a, xe, xw, sm.r2[q][rn][p], sm.r2[q][rs][p], r2n, r2a,
+                                 pick(P0.lx, e), e == 0 ? P0.lx[1] : P0.lxh, pick(P0.ly, e),
+                                 pick(P0.lyh, e), pick(P0.lz, e), pick(P1.lz, e), pick(P0.sg, e),
+                                 omega);
+      if (out_ok) {
+        const long long idx = (long long)k * g.sz + (long long)y * g.sy + xa;
+        const T o0 = e == 0 ? b2 : r2b, o1 = e == 0 ? r2b : b2;
+        if constexpr (sizeof(T) == 4)
+          *reinterpret_cast<float2*>(W + idx) = make_float2(o0, o1);
+        else
+          *reinterpret_cast<double2*>(W + idx) = make_double2(o0, o1);
+      }
+    }
+    // the next plane into the column registers, then exchange for step k+1
+    P0 = P1;
+    P1 = P2;
+    P2 = P3;
+    P3 = P4;
+    s2_take<T>(P4, cur, prol);  // plane k+5
+    r1a = r1b;
+    r1b = r1n;
+    b1a = b1b;
+    b1b = b1n;
+    r2a = r2b;
+    r2b = r2n;
+    if (col) {
+      sm.s[w][r][2 * p] = P3.s[0];  // plane k+4
+      sm.s[w][r][2 * p + 1] = P3.s[1];
+      sm.ly[w][r][2 * p] = P3.ly[0];
+      sm.ly[w][r][2 * p + 1] = P3.ly[1];
+      sm.lx0[w][r][p] = P3.lx[0];
+      sm.r1[w][r][p] = r1b;  // plane k+3
+      sm.b1[w][r][p] = b1b;  // plane k+2
+      sm.r2[w][r][p] = r2b;  // plane k+1
+    }
+    __syncthreads();
+  };
+  int k = k0 - 7;
+  for (; k + 1 < k1; k += 2) {
+    step(k, la, lb);
+    step(k + 1, lb, la);
+  }
+  if (k < k1) step(k, la, lb);
+}
+
+}  // namespace gmg
+
+// Two sweeps in one pass: X[rd] = sweep(sweep(X[rs] (+ P x_c))), at global
+// scope so that its symbol carries no namespace.
+template <typename T, typename TL, int TY>
+__global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
+    gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
+    const TL* __restrict__ L, const T* __restrict__ xc, const uint8_t* __restrict__ active,
+    gmg::Geom gc, int cx, int cy, int cz, int kchunk, const double* omega_p, const int* done) {
+  if (gmg::stopped(done)) return;
+  __shared__ gmg::S2Smem<T, TY> sm;
+  gmg::S2Args<T, TL> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
+  const int ntx = (g.nx + gmg::S2_TX - 1) / gmg::S2_TX, nty = (g.ny + TY - 1) / TY;
+  const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int k0 = tz * kchunk;
+  gmg::rb_sweep2_tile<T, TL, TY>(sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0,
+                                 min(g.nz, k0 + kchunk), (T)(*omega_p));
+}

@@ -33,7 +33,7 @@ class gmg_params(ctypes.Structure):
                 ("nu_coarse", ctypes.c_int32), ("rollback", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
                 ("smoother", ctypes.c_int32), ("deferred_norm", ctypes.c_int32),
-                ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
+                ("pair_sweeps", ctypes.c_int32), ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
                 ("theta_inc", ctypes.c_double)]
 
@@ -66,7 +66,8 @@ class gmg_tune_report(ctypes.Structure):
     _fields_ = [("nlevels", ctypes.c_int32), ("ty", ctypes.c_int32 * 32),
                 ("kchunk", ctypes.c_int32 * 32), ("ty_default", ctypes.c_int32 * 32),
                 ("kchunk_default", ctypes.c_int32 * 32), ("us", ctypes.c_double * 32),
-                ("us_default", ctypes.c_double * 32)]
+                ("us_default", ctypes.c_double * 32), ("pair_kchunk", ctypes.c_int32 * 32),
+                ("us_pair", ctypes.c_double * 32)]
 
 
 class GMGError(RuntimeError):
@@ -123,6 +124,7 @@ _SIGS = [
                                     ctypes.c_int32, ctypes.POINTER(gmg_tune_report)]),
     ("gmg_set_tiles", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32]),
+    ("gmg_set_pair_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     ("gmg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -416,8 +418,9 @@ def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inne
 
 
 def gmg_autotune(h, x, sigma, reps=5):
-    """Time the sweep tile candidates of every level and keep the fastest.
-    Returns per-level dicts (shape, ty, kchunk, us, defaults)."""
+    """Time the sweep tile candidates of every level and keep the fastest;
+    also the two-sweep pass where allowed.  Returns per-level dicts (shape,
+    ty, kchunk, us, defaults, pair_kchunk (0: separate sweeps), us_pair)."""
     rep = gmg_tune_report()
     _check(load().gmg_autotune(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), int(reps),
                                ctypes.byref(rep)))
@@ -426,12 +429,19 @@ def gmg_autotune(h, x, sigma, reps=5):
         n, _ = gmg_level_shape(h, l)
         out.append(dict(level=l, n=n, ty=rep.ty[l], kchunk=rep.kchunk[l], us=rep.us[l],
                         ty_default=rep.ty_default[l], kchunk_default=rep.kchunk_default[l],
-                        us_default=rep.us_default[l]))
+                        us_default=rep.us_default[l], pair_kchunk=rep.pair_kchunk[l],
+                        us_pair=rep.us_pair[l]))
     return out
 
 
 def gmg_set_tiles(h, level, ty, kchunk):
     _check(load().gmg_set_tiles(h.ptr, int(level), int(ty), int(kchunk)))
+
+
+def gmg_set_pair_sweeps(h, level, kchunk):
+    """Two-sweep passes of kchunk z-planes per workgroup on one level (0:
+    separate sweeps)."""
+    _check(load().gmg_set_pair_sweeps(h.ptr, int(level), int(kchunk)))
 
 
 def gmg_batch_autotune(b, reps=5):
