@@ -725,9 +725,14 @@ static void launch_pair(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd,
     const dim3 grid(((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + kPairTY - 1) / kPairTY) *
                     ((lv.g.nz + kchunk - 1) / kchunk));
     const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
-    hipLaunchKernelGGL((k_rb_sweep2<T, TL, kPairTY>), grid, dim3(S2Cfg<kPairTY>::NTB), 0, h->s,
-                       lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz,
-                       kchunk, &h->st->omega, done);
+    if (xc != nullptr)
+      hipLaunchKernelGGL((k_rb_sweep2<T, TL, kPairTY, true>), grid, dim3(S2Cfg<kPairTY>::NTB), 0,
+                         h->s, lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy,
+                         cz, kchunk, &h->st->omega, done);
+    else
+      hipLaunchKernelGGL((k_rb_sweep2<T, TL, kPairTY, false>), grid, dim3(S2Cfg<kPairTY>::NTB), 0,
+                         h->s, lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy,
+                         cz, kchunk, &h->st->omega, done);
   }
 }
 

@@ -75,6 +75,7 @@ struct S2Load {
   T s[2], sg[2], lx[2], ly[2], lz[2];
   T pc[2];      // coarse value of each cell (prolongation)
   uint32_t pa;  // active-mask bytes of the pair
+  bool in;      // the column and plane are in the domain (else zeros)
 };
 
 template <typename T, typename TL>
@@ -90,23 +91,25 @@ struct S2Args {
 };
 
 // Issue the loads of plane m for the column at in-plane offset `off` (-1:
-// outside a wall) with coarse in-plane offset `coff`.
-template <typename T, typename TL>
+// outside a wall) with coarse in-plane offset `coff` (PROL: also the
+// prolongation operands).  Every lane issues every load, at a clamped
+// in-domain address when the column or plane is outside a wall (s2_take
+// zeroes those), so the number of loads in flight is the same on every
+// path and the compiler waits for exactly the plane being taken.
+template <typename T, typename TL, bool PROL>
 __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, int m, int off,
                                          int coff) {
   const Geom& g = a.g;
-  const int mm = wrap_coord(m, g.nz, g.pz);
-#pragma unroll
-  for (int e = 0; e < 2; ++e) ld.s[e] = ld.sg[e] = ld.lx[e] = ld.ly[e] = ld.lz[e] = ld.pc[e] = T(0);
-  ld.pa = 0;
-  if (off < 0 || mm < 0) return;  // outside a wall: zeros
-  const long long idx = (long long)mm * g.sz + off;
+  const int mw = wrap_coord(m, g.nz, g.pz);
+  ld.in = off >= 0 && mw >= 0;
+  const int mm = mw >= 0 ? mw : 0;
+  const long long idx = (long long)mm * g.sz + (off >= 0 ? off : 0);
   ldv<T, 2>(a.S, idx, ld.s);
   ldv<T, 2>(a.sigma, idx, ld.sg);
   ldLv<T, 2>(a.L, idx, ld.lx);
   ldLv<T, 2>(a.L + g.n, idx, ld.ly);
   ldLv<T, 2>(a.L + 2 * g.n, idx, ld.lz);
-  if (a.xc != nullptr) {
+  if constexpr (PROL) {
     // factors are 1 or 2; the pair's second cell has the next parent only
     // when c_x = 1
     const long long cb = (long long)(mm >> (a.cz >> 1)) * a.gc.sz + coff;
@@ -116,17 +119,21 @@ __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, 
   }
 }
 
-// Loaded plane -> column registers (S corrected on active cells).
-template <typename T>
-__device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld, bool prol) {
+// Loaded plane -> column registers: zeros outside a wall (PROL: S corrected
+// on active cells).
+template <typename T, bool PROL>
+__device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld) {
+  const bool in = ld.in;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    const bool corr = prol && ((ld.pa >> (8 * e)) & 0xFFu) != 0;
-    p.s[e] = corr ? ld.s[e] + ld.pc[e] : ld.s[e];
-    p.sg[e] = ld.sg[e];
-    p.lx[e] = ld.lx[e];
-    p.ly[e] = ld.ly[e];
-    p.lz[e] = ld.lz[e];
+    if constexpr (PROL)
+      p.s[e] = !in ? T(0) : (((ld.pa >> (8 * e)) & 0xFFu) != 0 ? ld.s[e] + ld.pc[e] : ld.s[e]);
+    else
+      p.s[e] = in ? ld.s[e] : T(0);
+    p.sg[e] = in ? ld.sg[e] : T(0);
+    p.lx[e] = in ? ld.lx[e] : T(0);
+    p.ly[e] = in ? ld.ly[e] : T(0);
+    p.lz[e] = in ? ld.lz[e] : T(0);
     p.lyh[e] = T(0);
   }
   p.lxh = T(0);
@@ -139,8 +146,9 @@ __device__ __forceinline__ T pick(const T (&v)[2], int e) {
   return e ? v[1] : v[0];
 }
 
-// Sweeps 1 and 2 of the tile with origin (i0, j0) over the z-planes [k0, k1).
-template <typename T, typename TL, int TY>
+// Sweeps 1 and 2 of the tile with origin (i0, j0) over the z-planes [k0, k1)
+// (PROL: with the coarse correction folded into S).
+template <typename T, typename TL, int TY, bool PROL>
 __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T, TL>& a,
                                                T* __restrict__ W, int i0, int j0, int k0,
                                                int k1, T omega) {
@@ -154,7 +162,6 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   const int ii = wrap_coord(xa, g.nx, g.px), jj = wrap_coord(y, g.ny, g.py);
   const int off = (col && ii >= 0 && jj >= 0) ? (int)(jj * g.sy) + ii : -1;
   const int coff = (off >= 0) ? (int)((jj >> (a.cy >> 1)) * a.gc.sy) + (ii >> (a.cx >> 1)) : 0;
-  const bool prol = a.xc != nullptr;
   // neighbour indices in LDS, clamped (clamped reads only feed cells outside
   // the stage's region, whose results are never used)
   const int pw = p > 0 ? p - 1 : 0, pe = p + 1 < S2_PX ? p + 1 : S2_PX - 1;
@@ -183,11 +190,11 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   }
   // prologue: planes k0-4 and k0-3 in registers, k0-2 in flight; the loop
   // starts at step k0-7, whose P3, P4 are those planes
-  s2_fetch<T, TL>(la, a, k0 - 4, off, coff);
-  s2_fetch<T, TL>(lb, a, k0 - 3, off, coff);
-  s2_take<T>(P3, la, prol);
-  s2_take<T>(P4, lb, prol);
-  s2_fetch<T, TL>(la, a, k0 - 2, off, coff);
+  s2_fetch<T, TL, PROL>(la, a, k0 - 4, off, coff);
+  s2_fetch<T, TL, PROL>(lb, a, k0 - 3, off, coff);
+  s2_take<T, PROL>(P3, la);
+  s2_take<T, PROL>(P4, lb);
+  s2_fetch<T, TL, PROL>(la, a, k0 - 2, off, coff);
   // step k0-8's exchange (S, Ly, Lx of plane k0-4 = P3) so that step k0-7
   // can complete P3's high faces
   {
@@ -205,8 +212,9 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
 
   auto step = [&](int k, S2Load<T>& cur, S2Load<T>& nxt) {
     const int q = (k - 1) & 1, w = k & 1;
-    // issue the loads of plane k+6 (k+5 is in flight in `cur`)
-    if (k + 6 < k1 + 4) s2_fetch<T, TL>(nxt, a, k + 6, off, coff);
+    // issue the loads of plane k+6 (k+5 is in flight in `cur`); beyond the
+    // chunk's last needed plane (k1+3) they are loaded but never used
+    s2_fetch<T, TL, PROL>(nxt, a, k + 6, off, coff);
     // complete plane k+3: high faces from the previous step's exchange
     P3.lxh = sm.lx0[q][r][pe];
     P3.lyh[0] = sm.ly[q][rn][2 * p];
@@ -215,39 +223,41 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     // stage 1: sweep-1 red on plane k+3 from S
     if (k + 3 >= k0 - 3 && k + 3 < k1 + 3) {
       const int e = red_e(k + 3);
-      const T xe = e == 0 ? P3.s[1] : sm.s[q][r][2 * pe];
-      const T xw = e == 0 ? sm.s[q][r][2 * pw + 1] : P3.s[0];
-      const T v = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][rn][2 * p + e],
-                                sm.s[q][rs][2 * p + e], pick(P4.s, e), pick(P2.s, e),
-                                pick(P3.lx, e), e == 0 ? P3.lx[1] : P3.lxh, pick(P3.ly, e),
-                                pick(P3.lyh, e), pick(P3.lz, e), pick(P4.lz, e), pick(P3.sg, e),
-                                omega);
-      r1n = (e ? in3[1] : in3[0]) ? v : T(0);
+      if (e ? in3[1] : in3[0]) {  // whole waves outside the ring skip the update
+        const T xe = e == 0 ? P3.s[1] : sm.s[q][r][2 * pe];
+        const T xw = e == 0 ? sm.s[q][r][2 * pw + 1] : P3.s[0];
+        r1n = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][rn][2 * p + e], sm.s[q][rs][2 * p + e],
+                            pick(P4.s, e), pick(P2.s, e), pick(P3.lx, e),
+                            e == 0 ? P3.lx[1] : P3.lxh, pick(P3.ly, e), pick(P3.lyh, e),
+                            pick(P3.lz, e), pick(P4.lz, e), pick(P3.sg, e), omega);
+      }
     }
     // stage 2: sweep-1 black on plane k+2 from the sweep-1 red values
     if (k + 2 >= k0 - 2 && k + 2 < k1 + 2) {
       const int e = red_e(k + 2) ^ 1;
-      const T xe = e == 0 ? r1b : sm.r1[q][r][pe];
-      const T xw = e == 0 ? sm.r1[q][r][pw] : r1b;
-      const T v = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][rn][p], sm.r1[q][rs][p], r1n,
-                                r1a, pick(P2.lx, e), e == 0 ? P2.lx[1] : P2.lxh, pick(P2.ly, e),
-                                pick(P2.lyh, e), pick(P2.lz, e), pick(P3.lz, e), pick(P2.sg, e),
-                                omega);
-      b1n = (e ? in2[1] : in2[0]) ? v : T(0);
+      if (e ? in2[1] : in2[0]) {
+        const T xe = e == 0 ? r1b : sm.r1[q][r][pe];
+        const T xw = e == 0 ? sm.r1[q][r][pw] : r1b;
+        b1n = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][rn][p], sm.r1[q][rs][p], r1n, r1a,
+                            pick(P2.lx, e), e == 0 ? P2.lx[1] : P2.lxh, pick(P2.ly, e),
+                            pick(P2.lyh, e), pick(P2.lz, e), pick(P3.lz, e), pick(P2.sg, e),
+                            omega);
+      }
     }
     // stage 3: sweep-2 red on plane k+1 from the sweep-1 values
     if (k + 1 >= k0 - 1 && k + 1 < k1 + 1) {
       const int e = red_e(k + 1);
-      const T xe = e == 0 ? b1b : sm.b1[q][r][pe];
-      const T xw = e == 0 ? sm.b1[q][r][pw] : b1b;
-      const T v = relax_cell<T>(r1a, xe, xw, sm.b1[q][rn][p], sm.b1[q][rs][p], b1n, b1a,
-                                pick(P1.lx, e), e == 0 ? P1.lx[1] : P1.lxh, pick(P1.ly, e),
-                                pick(P1.lyh, e), pick(P1.lz, e), pick(P2.lz, e), pick(P1.sg, e),
-                                omega);
-      r2n = (e ? in1[1] : in1[0]) ? v : T(0);
+      if (e ? in1[1] : in1[0]) {
+        const T xe = e == 0 ? b1b : sm.b1[q][r][pe];
+        const T xw = e == 0 ? sm.b1[q][r][pw] : b1b;
+        r2n = relax_cell<T>(r1a, xe, xw, sm.b1[q][rn][p], sm.b1[q][rs][p], b1n, b1a,
+                            pick(P1.lx, e), e == 0 ? P1.lx[1] : P1.lxh, pick(P1.ly, e),
+                            pick(P1.lyh, e), pick(P1.lz, e), pick(P2.lz, e), pick(P1.sg, e),
+                            omega);
+      }
     }
     // stage 4: sweep-2 black on plane k; store plane k of W
-    if (k >= k0 && k < k1) {
+    if (k >= k0 && k < k1 && out_ok) {
       const int e = red_e(k) ^ 1;
       const T xe = e == 0 ? r2b : sm.r2[q][r][pe];
       const T xw = e == 0 ? sm.r2[q][r][pw] : r2b;
@@ -255,7 +265,7 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
                                  pick(P0.lx, e), e == 0 ? P0.lx[1] : P0.lxh, pick(P0.ly, e),
                                  pick(P0.lyh, e), pick(P0.lz, e), pick(P1.lz, e), pick(P0.sg, e),
                                  omega);
-      if (out_ok) {
+      {
         const long long idx = (long long)k * g.sz + (long long)y * g.sy + xa;
         const T o0 = e == 0 ? b2 : r2b, o1 = e == 0 ? r2b : b2;
         if constexpr (sizeof(T) == 4)
@@ -269,7 +279,7 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     P1 = P2;
     P2 = P3;
     P3 = P4;
-    s2_take<T>(P4, cur, prol);  // plane k+5
+    s2_take<T, PROL>(P4, cur);  // plane k+5
     r1a = r1b;
     r1b = r1n;
     b1a = b1b;
@@ -300,7 +310,7 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
 
 // Two sweeps in one pass: X[rd] = sweep(sweep(X[rs] (+ P x_c))), at global
 // scope so that its symbol carries no namespace.
-template <typename T, typename TL, int TY>
+template <typename T, typename TL, int TY, bool PROL>
 __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
     gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
     const TL* __restrict__ L, const T* __restrict__ xc, const uint8_t* __restrict__ active,
@@ -312,6 +322,6 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
   const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);
   const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
   const int k0 = tz * kchunk;
-  gmg::rb_sweep2_tile<T, TL, TY>(sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0,
+  gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0,
                                  min(g.nz, k0 + kchunk), (T)(*omega_p));
 }
