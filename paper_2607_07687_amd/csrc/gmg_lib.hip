@@ -105,6 +105,35 @@ __global__ __launch_bounds__(BT) void k_residual(Geom g, Roles<T> X, int role,
   }
 }
 
+// Start of a solve, one pass over x0, sigma and L: per-block partials of
+// ||sigma||^2 over the active cells (pa) and of ||sigma - A x0||^2 (pb), in
+// the order of k_masked_sumsq and k_residual (active <=> D != 0, as in the
+// mask), so both norms are bitwise those of the two separate kernels.
+template <typename T, typename TL>
+__global__ __launch_bounds__(BT) void k_start_norms(Geom g, const T* __restrict__ x,
+                                                    const T* __restrict__ sigma,
+                                                    const TL* __restrict__ L, double* pa,
+                                                    double* pb, int kchunk) {
+  const int k0 = blockIdx.z * kchunk;
+  double as = 0.0, ar = 0.0;
+  walk_column<T, TL>(g, x, L, blockIdx.x * BX + threadIdx.x, blockIdx.y * BY + threadIdx.y, k0,
+                     min(g.nz, k0 + kchunk), [&](long long idx, T ax, T D) {
+                       const T sv = sigma[idx];
+                       const T rv = (D != T(0)) ? sv - ax : T(0);
+                       if (D != T(0)) as += (double)sv * (double)sv;
+                       ar += (double)rv * (double)rv;
+                     });
+  const int tid = threadIdx.x + BX * threadIdx.y;
+  const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const double ss = block_sum(as, tid, BT);
+  __syncthreads();
+  const double sr = block_sum(ar, tid, BT);
+  if (tid == 0) {
+    pa[blk] = ss;
+    pb[blk] = sr;
+  }
+}
+
 // Sum of v^2 over active cells (mask != 0), per-block partials, z-chunked.
 template <typename T>
 __global__ __launch_bounds__(BT) void k_masked_sumsq(Geom g, const T* __restrict__ v,
@@ -275,8 +304,18 @@ __global__ __launch_bounds__(BT) void k_active(Geom g, const TL* __restrict__ L,
 // Deterministic sum of n partials (single block, fixed order).
 __device__ double reduce_partials(const double* p, long long n) {
   const int tid = threadIdx.x;
+  const long long st = blockDim.x;
   double s = 0.0;
-  for (long long q = tid; q < n; q += blockDim.x) s += p[q];
+  long long q = tid;
+  // eight loads in flight per thread, added in index order as one at a time
+  for (; q + 7 * st < n; q += 8 * st) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[q + u * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < n; q += st) s += p[q];
   return block_sum(s, tid, blockDim.x);
 }
 
@@ -1703,10 +1742,9 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
   int rounds = 0;
   DISPATCH_CYCLE(h, {
     T* xa = (T*)x;
-    const Roles<T> X0{{xa, (T*)h->w[0], (T*)h->w[1]}, nullptr};
-    hipLaunchKernelGGL((k_masked_sumsq<T>), red_grid(lv.g), kBlock, 0, h->s, lv.g,
-                       (const T*)sigma, lv.active, h->partials, kResChunk);
-    enq_resnorm<T, TL>(h, X0, 0, (const T*)sigma, (const TL*)lv.L, nullptr, h->maxpart, nullptr);
+    hipLaunchKernelGGL((k_start_norms<T, TL>), red_grid(lv.g), kBlock, 0, h->s, lv.g, xa,
+                       (const T*)sigma, (const TL*)lv.L, h->partials, h->partials + h->maxpart,
+                       kResChunk);
     hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, h->s, h->partials, np,
                        h->partials + h->maxpart, np, h->st, rtol, (int)max_cycles, h->p.omega0,
                        nullptr);
