@@ -69,6 +69,17 @@ __device__ __forceinline__ void walk_column(const Geom& g, const T* __restrict__
                        [&](long long idx, T ax, T D, T) { f(idx, ax, D); });
 }
 
+// The same with sigma loaded alongside each plane: f(idx, ax, D, sigma(idx)).
+template <typename T, typename TL, typename F>
+__device__ __forceinline__ void walk_column_s(const Geom& g, const T* __restrict__ x,
+                                              const T* __restrict__ sigma,
+                                              const TL* __restrict__ L, int i, int j, int k0,
+                                              int k1, F&& f) {
+  walk_column_vs<T, TL>(g, [&](long long q) { return x[q]; },
+                        [&](long long q) { return sigma[q]; }, L, i, j, k0, k1,
+                        [&](long long idx, T ax, T D, T, T sv) { f(idx, ax, D, sv); });
+}
+
 // r = sigma - A x on active cells (0 elsewhere) for column (i, j) over the
 // z-planes [k0, k1); optional store of r; returns the column's sum of r^2.
 template <typename T, typename TL>
@@ -77,8 +88,8 @@ __device__ __forceinline__ double residual_column(const Geom& g, const T* __rest
                                                   const TL* __restrict__ L, T* __restrict__ r,
                                                   int i, int j, int k0, int k1) {
   double acc = 0.0;
-  walk_column<T, TL>(g, x, L, i, j, k0, k1, [&](long long idx, T ax, T D) {
-    const T rv = (D != T(0)) ? sigma[idx] - ax : T(0);
+  walk_column_s<T, TL>(g, x, sigma, L, i, j, k0, k1, [&](long long idx, T ax, T D, T sv) {
+    const T rv = (D != T(0)) ? sv - ax : T(0);
     if (r) r[idx] = rv;
     acc += (double)rv * (double)rv;
   });
@@ -116,13 +127,13 @@ __global__ __launch_bounds__(BT) void k_start_norms(Geom g, const T* __restrict_
                                                     double* pb, int kchunk) {
   const int k0 = blockIdx.z * kchunk;
   double as = 0.0, ar = 0.0;
-  walk_column<T, TL>(g, x, L, blockIdx.x * BX + threadIdx.x, blockIdx.y * BY + threadIdx.y, k0,
-                     min(g.nz, k0 + kchunk), [&](long long idx, T ax, T D) {
-                       const T sv = sigma[idx];
-                       const T rv = (D != T(0)) ? sv - ax : T(0);
-                       if (D != T(0)) as += (double)sv * (double)sv;
-                       ar += (double)rv * (double)rv;
-                     });
+  walk_column_s<T, TL>(g, x, sigma, L, blockIdx.x * BX + threadIdx.x,
+                       blockIdx.y * BY + threadIdx.y, k0, min(g.nz, k0 + kchunk),
+                       [&](long long, T ax, T D, T sv) {
+                         const T rv = (D != T(0)) ? sv - ax : T(0);
+                         if (D != T(0)) as += (double)sv * (double)sv;
+                         ar += (double)rv * (double)rv;
+                       });
   const int tid = threadIdx.x + BX * threadIdx.y;
   const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const double ss = block_sum(as, tid, BT);
@@ -169,9 +180,10 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BX], const Geom& gf,
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
   T acc = T(0);
-  walk_column<T, TL>(gf, x, L, i, j, K * cz, K * cz + cz, [&](long long idx, T ax, T D) {
-    if (D != T(0)) acc += sigma[idx] - ax;
-  });
+  walk_column_s<T, TL>(gf, x, sigma, L, i, j, K * cz, K * cz + cz,
+                       [&](long long, T ax, T D, T sv) {
+                         if (D != T(0)) acc += sv - ax;
+                       });
   if (cx == 2) acc += __shfl_xor(acc, 1, 64);
   if (cy == 2) {
     rows[ty][tx] = acc;

@@ -59,9 +59,10 @@ __global__ __launch_bounds__(BT) void k_pcg_start(Geom g, Roles<T> X, int role,
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
   const int k0 = blockIdx.z * kchunk;
   double arz = 0.0, arr = 0.0;
-  walk_column_v<T, TL>(g, [&](long long q) { return x[q]; }, L, i, j, k0, min(g.nz, k0 + kchunk),
-                       [&](long long idx, T ax, T D, T) {
-                         const T rv = (D != T(0)) ? ax - sigma[idx] : T(0);
+  walk_column_vs<T, TL>(g, [&](long long q) { return x[q]; },
+                        [&](long long q) { return sigma[q]; }, L, i, j, k0,
+                        min(g.nz, k0 + kchunk), [&](long long idx, T ax, T D, T, T sv) {
+                         const T rv = (D != T(0)) ? ax - sv : T(0);
                          const T zv = (D != T(0)) ? rv / s[idx] : T(0);
                          r[idx] = rv;
                          z[idx] = zv;

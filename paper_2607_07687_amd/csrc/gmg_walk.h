@@ -6,14 +6,23 @@
 namespace gmg {
 
 // Walk column (i, j) of the field v (v(idx) gives its value at a cell) over
-// the z-planes [k0, k1) and call f(idx, ax, D, vc) for each cell with
-// ax = (A v)(cell), D its diagonal and vc = v(cell), computed with the same
+// the z-planes [k0, k1) and call f(idx, ax, D, vc, sd) for each cell with
+// ax = (A v)(cell), D its diagonal, vc = v(cell) and sd = side(idx) (a second
+// per-cell value the caller needs, e.g. sigma), computed with the same
 // arithmetic, term by term, as stencil_Ax.  The x and y neighbour offsets are
 // fixed for the column, and the z-neighbours and z-faces roll through
 // registers as the walk goes up.
-template <typename T, typename TL, typename V, typename F>
-__device__ __forceinline__ void walk_column_v(const Geom& g, V&& v, const TL* __restrict__ L, int i,
-                                              int j, int k0, int k1, F&& f) {
+//
+// The loads of plane k+1 are issued before plane k is computed, so each wave
+// keeps two planes of loads in flight (the walk is otherwise one memory
+// latency per plane); the last plane is peeled off the loop.  Every load is
+// issued on every path (a missing neighbour's offset points at the cell
+// itself) and the value selected afterwards, so no branch forces the
+// compiler to wait for all of them.
+template <typename T, typename TL, typename V, typename S, typename F>
+__device__ __forceinline__ void walk_column_vs(const Geom& g, V&& v, S&& side,
+                                               const TL* __restrict__ L, int i, int j, int k0,
+                                               int k1, F&& f) {
   if (i >= g.nx || j >= g.ny || k0 >= k1) return;
   const Nb nx = neighbours(i, g.nx, g.px, 1);
   const Nb ny = neighbours(j, g.ny, g.py, g.sy);
@@ -21,40 +30,76 @@ __device__ __forceinline__ void walk_column_v(const Geom& g, V&& v, const TL* __
   const TL* __restrict__ Lz = L + 2 * g.n;
   const long long base = (long long)j * g.sy + i;
   const long long top = (long long)(g.nz - 1) * g.sz;
+  // the loads of one plane
+  struct Plane {
+    T vt, lzt, lmx, lhx, ve, vw, lmy, lhy, vn, vs, sd;
+  };
+  auto load = [&](int k, Plane& p) {
+    const long long id = (long long)k * g.sz + base;
+    const long long hi = (k + 1 < g.nz) ? id + g.sz : base;
+    p.vt = v(hi);
+    p.lzt = ldL<T>(Lz, hi);
+    p.lmx = ldL<T>(L, id);
+    p.lhx = ldL<T>(L, id + nx.hi);
+    p.ve = v(id + nx.hi);
+    p.vw = v(id + nx.lo);
+    p.lmy = ldL<T>(Ly, id);
+    p.lhy = ldL<T>(Ly, id + ny.hi);
+    p.vn = v(id + ny.hi);
+    p.vs = v(id + ny.lo);
+    p.sd = side(id);
+  };
   long long idx = (long long)k0 * g.sz + base;
   T xc = v(idx);
   T xb = (k0 > 0) ? v(idx - g.sz) : (g.pz ? v(top + base) : xc);  // z low neighbour
   T lzm = ldL<T>(Lz, idx);
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k, idx += g.sz) {
+  // plane k from its loads, then roll the z-neighbours up
+  auto plane = [&](int k, const Plane& cur) {
     // z high neighbour and face: next plane, wrap, or (wall) self with face 0
-    const bool zin = k + 1 < g.nz;
-    const long long hi = zin ? idx + g.sz : base;
-    const T xt = (zin || g.pz) ? v(hi) : xc;
-    const T lzp = (zin || g.pz) ? ldL<T>(Lz, hi) : T(0);
+    const bool zok = k + 1 < g.nz || g.pz;
+    const T xt = zok ? cur.vt : xc;
+    const T lzp = zok ? cur.lzt : T(0);
     T ax = T(0), s = T(0);
     {
-      const T lm = ldL<T>(L, idx);
-      const T lp = nx.hi_ok ? ldL<T>(L, idx + nx.hi) : T(0);
-      ax += lp * (v(idx + nx.hi) - xc);
-      ax += lm * (v(idx + nx.lo) - xc);
+      const T lm = cur.lmx;
+      const T lp = nx.hi_ok ? cur.lhx : T(0);
+      ax += lp * (cur.ve - xc);
+      ax += lm * (cur.vw - xc);
       s += lm + lp;
     }
     {
-      const T lm = ldL<T>(Ly, idx);
-      const T lp = ny.hi_ok ? ldL<T>(Ly, idx + ny.hi) : T(0);
-      ax += lp * (v(idx + ny.hi) - xc);
-      ax += lm * (v(idx + ny.lo) - xc);
+      const T lm = cur.lmy;
+      const T lp = ny.hi_ok ? cur.lhy : T(0);
+      ax += lp * (cur.vn - xc);
+      ax += lm * (cur.vs - xc);
       s += lm + lp;
     }
     ax += lzp * (xt - xc);
     ax += lzm * (xb - xc);
     s += lzm + lzp;
-    f(idx, ax, -s, xc);
+    f(idx, ax, -s, xc, cur.sd);
     xb = xc;
     xc = xt;
     lzm = lzp;
+    idx += g.sz;
+  };
+  Plane cur, nxt;
+  load(k0, cur);
+  int k = k0;
+  for (; k + 1 < k1; ++k) {
+    load(k + 1, nxt);
+    plane(k, cur);
+    cur = nxt;
   }
+  plane(k, cur);
+}
+
+// walk_column_vs without a side value: f(idx, ax, D, vc).
+template <typename T, typename TL, typename V, typename F>
+__device__ __forceinline__ void walk_column_v(const Geom& g, V&& v, const TL* __restrict__ L, int i,
+                                              int j, int k0, int k1, F&& f) {
+  walk_column_vs<T, TL>(g, v, [](long long) { return T(0); }, L, i, j, k0, k1,
+                        [&](long long idx, T ax, T D, T vc, T) { f(idx, ax, D, vc); });
 }
 
 }  // namespace gmg
