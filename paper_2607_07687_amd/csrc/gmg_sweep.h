@@ -150,6 +150,7 @@ struct PlaneRegs {
   T s[C::NS][VEC], sg[C::NF][VEC], lx[C::NF][VEC], ly[C::NY][VEC], lz[C::NF][VEC];
   T pc[C::NS][VEC];        // coarse correction of each S element (prolongation only)
   uint32_t pa[C::NS];      // bit e set: element e is active and takes the correction
+  uint32_t in;             // bit u (S), 8 + u (sigma, Lx, Lz), 16 + u (Ly): item in the domain
 };
 
 template <typename T, typename TL, int TY, int VEC>
@@ -172,23 +173,29 @@ __device__ __forceinline__ void fetch_plane(PlaneRegs<T, TY, VEC>& rg,
                                             const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
                                             const LoadPlan<SweepCfg<TY, VEC>::NY>& py) {
   using C = SweepCfg<TY, VEC>;
+  static_assert(C::NS <= 8 && C::NF <= 8 && C::NY <= 8, "item bits");
   const Geom& g = a.g;
-  const int kk = wrap_coord(k, g.nz, g.pz);
-  const long long po = (long long)kk * g.sz;
+  const int kw = wrap_coord(k, g.nz, g.pz);
+  const long long po = (long long)(kw >= 0 ? kw : 0) * g.sz;
+  // Every item's main loads are issued, at a clamped in-domain address when
+  // the item lies outside a wall (store_plane zeroes those), so the number of
+  // loads in flight is the same on every path and the compiler waits only
+  // for the plane being stored.
+  rg.in = 0;
 #pragma unroll
   for (int u = 0; u < C::NS; ++u) {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) rg.s[u][e] = T(0);
     rg.pa[u] = 0;
-    if (ps.use[u] && ps.ii[u] >= 0 && ps.jj[u] >= 0 && kk >= 0) {
-      const int ii = ps.ii[u], jj = ps.jj[u];
+    const bool in = ps.use[u] && ps.ii[u] >= 0 && ps.jj[u] >= 0 && kw >= 0;
+    rg.in |= (uint32_t)in << u;
+    {
+      const int ii = in ? ps.ii[u] : 0, jj = in ? ps.jj[u] : 0;
       const long long idx = po + (long long)jj * g.sy + ii;
       ldv<T, VEC>(a.S, idx, rg.s[u]);
       if (a.xc != nullptr) {
         // Issued unconditionally (every in-domain cell has a coarse parent)
         // and applied when the plane is written to LDS, so no load waits on
         // another inside the prefetch.  Factors are 1 or 2: shift by c >> 1.
-        const long long cb = (long long)(kk >> (a.cz >> 1)) * a.gc.sz +
+        const long long cb = (long long)((kw >= 0 ? kw : 0) >> (a.cz >> 1)) * a.gc.sz +
                              (long long)(jj >> (a.cy >> 1)) * a.gc.sy;
         if constexpr (VEC == 2)
           rg.pa[u] = *reinterpret_cast<const uint16_t*>(a.active + idx);
@@ -201,21 +208,19 @@ __device__ __forceinline__ void fetch_plane(PlaneRegs<T, TY, VEC>& rg,
   }
 #pragma unroll
   for (int u = 0; u < C::NF; ++u) {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) rg.sg[u][e] = rg.lx[u][e] = rg.lz[u][e] = T(0);
-    if (pf.use[u] && pf.ii[u] >= 0 && pf.jj[u] >= 0 && kk >= 0) {
-      const long long idx = po + (long long)pf.jj[u] * g.sy + pf.ii[u];
-      ldv<T, VEC>(a.sigma, idx, rg.sg[u]);
-      ldLv<T, VEC>(a.L, idx, rg.lx[u]);
-      ldLv<T, VEC>(a.L + 2 * g.n, idx, rg.lz[u]);
-    }
+    const bool in = pf.use[u] && pf.ii[u] >= 0 && pf.jj[u] >= 0 && kw >= 0;
+    rg.in |= (uint32_t)in << (8 + u);
+    const long long idx = po + (long long)(in ? pf.jj[u] : 0) * g.sy + (in ? pf.ii[u] : 0);
+    ldv<T, VEC>(a.sigma, idx, rg.sg[u]);
+    ldLv<T, VEC>(a.L, idx, rg.lx[u]);
+    ldLv<T, VEC>(a.L + 2 * g.n, idx, rg.lz[u]);
   }
 #pragma unroll
   for (int u = 0; u < C::NY; ++u) {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) rg.ly[u][e] = T(0);
-    if (py.use[u] && py.ii[u] >= 0 && py.jj[u] >= 0 && kk >= 0)
-      ldLv<T, VEC>(a.L + g.n, po + (long long)py.jj[u] * g.sy + py.ii[u], rg.ly[u]);
+    const bool in = py.use[u] && py.ii[u] >= 0 && py.jj[u] >= 0 && kw >= 0;
+    rg.in |= (uint32_t)in << (16 + u);
+    ldLv<T, VEC>(a.L + g.n, po + (long long)(in ? py.jj[u] : 0) * g.sy + (in ? py.ii[u] : 0),
+                 rg.ly[u]);
   }
 }
 
@@ -226,29 +231,37 @@ __device__ __forceinline__ void store_plane(SweepSmem<T, TY>& sm, int slot, bool
                                             const LoadPlan<SweepCfg<TY, VEC>::NF>& pf,
                                             const LoadPlan<SweepCfg<TY, VEC>::NY>& py) {
   using C = SweepCfg<TY, VEC>;
+  // items outside a wall were loaded at a clamped address: store zeros
 #pragma unroll
   for (int u = 0; u < C::NS; ++u)
-    if (ps.use[u])
+    if (ps.use[u]) {
+      const bool in = (rg.in >> u) & 1u;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         // active-mask bytes: element e is byte e of pa (nonzero = active)
         const bool corr = prol && ((rg.pa[u] >> (8 * e)) & 0xFFu) != 0;
-        sm.s[slot][ps.row[u]][ps.col[u] + e] = corr ? rg.s[u][e] + rg.pc[u][e] : rg.s[u][e];
+        const T v = corr ? rg.s[u][e] + rg.pc[u][e] : rg.s[u][e];
+        sm.s[slot][ps.row[u]][ps.col[u] + e] = in ? v : T(0);
       }
+    }
 #pragma unroll
   for (int u = 0; u < C::NF; ++u)
-    if (pf.use[u])
+    if (pf.use[u]) {
+      const bool in = (rg.in >> (8 + u)) & 1u;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        sm.sg[slot][pf.row[u]][pf.col[u] + e] = rg.sg[u][e];
-        sm.lx[slot][pf.row[u]][pf.col[u] + e] = rg.lx[u][e];
-        sm.lz[slot][pf.row[u]][pf.col[u] + e] = rg.lz[u][e];
+        sm.sg[slot][pf.row[u]][pf.col[u] + e] = in ? rg.sg[u][e] : T(0);
+        sm.lx[slot][pf.row[u]][pf.col[u] + e] = in ? rg.lx[u][e] : T(0);
+        sm.lz[slot][pf.row[u]][pf.col[u] + e] = in ? rg.lz[u][e] : T(0);
       }
+    }
 #pragma unroll
   for (int u = 0; u < C::NY; ++u)
-    if (py.use[u])
+    if (py.use[u]) {
+      const bool in = (rg.in >> (16 + u)) & 1u;
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) sm.ly[slot][py.row[u]][py.col[u] + e] = rg.ly[u][e];
+      for (int e = 0; e < VEC; ++e) sm.ly[slot][py.row[u]][py.col[u] + e] = in ? rg.ly[u][e] : T(0);
+    }
 }
 
 // Relaxed Gauss-Seidel update of a red cell from S (rows of the S ring are
