@@ -336,7 +336,8 @@ def main():
     # warm-up, then K timed cycles of the adaptive solve
     tiles = AT.tune(h, x, sd, cache=None)  # timed sweep tiles per level (setup, untimed)
     log("tiles " + ", ".join(f"L{t['level']}:{t['ty']}x{t['kchunk']}" +
-                             (f"+pass{t['pair_kchunk']}" if t.get("pair_kchunk") else "")
+                             (f"+pass{t.get('pair_ty', 16)}x{t['pair_kchunk']}"
+                              if t.get("pair_kchunk") else "")
                              for t in tiles))
     x.zero_()
     G.gmg_solve(h, x, sd, 0.0, max(1, args.warmup))
@@ -391,7 +392,8 @@ def main():
     achieved = alg_bytes / (launch * 1e-3) / 1e9
     h.close()
     if pair_kc:
-        kname = "k_rb_sweep2<float,float,8> (level-0 two-sweep pass, 2 sweeps per launch)"
+        kname = (f"k_rb_sweep2<float,float,{tiles[0].get('pair_ty', 16)},false> "
+                 "(level-0 two-sweep pass, 2 sweeps per launch)")
     elif tiles[0]["ty"] != 1:
         kname = f"k_rb_sweep<float,float,{tiles[0]['ty']},2> (level-0 fused sweep)"
     else:
@@ -418,7 +420,8 @@ def main():
         "final_rel_residual": rn / sn,
         "setup_ms": setup_ms,
         "tiles": [{"level": t["level"], "ty": t["ty"], "kchunk": t["kchunk"],
-                   "pass_kchunk": t.get("pair_kchunk", 0)} for t in tiles],
+                   "pass_ty": t.get("pair_ty", 16), "pass_kchunk": t.get("pair_kchunk", 0)}
+                  for t in tiles],
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kind),

@@ -336,14 +336,16 @@ typedef struct gmg_tune_report {
   int32_t ty_default[32], kchunk_default[32];
   double us[32], us_default[32];
   int32_t pair_kchunk[32];  /* z-chunk of the two-sweep pass kept, 0 = none  */
-  double us_pair[32];       /* best time of one two-sweep pass (0: not tried) */
+  double us_pair[32];       /* mean time of one two-sweep pass without and with
+                               the folded correction (0: not tried)          */
+  int32_t pair_ty[32];      /* tile rows of that pass (8 or 16)               */
 } gmg_tune_report;
 
 /* Time `reps` sweeps of every level for each candidate (fused with ty in
  * {8, 4} and kchunk in {2, 4, ..., 64} up to nz, FP64 cycles: ty 4; and the
  * split half-sweeps, ty 1), and where pair_sweeps allows, `reps` two-sweep
- * passes with kchunk in {default, 4, 8, ..., 256} (a pass is kept if it beats
- * two of the chosen sweeps), with
+ * passes with ty in {16, 8} and kchunk in {default, 4, 8, ..., 256} (a pass
+ * is kept if it beats two of the chosen sweeps), with
  * HIP events on the handle's stream, and keep the fastest per level.  x and
  * sigma are level-0 device arrays (dtype == cycle_dtype) used as the sweep's
  * input (x is overwritten with smoothed values; coarse levels use internal
@@ -358,12 +360,13 @@ gmg_status gmg_autotune(gmg_handle* h, void* x, const void* sigma, int32_t reps,
  * not use the deferred norm. */
 gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk);
 
-/* Run the smoothing steps of one level with two-sweep passes of kchunk
- * z-planes per workgroup (kchunk = 0: separate sweeps).  GMG_EINVAL if the
- * handle's parameters do not allow passes (pair_sweeps 0, FP64 cycles, the
- * PCG smoother or an odd nx) or kchunk is outside [0, nz].  Results do not
- * depend on the choice.  Recorded graphs are dropped. */
-gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t kchunk);
+/* Run the smoothing steps of one level with two-sweep passes on tiles of
+ * 64 x ty cells (ty 8 or 16) with kchunk z-planes per workgroup (kchunk = 0:
+ * separate sweeps, ty ignored).  GMG_EINVAL if the handle's parameters do not
+ * allow passes (pair_sweeps 0, FP64 cycles, the PCG smoother or an odd nx),
+ * ty is not 8 or 16, or kchunk is outside [0, nz].  Results do not depend on
+ * the choice.  Recorded graphs are dropped. */
+gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk);
 
 /* Thread-local description of the last error ("" if none). */
 const char* gmg_last_error(void);

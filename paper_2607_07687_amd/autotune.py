@@ -35,18 +35,18 @@ def tune(h, x, sigma, dtype="f32", storage="f32", cache=None, reps=5):
             table = json.load(f)
     nl = G.gmg_num_levels(h)
     keys = [_key(arch, G.gmg_level_shape(h, l)[0], dtype, storage) for l in range(nl)]
-    if all(k in table and "pair_kchunk" in table[k] for k in keys):
+    if all(k in table and "pair_ty" in table[k] for k in keys):
         for l, k in enumerate(keys):
             G.gmg_set_tiles(h, l, table[k]["ty"], table[k]["kchunk"])
             try:
-                G.gmg_set_pair_sweeps(h, l, table[k]["pair_kchunk"])
+                G.gmg_set_pair_sweeps(h, l, table[k]["pair_kchunk"], table[k]["pair_ty"])
             except G.GMGError:  # this handle's parameters do not allow passes
                 G.gmg_set_pair_sweeps(h, l, 0)
         return [dict(level=l, **table[k], cached=True) for l, k in enumerate(keys)]
     res = G.gmg_autotune(h, x, sigma, reps)
     for r, k in zip(res, keys):
         table[k] = dict(ty=r["ty"], kchunk=r["kchunk"], us=r["us"],
-                        pair_kchunk=r["pair_kchunk"], us_pair=r["us_pair"])
+                        pair_kchunk=r["pair_kchunk"], pair_ty=r["pair_ty"], us_pair=r["us_pair"])
     if cache:
         d = os.path.dirname(cache)
         if d:

@@ -571,7 +571,7 @@ __global__ __launch_bounds__(BT) void k_ir_update(Geom g, double* __restrict__ x
 namespace {
 
 constexpr int kMaxLevels = 32;
-constexpr int kPairTY = 8;  // tile rows of the two-sweep pass
+constexpr int kPairTYDefault = 16;  // tile rows of the two-sweep pass by default
 constexpr int kTailMaxCells = 32768;
 constexpr int kResChunk = 16;  // z-planes per block in the norm reductions
 
@@ -586,6 +586,7 @@ struct Level {
   int ty;          // tile height of the fused sweep (rows of 64 cells)
   int pair_kc;     // > 0: two consecutive sweeps run as one two-sweep pass
                    // with this z-chunk; 0: separate sweeps
+  int pair_ty;     // tile rows of the two-sweep pass (8 or 16)
 };
 
 size_t dsize(int dt) { return dt == GMG_F64 ? 8 : (dt == GMG_BF16 ? 2 : 4); }
@@ -630,8 +631,8 @@ bool pair_capable(const gmg_params& p, const Geom& g) {
 // z-chunk of the two-sweep pass: one workgroup per CU (its register
 // footprint allows one), as many chunks as fill the 256 CUs, at least 2
 // planes per chunk.
-int pair_kchunk(const Geom& g) {
-  const long long tiles = (long long)((g.nx + S2_TX - 1) / S2_TX) * ((g.ny + kPairTY - 1) / kPairTY);
+int pair_kchunk(const Geom& g, int ty) {
+  const long long tiles = (long long)((g.nx + S2_TX - 1) / S2_TX) * ((g.ny + ty - 1) / ty);
   const long long chunks = std::max<long long>(1, kCUs / std::max<long long>(1, tiles));
   const int kc = (int)((g.nz + chunks - 1) / chunks);
   return std::max(std::min(2, g.nz), kc);
@@ -769,21 +770,28 @@ static void launch_split(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd
 // sweeps; rd != rs.
 template <typename T, typename TL>
 static void launch_pair(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd, const T* sigma,
-                        const T* xc, const int* done, int kchunk) {
+                        const T* xc, const int* done, int ty, int kchunk) {
   if constexpr (std::is_same<T, float>::value) {
     const Level& lv = h->lev[l];
     const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
-    const dim3 grid(((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + kPairTY - 1) / kPairTY) *
-                    ((lv.g.nz + kchunk - 1) / kchunk));
     const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
-    if (xc != nullptr)
-      hipLaunchKernelGGL((k_rb_sweep2<T, TL, kPairTY, true>), grid, dim3(S2Cfg<kPairTY>::NTB), 0,
-                         h->s, lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy,
-                         cz, kchunk, &h->st->omega, done);
+    auto go = [&](auto tyc) {
+      constexpr int TY = decltype(tyc)::value;
+      const dim3 grid(((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + TY - 1) / TY) *
+                      ((lv.g.nz + kchunk - 1) / kchunk));
+      if (xc != nullptr)
+        hipLaunchKernelGGL((k_rb_sweep2<T, TL, TY, true>), grid, dim3(S2Cfg<TY>::NTB), 0, h->s,
+                           lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz,
+                           kchunk, &h->st->omega, done);
+      else
+        hipLaunchKernelGGL((k_rb_sweep2<T, TL, TY, false>), grid, dim3(S2Cfg<TY>::NTB), 0, h->s,
+                           lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz,
+                           kchunk, &h->st->omega, done);
+    };
+    if (ty == 16)
+      go(std::integral_constant<int, 16>{});
     else
-      hipLaunchKernelGGL((k_rb_sweep2<T, TL, kPairTY, false>), grid, dim3(S2Cfg<kPairTY>::NTB), 0,
-                         h->s, lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy,
-                         cz, kchunk, &h->st->omega, done);
+      go(std::integral_constant<int, 8>{});
   }
 }
 
@@ -813,7 +821,7 @@ static int enq_sweeps(gmg_handle* h, int l, const Roles<T>& X, int r, const T* s
     const int rd = next_role(l, r);
     const T* c = (s == 0) ? xc : nullptr;
     if (nu - s >= 2 && lv.pair_kc > 0) {
-      launch_pair<T, TL>(h, l, X, r, rd, sigma, c, done, lv.pair_kc);
+      launch_pair<T, TL>(h, l, X, r, rd, sigma, c, done, lv.pair_ty, lv.pair_kc);
       s += 2;
     } else {
       enq_sweep<T, TL>(h, l, X, r, rd, sigma, c, done);
@@ -1246,7 +1254,8 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
     lv.kchunk = sweep_kchunk(lv.g, lv.ty, p->cycle_dtype == GMG_F64 ? 8 : 4);
     // two-sweep passes: on by default at level 0, where a pass streams the
     // largest arrays; the autotuner decides for the other levels
-    lv.pair_kc = (l == 0 && pair_capable(*p, lv.g)) ? pair_kchunk(lv.g) : 0;
+    lv.pair_ty = kPairTYDefault;
+    lv.pair_kc = (l == 0 && pair_capable(*p, lv.g)) ? pair_kchunk(lv.g, lv.pair_ty) : 0;
   }
   maxpart = nblocks(red_grid(h->lev[0].g));
   h->maxpart = maxpart;
@@ -1456,30 +1465,50 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
     rep->kchunk[l] = bkc;
     rep->us[l] = 1e3 * best;
     rep->us_default[l] = 1e3 * deft;
-    // two-sweep pass: kept where one pass beats two of the chosen sweeps
+    // two-sweep pass: kept where one pass beats two of the chosen sweeps.  A
+    // level's passes run once without and (below the coarsest level) once
+    // with the folded correction per cycle, so a candidate's cost is the mean
+    // of the two (the coarse level's iterate buffer serves as the correction
+    // operand; only the time matters here).
     rep->pair_kchunk[l] = 0;
+    rep->pair_ty[l] = lv.pair_ty;
     rep->us_pair[l] = 0.0;
     if (std::is_same<T, float>::value && pair_capable(h->p, lv.g)) {
-      const int pkcs[8] = {pair_kchunk(lv.g), 4, 8, 16, 32, 64, 128, 256};
+      const T* xc = (l + 1 < h->nlev) ? (const T*)h->lev[l + 1].x[0] : nullptr;
       float pbest = 1e30f;
-      int pkc = 0;
-      for (int kc : pkcs) {
-        if (kc > lv.g.nz) continue;
-        launch_pair<T, TL>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);  // warm-up
-        HIP_TRY(hipEventRecord(e0, h->s));
-        for (int r = 0; r < reps; ++r) launch_pair<T, TL>(h, l, X, 0, 1, sg, nullptr, nullptr, kc);
-        HIP_TRY(hipEventRecord(e1, h->s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        ms /= reps;
-        if (ms < pbest) {
-          pbest = ms;
-          pkc = kc;
+      int pkc = 0, pty = lv.pair_ty;
+      for (int ty : {16, 8}) {
+        const int pkcs[8] = {pair_kchunk(lv.g, ty), 4, 8, 16, 32, 64, 128, 256};
+        for (int kc : pkcs) {
+          if (kc > lv.g.nz) continue;
+          float cost = 0.f;
+          for (int fold = 0; fold < 2; ++fold) {
+            const T* c = fold ? xc : nullptr;
+            if (fold && c == nullptr) {
+              cost *= 2.f;
+              break;
+            }
+            launch_pair<T, TL>(h, l, X, 0, 1, sg, c, nullptr, ty, kc);  // warm-up
+            HIP_TRY(hipEventRecord(e0, h->s));
+            for (int r = 0; r < reps; ++r) launch_pair<T, TL>(h, l, X, 0, 1, sg, c, nullptr, ty, kc);
+            HIP_TRY(hipEventRecord(e1, h->s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            cost += ms / reps;
+          }
+          const float ms = 0.5f * cost;  // mean time of one pass
+          if (ms < pbest) {
+            pbest = ms;
+            pkc = kc;
+            pty = ty;
+          }
         }
       }
       lv.pair_kc = (pbest < 2.f * best) ? pkc : 0;
+      lv.pair_ty = pty;
       rep->pair_kchunk[l] = lv.pair_kc;
+      rep->pair_ty[l] = lv.pair_ty;
       rep->us_pair[l] = 1e3 * pbest;
     }
   }
@@ -1900,15 +1929,17 @@ gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchun
   return drop_graphs(h);
 }
 
-gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t kchunk) {
+gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk) {
   if (!h) return fail(GMG_EINVAL, "handle is NULL");
   if (level < 0 || level >= h->nlev) return fail(GMG_EINVAL, "level out of range");
+  if (kchunk != 0 && ty != 8 && ty != 16) return fail(GMG_EINVAL, "ty must be 8 or 16");
   if (kchunk != 0 && !pair_capable(h->p, h->lev[level].g))
     return fail(GMG_EINVAL,
                 "two-sweep passes need pair_sweeps = 1, FP32 cycles, the red-black smoother "
                 "and an even nx");
   if (kchunk < 0 || kchunk > h->lev[level].g.nz) return fail(GMG_EINVAL, "kchunk out of range");
   h->lev[level].pair_kc = kchunk;
+  if (kchunk != 0) h->lev[level].pair_ty = ty;
   return drop_graphs(h);
 }
 

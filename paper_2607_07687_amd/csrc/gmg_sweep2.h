@@ -43,11 +43,16 @@ namespace gmg {
 constexpr int S2_TX = 64;  // tile width in x
 constexpr int S2_PX = 36;  // x-pairs per row of the grown region (64 + 2 x 4 cells)
 
+// Tile heights: TY = 8 (9 waves) keeps two planes of loads in flight per
+// thread; TY = 16 (14 waves, 25 % less grown-ring work per tile cell) has
+// the registers for one only.
 template <int TY>
 struct S2Cfg {
+  static_assert(TY == 8 || TY == 16, "two-sweep tile height");
   static constexpr int RY = TY + 8;                // rows of the grown region
   static constexpr int NT = S2_PX * RY;            // threads holding a column
   static constexpr int NTB = (NT + 63) / 64 * 64;  // workgroup size (whole waves)
+  static constexpr int NSET = TY == 8 ? 2 : 1;     // load sets in flight
 };
 
 template <typename T, int TY>
@@ -188,13 +193,13 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     const S2Plane<T> z{};
     P0 = P1 = P2 = z;
   }
-  // prologue: planes k0-4 and k0-3 in registers, k0-2 in flight; the loop
-  // starts at step k0-7, whose P3, P4 are those planes
+  // prologue: planes k0-4 and k0-3 in registers (with two load sets, k0-2 in
+  // flight); the loop starts at step k0-7, whose P3, P4 are those planes
   s2_fetch<T, TL, PROL>(la, a, k0 - 4, off, coff);
   s2_fetch<T, TL, PROL>(lb, a, k0 - 3, off, coff);
   s2_take<T, PROL>(P3, la);
   s2_take<T, PROL>(P4, lb);
-  s2_fetch<T, TL, PROL>(la, a, k0 - 2, off, coff);
+  if constexpr (C::NSET == 2) s2_fetch<T, TL, PROL>(la, a, k0 - 2, off, coff);
   // step k0-8's exchange (S, Ly, Lx of plane k0-4 = P3) so that step k0-7
   // can complete P3's high faces
   {
@@ -212,9 +217,13 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
 
   auto step = [&](int k, S2Load<T>& cur, S2Load<T>& nxt) {
     const int q = (k - 1) & 1, w = k & 1;
-    // issue the loads of plane k+6 (k+5 is in flight in `cur`); beyond the
-    // chunk's last needed plane (k1+3) they are loaded but never used
-    s2_fetch<T, TL, PROL>(nxt, a, k + 6, off, coff);
+    // issue the loads of plane k+6 into `nxt` (k+5 is in flight in `cur`),
+    // or with one load set those of plane k+5 into `cur`; beyond the chunk's
+    // last needed plane (k1+3) they are loaded but never used
+    if constexpr (C::NSET == 2)
+      s2_fetch<T, TL, PROL>(nxt, a, k + 6, off, coff);
+    else
+      s2_fetch<T, TL, PROL>(cur, a, k + 5, off, coff);
     // complete plane k+3: high faces from the previous step's exchange
     P3.lxh = sm.lx0[q][r][pe];
     P3.lyh[0] = sm.ly[q][rn][2 * p];
@@ -299,11 +308,15 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     __syncthreads();
   };
   int k = k0 - 7;
-  for (; k + 1 < k1; k += 2) {
-    step(k, la, lb);
-    step(k + 1, lb, la);
+  if constexpr (C::NSET == 2) {
+    for (; k + 1 < k1; k += 2) {
+      step(k, la, lb);
+      step(k + 1, lb, la);
+    }
+    if (k < k1) step(k, la, lb);
+  } else {
+    for (; k < k1; ++k) step(k, la, la);
   }
-  if (k < k1) step(k, la, lb);
 }
 
 }  // namespace gmg

@@ -67,7 +67,7 @@ class gmg_tune_report(ctypes.Structure):
                 ("kchunk", ctypes.c_int32 * 32), ("ty_default", ctypes.c_int32 * 32),
                 ("kchunk_default", ctypes.c_int32 * 32), ("us", ctypes.c_double * 32),
                 ("us_default", ctypes.c_double * 32), ("pair_kchunk", ctypes.c_int32 * 32),
-                ("us_pair", ctypes.c_double * 32)]
+                ("us_pair", ctypes.c_double * 32), ("pair_ty", ctypes.c_int32 * 32)]
 
 
 class GMGError(RuntimeError):
@@ -124,7 +124,8 @@ _SIGS = [
                                     ctypes.c_int32, ctypes.POINTER(gmg_tune_report)]),
     ("gmg_set_tiles", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32]),
-    ("gmg_set_pair_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    ("gmg_set_pair_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32]),
     ("gmg_last_error", ctypes.c_char_p, []),
 ]
 
@@ -420,7 +421,7 @@ def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inne
 def gmg_autotune(h, x, sigma, reps=5):
     """Time the sweep tile candidates of every level and keep the fastest;
     also the two-sweep pass where allowed.  Returns per-level dicts (shape,
-    ty, kchunk, us, defaults, pair_kchunk (0: separate sweeps), us_pair)."""
+    ty, kchunk, us, defaults, pair_kchunk (0: separate sweeps), pair_ty, us_pair)."""
     rep = gmg_tune_report()
     _check(load().gmg_autotune(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), int(reps),
                                ctypes.byref(rep)))
@@ -430,7 +431,7 @@ def gmg_autotune(h, x, sigma, reps=5):
         out.append(dict(level=l, n=n, ty=rep.ty[l], kchunk=rep.kchunk[l], us=rep.us[l],
                         ty_default=rep.ty_default[l], kchunk_default=rep.kchunk_default[l],
                         us_default=rep.us_default[l], pair_kchunk=rep.pair_kchunk[l],
-                        us_pair=rep.us_pair[l]))
+                        pair_ty=rep.pair_ty[l], us_pair=rep.us_pair[l]))
     return out
 
 
@@ -438,10 +439,10 @@ def gmg_set_tiles(h, level, ty, kchunk):
     _check(load().gmg_set_tiles(h.ptr, int(level), int(ty), int(kchunk)))
 
 
-def gmg_set_pair_sweeps(h, level, kchunk):
-    """Two-sweep passes of kchunk z-planes per workgroup on one level (0:
-    separate sweeps)."""
-    _check(load().gmg_set_pair_sweeps(h.ptr, int(level), int(kchunk)))
+def gmg_set_pair_sweeps(h, level, kchunk, ty=16):
+    """Two-sweep passes on 64 x ty tiles (ty 8 or 16) of kchunk z-planes per
+    workgroup on one level (kchunk 0: separate sweeps)."""
+    _check(load().gmg_set_pair_sweeps(h.ptr, int(level), int(ty), int(kchunk)))
 
 
 def gmg_batch_autotune(b, reps=5):

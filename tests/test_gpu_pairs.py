@@ -38,13 +38,14 @@ def handles(L, s, per, prec, storage, **kw):
     return hp, hs, sd
 
 
-def set_pairs(h, kc):
-    """Two-sweep passes on every level that allows them, z-chunk kc(l, nz)."""
+def set_pairs(h, kc, ty=16):
+    """Two-sweep passes on every level that allows them, z-chunk kc(l, nz),
+    tiles of 64 x ty cells."""
     on = []
     for l in range(G.gmg_num_levels(h)):
         (nx, ny, nz), _ = G.gmg_level_shape(h, l)
         if nx % 2 == 0:
-            G.gmg_set_pair_sweeps(h, l, kc(l, nz))
+            G.gmg_set_pair_sweeps(h, l, kc(l, nz), ty)
             on.append(l)
         else:
             G.gmg_set_pair_sweeps(h, l, 0)
@@ -74,18 +75,20 @@ def same_cycles_and_solve(hp, hs, sd, prec, seed=2):
 KCS = {"one": lambda l, nz: 1, "three": lambda l, nz: min(3, nz), "whole": lambda l, nz: nz}
 
 
+@pytest.mark.parametrize("ty", [16, 8])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 @pytest.mark.parametrize("kc", list(KCS), ids=list(KCS))
 @pytest.mark.parametrize("case", EVEN, ids=lambda c: c[0])
-def test_pairs_match_separate_sweeps(case, kc, storage):
+def test_pairs_match_separate_sweeps(case, kc, storage, ty):
     name, n, per, contrast, holes = case
     L, s, _ = P.random_problem(n, per, seed=zlib.crc32(name.encode()) % 1000, contrast=contrast,
                                holes=holes)
     hp, hs, sd = handles(L, s, per, "f32", storage)
-    on = set_pairs(hp, KCS[kc])
+    on = set_pairs(hp, KCS[kc], ty)
     assert 0 in on
     r = same_cycles_and_solve(hp, hs, sd, "f32")
-    say(f"{name} {storage} kc={kc}: passes on levels {on}, {r['cycles']} cycles, bitwise equal")
+    say(f"{name} {storage} kc={kc} ty={ty}: passes on levels {on}, {r['cycles']} cycles, "
+        "bitwise equal")
     hp.close()
     hs.close()
 
@@ -96,9 +99,10 @@ def test_pairs_match_on_larger_grids(case):
     L, s, _ = P.random_problem(n, per, seed=zlib.crc32(name.encode()) % 1000, contrast=2.0,
                                holes=0.05)
     hp, hs, sd = handles(L, s, per, "f32", "f32")
-    for kc in (lambda l, nz: 0 if l else 5, lambda l, nz: 16 if l == 0 else min(4, nz)):
-        on = set_pairs(hp, kc)
-        same_cycles_and_solve(hp, hs, sd, "f32", seed=len(on))
+    for kc, ty in ((lambda l, nz: 0 if l else 5, 8), (lambda l, nz: 16 if l == 0 else min(4, nz), 8),
+                   (lambda l, nz: 0 if l else 7, 16), (lambda l, nz: 12 if l == 0 else min(3, nz), 16)):
+        on = set_pairs(hp, kc, ty)
+        same_cycles_and_solve(hp, hs, sd, "f32", seed=len(on) + ty)
     hp.close()
     hs.close()
 
@@ -120,9 +124,9 @@ def test_pairs_default_and_autotune():
     hp, hs, sd = handles(L, s, per, "f32", "f32")
     x = torch.zeros_like(sd)
     rep = G.gmg_autotune(hp, x, sd, 2)
-    assert rep[0]["us_pair"] > 0
-    say("autotune: " + ", ".join(f"L{r['level']} pair {r['pair_kchunk']} ({r['us_pair']:.1f} us)"
-                                 f" vs sweep {r['us']:.1f} us" for r in rep))
+    assert rep[0]["us_pair"] > 0 and rep[0]["pair_ty"] in (8, 16)
+    say("autotune: " + ", ".join(f"L{r['level']} pair {r['pair_ty']}x{r['pair_kchunk']} "
+                                 f"({r['us_pair']:.1f} us) vs sweep {r['us']:.1f} us" for r in rep))
     same_cycles_and_solve(hp, hs, sd, "f32")
     hp.close()
     hs.close()
@@ -135,12 +139,13 @@ def test_pair_parameter_checks():
         G.gmg_setup(G.gmg_default_params((8, 8, 8), (False,) * 3, pair_sweeps=2), L)
     assert e.value.status == G.GMG_EINVAL
     h = G.gmg_setup(G.gmg_default_params((8, 8, 8), (False,) * 3), L)
-    for level, kc in ((0, 9), (0, -1), (7, 1)):
+    for level, kc, ty in ((0, 9, 16), (0, -1, 16), (7, 1, 16), (0, 2, 4), (0, 2, 12)):
         with pytest.raises(G.GMGError) as e:
-            G.gmg_set_pair_sweeps(h, level, kc)
+            G.gmg_set_pair_sweeps(h, level, kc, ty)
         assert e.value.status == G.GMG_EINVAL
     G.gmg_set_pair_sweeps(h, 0, 0)
-    G.gmg_set_pair_sweeps(h, 0, 8)
+    G.gmg_set_pair_sweeps(h, 0, 8, 8)
+    G.gmg_set_pair_sweeps(h, 0, 8, 16)
     h.close()
     # FP64 cycles, the PCG smoother, pair_sweeps 0 and an odd nx do not allow passes
     for kw, Lt, n in ((dict(dtype=G.GMG_F64), L.double(), (8, 8, 8)),
