@@ -36,6 +36,8 @@
 // sweep does.
 #pragma once
 
+#include <type_traits>
+
 #include "gmg_sweep.h"  // wrap_coord, 2-wide loads
 
 namespace gmg {
@@ -46,12 +48,22 @@ constexpr int S2_PX = 36;  // x-pairs per row of the grown region (64 + 2 x 4 ce
 // Tile heights: TY = 8 (9 waves) keeps two planes of loads in flight per
 // thread; TY = 16 (14 waves, 25 % less grown-ring work per tile cell) has
 // the registers for one only.
+//
+// With TY = 16 the even and the odd rows of the grown region go to separate
+// whole waves (7 each).  In a pair column the red cell is the first or the
+// second by the parity of x + y + k, and x + y has the parity of the row, so
+// every lane of a wave then updates the same element of its pair: the stages
+// branch once on it, uniformly, instead of selecting per lane.  (With TY = 8
+// the split would cost a tenth wave, more than the selects save.)
 template <int TY>
 struct S2Cfg {
   static_assert(TY == 8 || TY == 16, "two-sweep tile height");
   static constexpr int RY = TY + 8;                // rows of the grown region
   static constexpr int NT = S2_PX * RY;            // threads holding a column
-  static constexpr int NTB = (NT + 63) / 64 * 64;  // workgroup size (whole waves)
+  static constexpr bool SPLIT = TY == 16;          // waves of one row parity
+  static constexpr int NH = S2_PX * (RY / 2);      // columns of one row parity
+  static constexpr int H = (NH + 63) / 64 * 64;    // threads of one row parity
+  static constexpr int NTB = SPLIT ? 2 * H : (NT + 63) / 64 * 64;  // workgroup size
   static constexpr int NSET = TY == 8 ? 2 : 1;     // load sets in flight
 };
 
@@ -144,8 +156,9 @@ __device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld) {
   p.lxh = T(0);
 }
 
-// Element e (0 or 1, known only at run time) of a pair held in registers:
-// a select, since an indexed access would move the pair to scratch memory.
+// Element e of a pair held in registers: a select when e is known only at
+// run time (an indexed access would move the pair to scratch memory), a
+// plain register when it is a constant.
 template <typename T>
 __device__ __forceinline__ T pick(const T (&v)[2], int e) {
   return e ? v[1] : v[0];
@@ -160,8 +173,14 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   using C = S2Cfg<TY>;
   const Geom& g = a.g;
   const int t = threadIdx.x;
-  const bool col = t < C::NT;  // padding threads only join the barriers
-  const int p = col ? t % S2_PX : 0, r = col ? t / S2_PX : 0;
+  // row parity of the wave (SPLIT; C::H is a multiple of the wave size, so
+  // it is uniform) and the thread's index among the threads of that parity
+  const int hw = C::SPLIT ? __builtin_amdgcn_readfirstlane(t / C::H) : 0;
+  const int u = t - hw * C::H;
+  // padding threads only join the barriers
+  const bool col = C::SPLIT ? u < C::NH : t < C::NT;
+  const int p = !col ? 0 : C::SPLIT ? u % S2_PX : t % S2_PX;
+  const int r = !col ? hw : C::SPLIT ? 2 * (u / S2_PX) + hw : t / S2_PX;
   const int xa = i0 - 4 + 2 * p;  // x of the pair's first cell
   const int y = j0 - 4 + r;
   const int ii = wrap_coord(xa, g.nx, g.px), jj = wrap_coord(y, g.ny, g.py);
@@ -179,10 +198,10 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   const bool in3[2] = {in_ring(0, 3), in_ring(1, 3)}, in2[2] = {in_ring(0, 2), in_ring(1, 2)};
   const bool in1[2] = {in_ring(0, 1), in_ring(1, 1)};
   const bool out_ok = col && in_ring(0, 0) && y < g.ny && xa < g.nx;
-  // the pair's red element on plane m (colour by unwrapped coordinates; every
-  // periodic extent is even)
-  const int par = (xa + y) & 1;
-  auto red_e = [&](int m) { return (par + m) & 1; };
+  // parity of x + y of the pair's first cell (colour by unwrapped
+  // coordinates; every periodic extent is even, and tile origins are even, so
+  // it is the parity of r: hw with SPLIT)
+  const int par = C::SPLIT ? hw : (xa + y) & 1;
 
   S2Plane<T> P0, P1, P2, P3, P4;  // planes k .. k+4 at step k
   T r1a = T(0), r1b = T(0);       // sweep-1 red of planes k+1, k+2
@@ -229,59 +248,81 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     P3.lyh[0] = sm.ly[q][rn][2 * p];
     P3.lyh[1] = sm.ly[q][rn][2 * p + 1];
     T r1n = T(0), b1n = T(0), r2n = T(0);
+    // The four stages of step k all update element e = 1 - (par + k) mod 2
+    // of their pairs: the red one on planes k+3 and k+1, the black one on
+    // k+2 and k.  Each stage takes it as `ec`: with SPLIT a compile-time
+    // constant, entered through a wave-uniform branch per stage.
+    auto run = [&](auto&& stage) {
+      if constexpr (C::SPLIT) {
+        if ((par + k) & 1)
+          stage(std::integral_constant<int, 0>{});
+        else
+          stage(std::integral_constant<int, 1>{});
+      } else {
+        stage(((par + k) & 1) ^ 1);
+      }
+    };
     // stage 1: sweep-1 red on plane k+3 from S
     if (k + 3 >= k0 - 3 && k + 3 < k1 + 3) {
-      const int e = red_e(k + 3);
-      if (e ? in3[1] : in3[0]) {  // whole waves outside the ring skip the update
-        const T xe = e == 0 ? P3.s[1] : sm.s[q][r][2 * pe];
-        const T xw = e == 0 ? sm.s[q][r][2 * pw + 1] : P3.s[0];
-        r1n = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][rn][2 * p + e], sm.s[q][rs][2 * p + e],
-                            pick(P4.s, e), pick(P2.s, e), pick(P3.lx, e),
-                            e == 0 ? P3.lx[1] : P3.lxh, pick(P3.ly, e), pick(P3.lyh, e),
-                            pick(P3.lz, e), pick(P4.lz, e), pick(P3.sg, e), omega);
-      }
+      run([&](auto ec) {
+        const int e = ec;
+        if (e ? in3[1] : in3[0]) {  // whole waves outside the ring skip the update
+          const T xe = e == 0 ? P3.s[1] : sm.s[q][r][2 * pe];
+          const T xw = e == 0 ? sm.s[q][r][2 * pw + 1] : P3.s[0];
+          r1n = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][rn][2 * p + e],
+                              sm.s[q][rs][2 * p + e], pick(P4.s, e), pick(P2.s, e),
+                              pick(P3.lx, e), e == 0 ? P3.lx[1] : P3.lxh, pick(P3.ly, e),
+                              pick(P3.lyh, e), pick(P3.lz, e), pick(P4.lz, e), pick(P3.sg, e),
+                              omega);
+        }
+      });
     }
     // stage 2: sweep-1 black on plane k+2 from the sweep-1 red values
     if (k + 2 >= k0 - 2 && k + 2 < k1 + 2) {
-      const int e = red_e(k + 2) ^ 1;
-      if (e ? in2[1] : in2[0]) {
-        const T xe = e == 0 ? r1b : sm.r1[q][r][pe];
-        const T xw = e == 0 ? sm.r1[q][r][pw] : r1b;
-        b1n = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][rn][p], sm.r1[q][rs][p], r1n, r1a,
-                            pick(P2.lx, e), e == 0 ? P2.lx[1] : P2.lxh, pick(P2.ly, e),
-                            pick(P2.lyh, e), pick(P2.lz, e), pick(P3.lz, e), pick(P2.sg, e),
-                            omega);
-      }
+      run([&](auto ec) {
+        const int e = ec;
+        if (e ? in2[1] : in2[0]) {
+          const T xe = e == 0 ? r1b : sm.r1[q][r][pe];
+          const T xw = e == 0 ? sm.r1[q][r][pw] : r1b;
+          b1n = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][rn][p], sm.r1[q][rs][p], r1n, r1a,
+                              pick(P2.lx, e), e == 0 ? P2.lx[1] : P2.lxh, pick(P2.ly, e),
+                              pick(P2.lyh, e), pick(P2.lz, e), pick(P3.lz, e), pick(P2.sg, e),
+                              omega);
+        }
+      });
     }
     // stage 3: sweep-2 red on plane k+1 from the sweep-1 values
     if (k + 1 >= k0 - 1 && k + 1 < k1 + 1) {
-      const int e = red_e(k + 1);
-      if (e ? in1[1] : in1[0]) {
-        const T xe = e == 0 ? b1b : sm.b1[q][r][pe];
-        const T xw = e == 0 ? sm.b1[q][r][pw] : b1b;
-        r2n = relax_cell<T>(r1a, xe, xw, sm.b1[q][rn][p], sm.b1[q][rs][p], b1n, b1a,
-                            pick(P1.lx, e), e == 0 ? P1.lx[1] : P1.lxh, pick(P1.ly, e),
-                            pick(P1.lyh, e), pick(P1.lz, e), pick(P2.lz, e), pick(P1.sg, e),
-                            omega);
-      }
+      run([&](auto ec) {
+        const int e = ec;
+        if (e ? in1[1] : in1[0]) {
+          const T xe = e == 0 ? b1b : sm.b1[q][r][pe];
+          const T xw = e == 0 ? sm.b1[q][r][pw] : b1b;
+          r2n = relax_cell<T>(r1a, xe, xw, sm.b1[q][rn][p], sm.b1[q][rs][p], b1n, b1a,
+                              pick(P1.lx, e), e == 0 ? P1.lx[1] : P1.lxh, pick(P1.ly, e),
+                              pick(P1.lyh, e), pick(P1.lz, e), pick(P2.lz, e), pick(P1.sg, e),
+                              omega);
+        }
+      });
     }
     // stage 4: sweep-2 black on plane k; store plane k of W
-    if (k >= k0 && k < k1 && out_ok) {
-      const int e = red_e(k) ^ 1;
-      const T xe = e == 0 ? r2b : sm.r2[q][r][pe];
-      const T xw = e == 0 ? sm.r2[q][r][pw] : r2b;
-      const T b2 = relax_cell<T>(b1a, xe, xw, sm.r2[q][rn][p], sm.r2[q][rs][p], r2n, r2a,
-                                 pick(P0.lx, e), e == 0 ? P0.lx[1] : P0.lxh, pick(P0.ly, e),
-                                 pick(P0.lyh, e), pick(P0.lz, e), pick(P1.lz, e), pick(P0.sg, e),
-                                 omega);
-      {
+    if (k >= k0 && k < k1) {
+      run([&](auto ec) {
+        const int e = ec;
+        if (!out_ok) return;
+        const T xe = e == 0 ? r2b : sm.r2[q][r][pe];
+        const T xw = e == 0 ? sm.r2[q][r][pw] : r2b;
+        const T b2 = relax_cell<T>(b1a, xe, xw, sm.r2[q][rn][p], sm.r2[q][rs][p], r2n, r2a,
+                                   pick(P0.lx, e), e == 0 ? P0.lx[1] : P0.lxh, pick(P0.ly, e),
+                                   pick(P0.lyh, e), pick(P0.lz, e), pick(P1.lz, e),
+                                   pick(P0.sg, e), omega);
         const long long idx = (long long)k * g.sz + (long long)y * g.sy + xa;
         const T o0 = e == 0 ? b2 : r2b, o1 = e == 0 ? r2b : b2;
         if constexpr (sizeof(T) == 4)
           *reinterpret_cast<float2*>(W + idx) = make_float2(o0, o1);
         else
           *reinterpret_cast<double2*>(W + idx) = make_double2(o0, o1);
-      }
+      });
     }
     // the next plane into the column registers, then exchange for step k+1
     P0 = P1;
@@ -315,6 +356,15 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     }
     if (k < k1) step(k, la, lb);
   } else {
+    // five steps per iteration: the five plane registers then rotate by
+    // renaming instead of by moves
+    for (; k + 4 < k1; k += 5) {
+      step(k, la, la);
+      step(k + 1, la, la);
+      step(k + 2, la, la);
+      step(k + 3, la, la);
+      step(k + 4, la, la);
+    }
     for (; k < k1; ++k) step(k, la, la);
   }
 }
