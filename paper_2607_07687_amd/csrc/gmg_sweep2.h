@@ -67,14 +67,18 @@ struct S2Cfg {
   static constexpr int NSET = TY == 8 ? 2 : 1;     // load sets in flight
 };
 
+// Rows and columns carry one entry of padding on each side, so that every
+// thread's neighbours are in bounds without clamping and each neighbour is
+// the thread's own entry plus a constant offset.  Padding is never written;
+// only threads outside every stage's region would read it.
 template <typename T, int TY>
 struct S2Smem {
-  T s[2][TY + 8][2 * S2_PX];   // S of the newest plane
-  T ly[2][TY + 8][2 * S2_PX];  // Ly of the newest plane (high y-faces of the row below)
-  T lx0[2][TY + 8][S2_PX];     // Lx of each pair's first cell (high x-face of the pair before)
-  T r1[2][TY + 8][S2_PX];      // sweep-1 red value of each pair
-  T b1[2][TY + 8][S2_PX];      // sweep-1 black value of each pair
-  T r2[2][TY + 8][S2_PX];      // sweep-2 red value of each pair
+  T s[2][TY + 10][2 * S2_PX + 2];   // S of the newest plane
+  T ly[2][TY + 10][2 * S2_PX + 2];  // Ly of the newest plane (high y-faces of the row below)
+  T lx0[2][TY + 10][S2_PX + 2];     // Lx of each pair's first cell (high x-face of the pair before)
+  T r1[2][TY + 10][S2_PX + 2];      // sweep-1 red value of each pair
+  T b1[2][TY + 10][S2_PX + 2];      // sweep-1 black value of each pair
+  T r2[2][TY + 10][S2_PX + 2];      // sweep-2 red value of each pair
 };
 
 // Inputs of one plane of a thread's pair column.
@@ -186,10 +190,11 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   const int ii = wrap_coord(xa, g.nx, g.px), jj = wrap_coord(y, g.ny, g.py);
   const int off = (col && ii >= 0 && jj >= 0) ? (int)(jj * g.sy) + ii : -1;
   const int coff = (off >= 0) ? (int)((jj >> (a.cy >> 1)) * a.gc.sy) + (ii >> (a.cx >> 1)) : 0;
-  // neighbour indices in LDS, clamped (clamped reads only feed cells outside
-  // the stage's region, whose results are never used)
-  const int pw = p > 0 ? p - 1 : 0, pe = p + 1 < S2_PX ? p + 1 : S2_PX - 1;
-  const int rs = r > 0 ? r - 1 : 0, rn = r + 1 < C::RY ? r + 1 : C::RY - 1;
+  // LDS indices (padded by one): the thread's row R and its neighbours RN
+  // (y+1) and RS (y-1); its pair column c and the pairs to the west cw and
+  // east ce; cs, the cell column of its pair's first cell
+  const int R = r + 1, RN = r + 2, RS = r;
+  const int c = p + 1, cw = p, ce = p + 2, cs = 2 * p + 1;
   // cell e of the pair lies in the tile grown by d cells
   auto in_ring = [&](int e, int d) {
     const int x = xa + e;
@@ -224,12 +229,12 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   {
     const int q = (k0 - 8) & 1;
     if (col) {
-      sm.s[q][r][2 * p] = P3.s[0];
-      sm.s[q][r][2 * p + 1] = P3.s[1];
-      sm.ly[q][r][2 * p] = P3.ly[0];
-      sm.ly[q][r][2 * p + 1] = P3.ly[1];
-      sm.lx0[q][r][p] = P3.lx[0];
-      sm.r1[q][r][p] = sm.b1[q][r][p] = sm.r2[q][r][p] = T(0);
+      sm.s[q][R][cs] = P3.s[0];
+      sm.s[q][R][cs + 1] = P3.s[1];
+      sm.ly[q][R][cs] = P3.ly[0];
+      sm.ly[q][R][cs + 1] = P3.ly[1];
+      sm.lx0[q][R][c] = P3.lx[0];
+      sm.r1[q][R][c] = sm.b1[q][R][c] = sm.r2[q][R][c] = T(0);
     }
   }
   __syncthreads();
@@ -244,9 +249,9 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     else
       s2_fetch<T, TL, PROL>(cur, a, k + 5, off, coff);
     // complete plane k+3: high faces from the previous step's exchange
-    P3.lxh = sm.lx0[q][r][pe];
-    P3.lyh[0] = sm.ly[q][rn][2 * p];
-    P3.lyh[1] = sm.ly[q][rn][2 * p + 1];
+    P3.lxh = sm.lx0[q][R][ce];
+    P3.lyh[0] = sm.ly[q][RN][cs];
+    P3.lyh[1] = sm.ly[q][RN][cs + 1];
     T r1n = T(0), b1n = T(0), r2n = T(0);
     // The four stages of step k all update element e = 1 - (par + k) mod 2
     // of their pairs: the red one on planes k+3 and k+1, the black one on
@@ -267,10 +272,10 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
       run([&](auto ec) {
         const int e = ec;
         if (e ? in3[1] : in3[0]) {  // whole waves outside the ring skip the update
-          const T xe = e == 0 ? P3.s[1] : sm.s[q][r][2 * pe];
-          const T xw = e == 0 ? sm.s[q][r][2 * pw + 1] : P3.s[0];
-          r1n = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][rn][2 * p + e],
-                              sm.s[q][rs][2 * p + e], pick(P4.s, e), pick(P2.s, e),
+          const T xe = e == 0 ? P3.s[1] : sm.s[q][R][cs + 2];
+          const T xw = e == 0 ? sm.s[q][R][cs - 1] : P3.s[0];
+          r1n = relax_cell<T>(pick(P3.s, e), xe, xw, sm.s[q][RN][cs + e],
+                              sm.s[q][RS][cs + e], pick(P4.s, e), pick(P2.s, e),
                               pick(P3.lx, e), e == 0 ? P3.lx[1] : P3.lxh, pick(P3.ly, e),
                               pick(P3.lyh, e), pick(P3.lz, e), pick(P4.lz, e), pick(P3.sg, e),
                               omega);
@@ -282,9 +287,9 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
       run([&](auto ec) {
         const int e = ec;
         if (e ? in2[1] : in2[0]) {
-          const T xe = e == 0 ? r1b : sm.r1[q][r][pe];
-          const T xw = e == 0 ? sm.r1[q][r][pw] : r1b;
-          b1n = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][rn][p], sm.r1[q][rs][p], r1n, r1a,
+          const T xe = e == 0 ? r1b : sm.r1[q][R][ce];
+          const T xw = e == 0 ? sm.r1[q][R][cw] : r1b;
+          b1n = relax_cell<T>(pick(P2.s, e), xe, xw, sm.r1[q][RN][c], sm.r1[q][RS][c], r1n, r1a,
                               pick(P2.lx, e), e == 0 ? P2.lx[1] : P2.lxh, pick(P2.ly, e),
                               pick(P2.lyh, e), pick(P2.lz, e), pick(P3.lz, e), pick(P2.sg, e),
                               omega);
@@ -296,9 +301,9 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
       run([&](auto ec) {
         const int e = ec;
         if (e ? in1[1] : in1[0]) {
-          const T xe = e == 0 ? b1b : sm.b1[q][r][pe];
-          const T xw = e == 0 ? sm.b1[q][r][pw] : b1b;
-          r2n = relax_cell<T>(r1a, xe, xw, sm.b1[q][rn][p], sm.b1[q][rs][p], b1n, b1a,
+          const T xe = e == 0 ? b1b : sm.b1[q][R][ce];
+          const T xw = e == 0 ? sm.b1[q][R][cw] : b1b;
+          r2n = relax_cell<T>(r1a, xe, xw, sm.b1[q][RN][c], sm.b1[q][RS][c], b1n, b1a,
                               pick(P1.lx, e), e == 0 ? P1.lx[1] : P1.lxh, pick(P1.ly, e),
                               pick(P1.lyh, e), pick(P1.lz, e), pick(P2.lz, e), pick(P1.sg, e),
                               omega);
@@ -310,9 +315,9 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
       run([&](auto ec) {
         const int e = ec;
         if (!out_ok) return;
-        const T xe = e == 0 ? r2b : sm.r2[q][r][pe];
-        const T xw = e == 0 ? sm.r2[q][r][pw] : r2b;
-        const T b2 = relax_cell<T>(b1a, xe, xw, sm.r2[q][rn][p], sm.r2[q][rs][p], r2n, r2a,
+        const T xe = e == 0 ? r2b : sm.r2[q][R][ce];
+        const T xw = e == 0 ? sm.r2[q][R][cw] : r2b;
+        const T b2 = relax_cell<T>(b1a, xe, xw, sm.r2[q][RN][c], sm.r2[q][RS][c], r2n, r2a,
                                    pick(P0.lx, e), e == 0 ? P0.lx[1] : P0.lxh, pick(P0.ly, e),
                                    pick(P0.lyh, e), pick(P0.lz, e), pick(P1.lz, e),
                                    pick(P0.sg, e), omega);
@@ -337,14 +342,14 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     r2a = r2b;
     r2b = r2n;
     if (col) {
-      sm.s[w][r][2 * p] = P3.s[0];  // plane k+4
-      sm.s[w][r][2 * p + 1] = P3.s[1];
-      sm.ly[w][r][2 * p] = P3.ly[0];
-      sm.ly[w][r][2 * p + 1] = P3.ly[1];
-      sm.lx0[w][r][p] = P3.lx[0];
-      sm.r1[w][r][p] = r1b;  // plane k+3
-      sm.b1[w][r][p] = b1b;  // plane k+2
-      sm.r2[w][r][p] = r2b;  // plane k+1
+      sm.s[w][R][cs] = P3.s[0];  // plane k+4
+      sm.s[w][R][cs + 1] = P3.s[1];
+      sm.ly[w][R][cs] = P3.ly[0];
+      sm.ly[w][R][cs + 1] = P3.ly[1];
+      sm.lx0[w][R][c] = P3.lx[0];
+      sm.r1[w][R][c] = r1b;  // plane k+3
+      sm.b1[w][R][c] = b1b;  // plane k+2
+      sm.r2[w][R][c] = r2b;  // plane k+1
     }
     __syncthreads();
   };
