@@ -625,7 +625,8 @@ constexpr int kCUs = 256;
 // even nx (the pass works on x-pairs).
 bool pair_capable(const gmg_params& p, const Geom& g) {
   return p.pair_sweeps && p.cycle_dtype == GMG_F32 && p.smoother == GMG_SMOOTH_RBGS &&
-         g.nx % 2 == 0 && (p.nu_pre >= 2 || p.nu_post >= 2 || p.nu_coarse >= 2);
+         g.nx % 2 == 0 && g.n <= S2_MAX_CELLS &&
+         (p.nu_pre >= 2 || p.nu_post >= 2 || p.nu_coarse >= 2);
 }
 
 // z-chunk of the two-sweep pass: one workgroup per CU (its register

@@ -89,15 +89,53 @@ struct S2Plane {
   T lyh[2];  // Ly at y+1: high y-faces
 };
 
-// Global loads of one plane in flight (the prolongation operands separate,
-// so that no load waits on another).
+// Loads of one plane in flight (the prolongation operands separate, so
+// that no load waits on another).
 template <typename T>
 struct S2Load {
   T s[2], sg[2], lx[2], ly[2], lz[2];
   T pc[2];      // coarse value of each cell (prolongation)
   uint32_t pa;  // active-mask bytes of the pair
-  bool in;      // the column and plane are in the domain (else zeros)
 };
+
+// The per-plane inputs are read with raw buffer loads.  Such a load whose
+// offset lies at or past its descriptor's size returns zero and touches no
+// memory, which gives the zeros of columns and planes outside a wall with no
+// per-lane selects: an outside column uses lane offset S2_OUT, an outside
+// plane the descriptor `zero` of size 0.  Every in-domain offset (plane offset
+// plus lane offset) stays below the field's size, so the result does not
+// depend on whether the hardware counts the plane (scalar) offset in its
+// range check, and S2_OUT plus any plane offset stays below 2^32.  This needs
+// every field to be at most 2^30 bytes (n <= 2^28 cells; the host enables
+// the pass only then).
+constexpr int S2_OUT = 1 << 30;
+constexpr long long S2_MAX_CELLS = 1LL << 28;
+// descriptor word 3 of the gfx9 family: 32-bit data format, raw addressing
+constexpr int S2_RSRC_W3 = 0x00020000;
+
+struct S2Bufs {
+  __amdgpu_buffer_rsrc_t S, sg, lx, ly, lz, act, zero;
+};
+
+template <typename T>
+__device__ __forceinline__ void s2_ld2(__amdgpu_buffer_rsrc_t b, int vo, int so, T* v) {
+  static_assert(sizeof(T) == 4, "the two-sweep pass runs FP32 cycles");
+  const float2 f = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(b, vo, so, 0));
+  v[0] = f.x;
+  v[1] = f.y;
+}
+// faces: FP32, or BF16 bits (two in one dword)
+template <typename T, typename TL>
+__device__ __forceinline__ void s2_ldL2(__amdgpu_buffer_rsrc_t b, int vo4, int vo2, int so4,
+                                        int so2, T* v) {
+  if constexpr (sizeof(TL) == 4) {
+    s2_ld2<T>(b, vo4, so4, v);
+  } else {
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b, vo2, so2, 0);
+    v[0] = __uint_as_float(w << 16);
+    v[1] = __uint_as_float(w & 0xFFFF0000u);
+  }
+}
 
 template <typename T, typename TL>
 struct S2Args {
@@ -111,50 +149,48 @@ struct S2Args {
   int cx, cy, cz;
 };
 
-// Issue the loads of plane m for the column at in-plane offset `off` (-1:
-// outside a wall) with coarse in-plane offset `coff` (PROL: also the
-// prolongation operands).  Every lane issues every load, at a clamped
-// in-domain address when the column or plane is outside a wall (s2_take
-// zeroes those), so the number of loads in flight is the same on every
-// path and the compiler waits for exactly the plane being taken.
+// Issue the loads of plane m for the column with lane offsets vo4, vo2, vo1
+// (its in-plane offset in 4-, 2- and 1-byte elements, S2_OUT outside a wall)
+// and coarse in-plane offset `coff` (PROL: also the prolongation operands).
+// Every lane issues every load, so the number of loads in flight is the same
+// on every path and the compiler waits for exactly the plane being taken.
 template <typename T, typename TL, bool PROL>
-__device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, int m, int off,
-                                         int coff) {
+__device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, const S2Bufs& b,
+                                         int m, int vo4, int vo2, int vo1, int coff) {
   const Geom& g = a.g;
-  const int mw = wrap_coord(m, g.nz, g.pz);
-  ld.in = off >= 0 && mw >= 0;
-  const int mm = mw >= 0 ? mw : 0;
-  const long long idx = (long long)mm * g.sz + (off >= 0 ? off : 0);
-  ldv<T, 2>(a.S, idx, ld.s);
-  ldv<T, 2>(a.sigma, idx, ld.sg);
-  ldLv<T, 2>(a.L, idx, ld.lx);
-  ldLv<T, 2>(a.L + g.n, idx, ld.ly);
-  ldLv<T, 2>(a.L + 2 * g.n, idx, ld.lz);
+  const int mw = wrap_coord(m, g.nz, g.pz);  // uniform
+  const bool pin = mw >= 0;
+  const int mm = pin ? mw : 0;
+  const int so1 = mm * (int)g.sz, so2 = 2 * so1, so4 = 4 * so1;
+  s2_ld2<T>(pin ? b.S : b.zero, vo4, so4, ld.s);
+  s2_ld2<T>(pin ? b.sg : b.zero, vo4, so4, ld.sg);
+  s2_ldL2<T, TL>(pin ? b.lx : b.zero, vo4, vo2, so4, so2, ld.lx);
+  s2_ldL2<T, TL>(pin ? b.ly : b.zero, vo4, vo2, so4, so2, ld.ly);
+  s2_ldL2<T, TL>(pin ? b.lz : b.zero, vo4, vo2, so4, so2, ld.lz);
   if constexpr (PROL) {
     // factors are 1 or 2; the pair's second cell has the next parent only
-    // when c_x = 1
+    // when c_x = 1.  Outside a wall the mask reads zero, and the coarse
+    // value (at a clamped address) is not used.
     const long long cb = (long long)(mm >> (a.cz >> 1)) * a.gc.sz + coff;
-    ld.pa = *reinterpret_cast<const uint16_t*>(a.active + idx);
+    ld.pa = __builtin_amdgcn_raw_buffer_load_b16(pin ? b.act : b.zero, vo1, so1, 0);
 #pragma unroll
     for (int e = 0; e < 2; ++e) ld.pc[e] = a.xc[cb + (a.cx == 1 ? e : 0)];
   }
 }
 
-// Loaded plane -> column registers: zeros outside a wall (PROL: S corrected
-// on active cells).
+// Loaded plane -> column registers (PROL: S corrected on active cells).
 template <typename T, bool PROL>
 __device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld) {
-  const bool in = ld.in;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     if constexpr (PROL)
-      p.s[e] = !in ? T(0) : (((ld.pa >> (8 * e)) & 0xFFu) != 0 ? ld.s[e] + ld.pc[e] : ld.s[e]);
+      p.s[e] = ((ld.pa >> (8 * e)) & 0xFFu) != 0 ? ld.s[e] + ld.pc[e] : ld.s[e];
     else
-      p.s[e] = in ? ld.s[e] : T(0);
-    p.sg[e] = in ? ld.sg[e] : T(0);
-    p.lx[e] = in ? ld.lx[e] : T(0);
-    p.ly[e] = in ? ld.ly[e] : T(0);
-    p.lz[e] = in ? ld.lz[e] : T(0);
+      p.s[e] = ld.s[e];
+    p.sg[e] = ld.sg[e];
+    p.lx[e] = ld.lx[e];
+    p.ly[e] = ld.ly[e];
+    p.lz[e] = ld.lz[e];
     p.lyh[e] = T(0);
   }
   p.lxh = T(0);
@@ -190,6 +226,18 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   const int ii = wrap_coord(xa, g.nx, g.px), jj = wrap_coord(y, g.ny, g.py);
   const int off = (col && ii >= 0 && jj >= 0) ? (int)(jj * g.sy) + ii : -1;
   const int coff = (off >= 0) ? (int)((jj >> (a.cy >> 1)) * a.gc.sy) + (ii >> (a.cx >> 1)) : 0;
+  const int vo1 = off >= 0 ? off : S2_OUT, vo2 = off >= 0 ? 2 * off : S2_OUT,
+            vo4 = off >= 0 ? 4 * off : S2_OUT;
+  const int nb = (int)g.n;  // at most S2_MAX_CELLS
+  const S2Bufs b{__builtin_amdgcn_make_buffer_rsrc((void*)a.S, 0, 4 * nb, S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)a.sigma, 0, 4 * nb, S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)a.L, 0, (int)sizeof(TL) * nb, S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)(a.L + g.n), 0, (int)sizeof(TL) * nb,
+                                                   S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)(a.L + 2 * g.n), 0,
+                                                   (int)sizeof(TL) * nb, S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)a.active, 0, nb, S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)a.S, 0, 0, S2_RSRC_W3)};
   // LDS indices (padded by one): the thread's row R and its neighbours RN
   // (y+1) and RS (y-1); its pair column c and the pairs to the west cw and
   // east ce; cs, the cell column of its pair's first cell
@@ -219,11 +267,11 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   }
   // prologue: planes k0-4 and k0-3 in registers (with two load sets, k0-2 in
   // flight); the loop starts at step k0-7, whose P3, P4 are those planes
-  s2_fetch<T, TL, PROL>(la, a, k0 - 4, off, coff);
-  s2_fetch<T, TL, PROL>(lb, a, k0 - 3, off, coff);
+  s2_fetch<T, TL, PROL>(la, a, b, k0 - 4, vo4, vo2, vo1, coff);
+  s2_fetch<T, TL, PROL>(lb, a, b, k0 - 3, vo4, vo2, vo1, coff);
   s2_take<T, PROL>(P3, la);
   s2_take<T, PROL>(P4, lb);
-  if constexpr (C::NSET == 2) s2_fetch<T, TL, PROL>(la, a, k0 - 2, off, coff);
+  if constexpr (C::NSET == 2) s2_fetch<T, TL, PROL>(la, a, b, k0 - 2, vo4, vo2, vo1, coff);
   // step k0-8's exchange (S, Ly, Lx of plane k0-4 = P3) so that step k0-7
   // can complete P3's high faces
   {
@@ -245,9 +293,9 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     // or with one load set those of plane k+5 into `cur`; beyond the chunk's
     // last needed plane (k1+3) they are loaded but never used
     if constexpr (C::NSET == 2)
-      s2_fetch<T, TL, PROL>(nxt, a, k + 6, off, coff);
+      s2_fetch<T, TL, PROL>(nxt, a, b, k + 6, vo4, vo2, vo1, coff);
     else
-      s2_fetch<T, TL, PROL>(cur, a, k + 5, off, coff);
+      s2_fetch<T, TL, PROL>(cur, a, b, k + 5, vo4, vo2, vo1, coff);
     // complete plane k+3: high faces from the previous step's exchange
     P3.lxh = sm.lx0[q][R][ce];
     P3.lyh[0] = sm.ly[q][RN][cs];
