@@ -159,3 +159,20 @@ def test_pair_parameter_checks():
         assert e.value.status == G.GMG_EINVAL
         G.gmg_set_pair_sweeps(h, 0, 0)
         h.close()
+
+
+def test_pair_refused_above_buffer_limit():
+    # the pass addresses each field with 32-bit buffer offsets: a level of
+    # more than 2^28 cells must run separate sweeps (3.2 GB of faces here)
+    require_gpu()
+    n = (2048, 512, 257)
+    assert n[0] * n[1] * n[2] > 1 << 28
+    L = torch.ones((3, n[2], n[1], n[0]), dtype=torch.float32, device="cuda")
+    h = G.gmg_setup(G.gmg_default_params(n, (False,) * 3), L)
+    del L
+    with pytest.raises(G.GMGError) as e:
+        G.gmg_set_pair_sweeps(h, 0, 8)
+    assert e.value.status == G.GMG_EINVAL
+    # level 1 is below the limit and keeps its passes
+    G.gmg_set_pair_sweeps(h, 1, 8)
+    h.close()
