@@ -1793,11 +1793,16 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
     HIP_TRY(hipGetLastError());
     int launched = 0, chunk = 2;
     while (true) {
-      HIP_TRY(hipMemcpyAsync(h->hst, h->st, offsetof(SolveState, hist), hipMemcpyDeviceToHost,
-                             h->s));
-      HIP_TRY(hipStreamSynchronize(h->s));
+      // The first round goes out right behind the start kernels, unpolled:
+      // if the start already decided the solve (sigma = 0), its cycles find
+      // `done` set and do nothing.
+      if (launched > 0) {
+        HIP_TRY(hipMemcpyAsync(h->hst, h->st, offsetof(SolveState, hist),
+                               hipMemcpyDeviceToHost, h->s));
+        HIP_TRY(hipStreamSynchronize(h->s));
+      }
       // with the deferred decision the first pass decides nothing
-      if (h->hst->done || launched >= max_cycles + (spec ? 1 : 0)) break;
+      if ((launched > 0 && h->hst->done) || launched >= max_cycles + (spec ? 1 : 0)) break;
       if (launched > 0) {
         // size the next launch round from the observed contraction
         const double rho = h->hst->rho, tgt = rtol * h->hst->snorm;

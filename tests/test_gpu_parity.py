@@ -272,6 +272,11 @@ def test_solve_edge_cases(deferred):
     xd = torch.zeros_like(sd)
     rg = G.gmg_solve(h, xd, torch.zeros_like(sd), 1e-6, 5)
     assert rg["status"] == "GMG_OK" and rg["cycles"] == 0
+    # ... and x is left as it was (the first round of cycles is launched
+    # before the host reads the start's decision, and must do nothing)
+    x1 = torch.ones_like(sd)
+    rg = G.gmg_solve(h, x1, torch.zeros_like(sd), 1e-6, 5)
+    assert rg["cycles"] == 0 and torch.all(x1 == 1.0)
     # max_cycles = 0 -> not converged, x untouched
     x0 = torch.ones_like(sd)
     rg = G.gmg_solve(h, x0, sd, 1e-6, 0)
