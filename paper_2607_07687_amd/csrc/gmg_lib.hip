@@ -96,14 +96,31 @@ __device__ __forceinline__ double residual_column(const Geom& g, const T* __rest
   return acc;
 }
 
-// r = sigma - A x over a chunk of z-planes; one FP64 partial of r^2 per block.
+// Order of the z-blocks of a level-0 pass over x, sigma and L that follows a
+// two-sweep pass.  That pass marches each of its z-chunks upwards, so when it
+// ends the upper part of every chunk is what it touched last and is the most
+// likely to be still in the 256 MB Infinity Cache.  With `per` z-blocks of
+// this kernel per chunk of the pass (per > 1, dividing the z-block count),
+// dispatch index b is mapped so that the top z-block of every chunk goes
+// first, then the one below, and so on; per = 1 keeps the natural order.  A
+// bijection on [0, nzb): results do not depend on it.
+__device__ __forceinline__ int chunk_top_first(int b, int nzb, int per) {
+  if (per <= 1) return b;
+  const int ng = nzb / per;  // chunks of the pass
+  return (b % ng) * per + (per - 1 - b / ng);
+}
+
+// r = sigma - A x over a chunk of z-planes; one FP64 partial of r^2 per block
+// (stored by the block's z-chunk, whatever the dispatch order).
 template <typename T, typename TL>
 __global__ __launch_bounds__(BT) void k_residual(Geom g, Roles<T> X, int role,
                                                  const T* __restrict__ sigma,
                                                  const TL* __restrict__ L, T* r,
-                                                 double* partials, int kchunk, const int* done) {
+                                                 double* partials, int kchunk, const int* done,
+                                                 int zper) {
   if (stopped(done)) return;
-  const int k0 = blockIdx.z * kchunk;
+  const int zb = chunk_top_first(blockIdx.z, gridDim.z, zper);
+  const int k0 = zb * kchunk;
   const double acc = residual_column<T, TL>(g, X.get(role), sigma, L, r,
                                             blockIdx.x * BX + threadIdx.x,
                                             blockIdx.y * BY + threadIdx.y, k0,
@@ -112,7 +129,7 @@ __global__ __launch_bounds__(BT) void k_residual(Geom g, Roles<T> X, int role,
     const int tid = threadIdx.x + BX * threadIdx.y;
     const double s = block_sum(acc, tid, BT);
     if (tid == 0)
-      partials[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+      partials[((long long)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -201,11 +218,12 @@ template <typename T, typename TL>
 __global__ __launch_bounds__(BT) void k_restrict_residual(
     Geom gf, Roles<T> X, int role, const T* __restrict__ sigma, const TL* __restrict__ L,
     Geom gc, int cx, int cy, int cz, T* __restrict__ sigma_c, T* __restrict__ x_c,
-    const int* done) {
+    const int* done, int zper) {
   if (stopped(done)) return;
   __shared__ T rows[BY][BX];
   restrict_tile<T, TL>(rows, gf, X.get(role), sigma, L, gc, cx, cy, cz, sigma_c, x_c,
-                       blockIdx.x * BX, blockIdx.y * BY, blockIdx.z);
+                       blockIdx.x * BX, blockIdx.y * BY,
+                       chunk_top_first(blockIdx.z, gridDim.z, zper));
 }
 
 // Piecewise-constant prolongation + correction on active fine cells:
@@ -833,14 +851,28 @@ static int enq_sweeps(gmg_handle* h, int l, const Roles<T>& X, int r, const T* s
   return r;
 }
 
+// z-blocks of a kernel that follows the nu sweeps of level l, per z-chunk of
+// the two-sweep passes those sweeps ran as (planes_per_block fine planes per
+// z-block of nzb), for chunk_top_first; 1 where the sweeps were not all
+// passes or the chunks do not tile the z-blocks evenly.
+static int zper_after_passes(const gmg_handle* h, int l, int nu, int planes_per_block, int nzb) {
+  const Level& lv = h->lev[l];
+  const int kc = lv.pair_kc;
+  if (kc <= 0 || nu < 2 || nu % 2 != 0 || kc % planes_per_block != 0) return 1;
+  const int per = kc / planes_per_block;
+  return (per > 1 && nzb % per == 0 && (long long)per * planes_per_block * (nzb / per) == lv.g.nz)
+             ? per
+             : 1;
+}
+
 template <typename T, typename TL>
 static void enq_restrict(gmg_handle* h, int l, const Roles<T>& X, int role, const T* sigma,
-                         T* sigma_c, T* x_c, const int* done) {
+                         T* sigma_c, T* x_c, const int* done, int zper = 1) {
   const Level& lv = h->lev[l];
   const Level& lc = h->lev[l + 1];
   const dim3 grid((lv.g.nx + BX - 1) / BX, (lv.g.ny + BY - 1) / BY, lc.g.nz);
   hipLaunchKernelGGL((k_restrict_residual<T, TL>), grid, kBlock, 0, h->s, lv.g, X, role, sigma,
-                     (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c, done);
+                     (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c, done, zper);
 }
 
 // LDS bytes the tail needs when it starts at level lt.
@@ -1019,7 +1051,9 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     }
     role[l] = r;
     if (coarsest) break;
-    enq_restrict<T, TL>(h, l, X, r, sg, (T*)h->lev[l + 1].sigma, (T*)h->lev[l + 1].x[0], done);
+    enq_restrict<T, TL>(h, l, X, r, sg, (T*)h->lev[l + 1].sigma, (T*)h->lev[l + 1].x[0], done,
+                        pcg ? 1 : zper_after_passes(h, l, nsw, h->lev[l].c[2],
+                                                    h->lev[l + 1].g.nz));
   }
   if (lt < nl) {
     enq_tail<T, TL>(h, lt, done);
@@ -1067,8 +1101,12 @@ static long long enq_resnorm(gmg_handle* h, const Roles<T>& X, int role, const T
                              const TL* L, T* r, long long off, const int* done) {
   const Level& lv = h->lev[0];
   const dim3 gr = red_grid(lv.g);
+  const int zper = h->p.smoother == GMG_SMOOTH_RBGS
+                       ? zper_after_passes(h, 0, h->nlev > 1 ? h->p.nu_post : h->p.nu_coarse,
+                                           kResChunk, (int)gr.z)
+                       : 1;
   hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, X, role, sigma, L, r,
-                     h->partials + off, kResChunk, done);
+                     h->partials + off, kResChunk, done, zper);
   return nblocks(gr);
 }
 
@@ -1384,7 +1422,7 @@ static gmg_status ir_outer_step(gmg_handle* h, double* x, const double* sigma, i
   const long long np = nblocks(gr);
   const Roles<double> X{{x, x, x}, nullptr};
   hipLaunchKernelGGL((k_residual<double, double>), gr, kBlock, 0, h->s, lv.g, X, 0, sigma,
-                     (const double*)h->L0x, h->r64, h->partials, kResChunk, &h->ir->done);
+                     (const double*)h->L0x, h->r64, h->partials, kResChunk, &h->ir->done, 1);
   hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(256), 0, h->s, h->partials, np, h->ir);
   hipLaunchKernelGGL(k_scale_cast, gr, kBlock, 0, h->s, lv.g, (const double*)h->r64, h->ir,
                      h->b32, h->e32, h->partials + h->maxpart, kResChunk);
@@ -1606,7 +1644,7 @@ gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma, void* r
     Roles<double> X{{(double*)x, (double*)x, (double*)x}, nullptr};
     hipLaunchKernelGGL((k_residual<double, double>), gr, kBlock, 0, h->s, lv.g, X, 0,
                        (const double*)sigma, (const double*)h->L0x, (double*)r, pa, kResChunk,
-                       nullptr);
+                       nullptr, 1);
     if (snorm)
       hipLaunchKernelGGL((k_masked_sumsq<double>), gr, kBlock, 0, h->s, lv.g,
                          (const double*)sigma, lv.active, h->partials + h->maxpart, kResChunk);
@@ -1614,7 +1652,7 @@ gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma, void* r
     DISPATCH_CYCLE(h, {
       Roles<T> X{{(T*)x, (T*)x, (T*)x}, nullptr};
       hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, X, 0, (const T*)sigma,
-                         (const TL*)lv.L, (T*)r, pa, kResChunk, nullptr);
+                         (const TL*)lv.L, (T*)r, pa, kResChunk, nullptr, 1);
       if (snorm)
         hipLaunchKernelGGL((k_masked_sumsq<T>), gr, kBlock, 0, h->s, lv.g, (const T*)sigma,
                            lv.active, h->partials + h->maxpart, kResChunk);
