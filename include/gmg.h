@@ -115,8 +115,10 @@ typedef struct gmg_params {
                             bitwise the same result.  On at level 0 by
                             default; gmg_autotune and gmg_set_pair_sweeps
                             choose per level.  Needs FP32 cycles, the
-                            red-black smoother and an even nx; the deferred
-                            norm's sweeps stay single.  0: separate sweeps.   */
+                            red-black smoother, an even nx and at most 2^28
+                            cells on the level (32-bit buffer offsets); the
+                            deferred norm's sweeps stay single.  0: separate
+                            sweeps.                                           */
   double omega0;         /* relaxation factor at the start of a solve (1.0)   */
   double omega_min;      /* lower bound (0.1)                                 */
   double omega_max;      /* upper bound (1.0)                                 */
@@ -363,7 +365,8 @@ gmg_status gmg_set_tiles(gmg_handle* h, int32_t level, int32_t ty, int32_t kchun
 /* Run the smoothing steps of one level with two-sweep passes on tiles of
  * 64 x ty cells (ty 8 or 16) with kchunk z-planes per workgroup (kchunk = 0:
  * separate sweeps, ty ignored).  GMG_EINVAL if the handle's parameters do not
- * allow passes (pair_sweeps 0, FP64 cycles, the PCG smoother or an odd nx),
+ * allow passes (pair_sweeps 0, FP64 cycles, the PCG smoother, an odd nx or
+ * more than 2^28 cells on the level),
  * ty is not 8 or 16, or kchunk is outside [0, nz].  Results do not depend on
  * the choice.  Recorded graphs are dropped. */
 gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t ty, int32_t kchunk);
