@@ -38,7 +38,7 @@
 
 #include <type_traits>
 
-#include "gmg_sweep.h"  // wrap_coord, 2-wide loads
+#include "gmg_sweep.h"  // wrap_coord (and gmg_device.h: relax_cell, xcd_tile)
 
 namespace gmg {
 
