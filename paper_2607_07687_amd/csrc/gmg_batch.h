@@ -28,7 +28,9 @@ struct BLevel {
   const int* sel;
   const float* sigma;  // level 0: the scaled correction rhs b; coarse: restricted rhs
   float* sigma_next;   // restriction output (level l+1)
-  float* x_next0;      // level l+1 iterate role 0 (zeroed by restriction, prolongation source)
+  float* x_next0;      // level l+1 iterate role 0 (zeroed by restriction)
+  float* x_next1;      // level l+1 iterate role 1 (the prolongation source is the role
+                       // that level's smoothing ended on)
   const int* done;     // the problem's inner-solve flag
   const double* omega;
 };
@@ -58,16 +60,20 @@ struct BTile {
   int slot;            // partial slot (residual tiles)
 };
 
+// Fused sweep of every tile; corr_role >= 0 folds the prolongation of the
+// next level's iterate role corr_role into it (not on a problem's coarsest
+// level, which has no next level).
 template <typename TL, int TY>
 __global__ __launch_bounds__(32 * TY) void k_b_sweep(const BLevel<TL>* __restrict__ lv,
                                                      const BTile* __restrict__ tiles, int rs,
-                                                     int rd, int with_corr) {
+                                                     int rd, int corr_role) {
   const BTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const BLevel<TL>& d = lv[t.d];
   if (*d.done) return;
   __shared__ SweepSmem<float, TY> sm;
   const Roles<float> X{{d.x[0], d.x[1], d.x[2]}, d.sel};
-  const float* xc = (with_corr && !d.coarsest) ? d.x_next0 : nullptr;
+  const float* xc =
+      (corr_role >= 0 && !d.coarsest) ? (corr_role ? d.x_next1 : d.x_next0) : nullptr;
   const float omega = (float)(*d.omega);
   if (d.vec2) {
     SweepArgs<float, TL, TY, 2> a{d.g, X.get(rs), d.sigma, d.L, xc, d.active, d.gc,
@@ -78,6 +84,29 @@ __global__ __launch_bounds__(32 * TY) void k_b_sweep(const BLevel<TL>* __restric
                                   d.cx, d.cy, d.cz};
     rb_sweep_tile<float, TL, TY, 1>(sm, a, X.get(rd), t.i0, t.j0, t.k0, t.k1, omega);
   }
+}
+
+// Two-sweep pass of every pass tile (two sweeps of one smoothing step in one
+// launch, bitwise two fused sweeps).  PROL: the first post-smoothing pass,
+// folding the prolongation of the next level's iterate role corr_role; on a
+// problem's coarsest level it adds nothing (the mask then reads zero, and
+// the level's own iterate stands in for the coarse one).
+template <typename TL, int TY, bool PROL>
+__global__ __launch_bounds__(S2Cfg<TY>::NTB) void k_b_sweep2(const BLevel<TL>* __restrict__ lv,
+                                                             const BTile* __restrict__ tiles,
+                                                             int rs, int rd, int corr_role) {
+  const BTile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const BLevel<TL>& d = lv[t.d];
+  if (*d.done) return;
+  __shared__ S2Smem<float, TY> sm;
+  const Roles<float> X{{d.x[0], d.x[1], d.x[2]}, d.sel};
+  const float omega = (float)(*d.omega);
+  const bool corr = PROL && !d.coarsest;
+  const float* xc = corr ? (corr_role ? d.x_next1 : d.x_next0) : X.get(rs);
+  const S2Args<float, TL> a{d.g,      X.get(rs),       d.sigma,         d.L,
+                            xc,       d.active,        corr ? d.gc : d.g, corr ? d.cx : 1,
+                            corr ? d.cy : 1, corr ? d.cz : 1, corr ? 1 : 0};
+  rb_sweep2_tile<float, TL, TY, PROL>(sm, a, X.get(rd), t.i0, t.j0, t.k0, t.k1, omega);
 }
 
 template <typename TL>
@@ -314,9 +343,11 @@ struct gmg_batch {
   void* lv;                 // BLevel<TL>[] for all (problem, level)
   void* ov;                 // BOuter<TL>[n]
   BTile* sweep_tiles;       // per depth, concatenated
+  BTile* pair_tiles;        // two-sweep pass tiles per depth (depths where all allow it)
   BTile* rest_tiles;
   BTile* res_tiles;         // level-0 residual / update tiles
   std::vector<int> sweep_off, sweep_cnt, rest_off, rest_cnt;
+  std::vector<int> pair_off, pair_cnt, pair_ty;  // pair_cnt 0: separate sweeps
   int res_cnt;
   // captured whole-solve graph and what it was recorded for
   CapturedSeq graph;
@@ -367,6 +398,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
       }
       d.sigma_next = coarsest ? nullptr : (float*)h->lev[l + 1].sigma;
       d.x_next0 = coarsest ? nullptr : (float*)h->lev[l + 1].x[0];
+      d.x_next1 = coarsest ? nullptr : (float*)h->lev[l + 1].x[1];
       d.done = &h->st->done;
       d.omega = &h->st->omega;
       const int di = (int)lvs.size();
@@ -408,8 +440,50 @@ gmg_status batch_build_tables(gmg_batch* b) {
     o.st = h->st;
     ovs.push_back(o);
   }
+  // two-sweep pass tiles, at depths where every problem that reaches the
+  // depth allows passes (even nx, at most 2^28 cells; FP32 cycles and the
+  // red-black smoother hold for every batch): 64 x 16 tiles at depth 0 and
+  // 64 x 8 below, with z-chunks sized so that a depth's tiles fill about two
+  // rounds of the CUs.  Elsewhere the depth keeps separate sweeps.
+  std::vector<std::vector<BTile>> pt(b->depth);
+  b->pair_ty.assign(b->depth, 0);
+  if (b->p0.pair_sweeps && (b->p0.nu_pre >= 2 || b->p0.nu_post >= 2)) {
+    for (int l = 0; l < b->depth; ++l) {
+      const int ty = (l == 0) ? 16 : 8;
+      bool ok = true;
+      long long xy = 0;
+      for (int p = 0; p < b->n; ++p) {
+        const gmg_handle* h = b->h[p];
+        if (l >= h->nlev) continue;
+        const Geom& g = h->lev[l].g;
+        if (g.nx % 2 != 0 || g.n > S2_MAX_CELLS) ok = false;
+        xy += (long long)((g.nx + S2_TX - 1) / S2_TX) * ((g.ny + ty - 1) / ty);
+      }
+      if (!ok || xy == 0) continue;
+      const int chunks = std::max(1, (int)std::lround(2.0 * kCUs / (double)xy));
+      for (int p = 0; p < b->n; ++p) {
+        const gmg_handle* h = b->h[p];
+        if (l >= h->nlev) continue;
+        const Geom& g = h->lev[l].g;
+        const int di = lv_index[p * kMaxLevels + l];
+        const int kc = std::min(g.nz, std::max(2, (g.nz + chunks - 1) / chunks));
+        for (int kz = 0; kz < g.nz; kz += kc)
+          for (int y0 = 0; y0 < g.ny; y0 += ty)
+            for (int x0 = 0; x0 < g.nx; x0 += S2_TX)
+              pt[l].push_back(BTile{di, x0, y0, kz, std::min(g.nz, kz + kc), 0});
+      }
+      b->pair_ty[l] = ty;
+    }
+  }
   // flatten
-  std::vector<BTile> swf, rtf;
+  std::vector<BTile> swf, rtf, ptf;
+  b->pair_off.assign(b->depth, 0);
+  b->pair_cnt.assign(b->depth, 0);
+  for (int l = 0; l < b->depth; ++l) {
+    b->pair_off[l] = (int)ptf.size();
+    b->pair_cnt[l] = (int)pt[l].size();
+    ptf.insert(ptf.end(), pt[l].begin(), pt[l].end());
+  }
   b->sweep_off.assign(b->depth, 0);
   b->sweep_cnt.assign(b->depth, 0);
   b->rest_off.assign(b->depth, 0);
@@ -426,6 +500,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
   HIP_TRY(hipMalloc(&b->lv, lvs.size() * sizeof(BLevel<TL>)));
   HIP_TRY(hipMalloc(&b->ov, ovs.size() * sizeof(BOuter<TL>)));
   HIP_TRY(hipMalloc(&b->sweep_tiles, std::max<size_t>(1, swf.size()) * sizeof(BTile)));
+  HIP_TRY(hipMalloc(&b->pair_tiles, std::max<size_t>(1, ptf.size()) * sizeof(BTile)));
   HIP_TRY(hipMalloc(&b->rest_tiles, std::max<size_t>(1, rtf.size()) * sizeof(BTile)));
   HIP_TRY(hipMalloc(&b->res_tiles, std::max<size_t>(1, rs.size()) * sizeof(BTile)));
   HIP_TRY(hipMemcpy(b->lv, lvs.data(), lvs.size() * sizeof(BLevel<TL>), hipMemcpyHostToDevice));
@@ -434,6 +509,8 @@ gmg_status batch_build_tables(gmg_batch* b) {
     HIP_TRY(hipMemcpy(b->sweep_tiles, swf.data(), swf.size() * sizeof(BTile), hipMemcpyHostToDevice));
   if (!rtf.empty())
     HIP_TRY(hipMemcpy(b->rest_tiles, rtf.data(), rtf.size() * sizeof(BTile), hipMemcpyHostToDevice));
+  if (!ptf.empty())
+    HIP_TRY(hipMemcpy(b->pair_tiles, ptf.data(), ptf.size() * sizeof(BTile), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->res_tiles, rs.data(), rs.size() * sizeof(BTile), hipMemcpyHostToDevice));
   return GMG_OK;
 }
@@ -450,6 +527,22 @@ gmg_status batch_set_caller(gmg_batch* b, double* const* xs, const double* const
   }
   HIP_TRY(hipMemcpy(b->ov, ovs.data(), b->n * sizeof(BOuter<TL>), hipMemcpyHostToDevice));
   return GMG_OK;
+}
+
+// The two-sweep pass of depth l on every pass tile: X[rd] = sweep(sweep(X[rs])).
+template <typename TL, bool PROL>
+void batch_pass(const gmg_batch* b, hipStream_t s, const gmg::BLevel<TL>* lv, int l, int rs,
+                int rd, int corr_role) {
+  using namespace gmg;
+  auto go = [&](auto tyc) {
+    constexpr int TY = decltype(tyc)::value;
+    hipLaunchKernelGGL((k_b_sweep2<TL, TY, PROL>), dim3(b->pair_cnt[l]), dim3(S2Cfg<TY>::NTB),
+                       0, s, lv, b->pair_tiles + b->pair_off[l], rs, rd, corr_role);
+  };
+  if (b->pair_ty[l] == 16)
+    go(std::integral_constant<int, 16>{});
+  else
+    go(std::integral_constant<int, 8>{});
 }
 
 template <typename TL>
@@ -473,13 +566,21 @@ gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, double rtol, int max
                        p.omega0);
     for (int c = 0; c < max_inner; ++c) {
       int role[kMaxLevels];
+      // consecutive sweeps of a smoothing step run as two-sweep passes where
+      // the depth has pass tiles (each pass moves the iterate one role on)
       for (int l = 0; l < b->depth; ++l) {  // descent
         int r = 0;
-        for (int q = 0; q < p.nu_pre; ++q) {
+        for (int q = 0; q < p.nu_pre;) {
           const int rd = next_role(l, r);
-          if (b->sweep_cnt[l])
-            hipLaunchKernelGGL((k_b_sweep<TL, TY>), dim3(b->sweep_cnt[l]), dim3(32 * TY), 0, s,
-                               lv, b->sweep_tiles + b->sweep_off[l], r, rd, 0);
+          if (b->pair_cnt[l] && p.nu_pre - q >= 2) {
+            batch_pass<TL, false>(b, s, lv, l, r, rd, -1);
+            q += 2;
+          } else {
+            if (b->sweep_cnt[l])
+              hipLaunchKernelGGL((k_b_sweep<TL, TY>), dim3(b->sweep_cnt[l]), dim3(32 * TY), 0, s,
+                                 lv, b->sweep_tiles + b->sweep_off[l], r, rd, -1);
+            q += 1;
+          }
           r = rd;
         }
         role[l] = r;
@@ -489,11 +590,22 @@ gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, double rtol, int max
       }
       for (int l = b->depth - 1; l >= 0; --l) {  // ascent (coarsest levels finish smoothing)
         int r = role[l];
-        for (int q = 0; q < p.nu_post; ++q) {
+        // the prolongation source: the role level l+1's smoothing ended on
+        const int cr = (l + 1 < b->depth) ? role[l + 1] : 0;
+        for (int q = 0; q < p.nu_post;) {
           const int rd = next_role(l, r);
-          if (b->sweep_cnt[l])
-            hipLaunchKernelGGL((k_b_sweep<TL, TY>), dim3(b->sweep_cnt[l]), dim3(32 * TY), 0, s,
-                               lv, b->sweep_tiles + b->sweep_off[l], r, rd, q == 0 ? 1 : 0);
+          if (b->pair_cnt[l] && p.nu_post - q >= 2) {
+            if (q == 0)
+              batch_pass<TL, true>(b, s, lv, l, r, rd, cr);
+            else
+              batch_pass<TL, false>(b, s, lv, l, r, rd, -1);
+            q += 2;
+          } else {
+            if (b->sweep_cnt[l])
+              hipLaunchKernelGGL((k_b_sweep<TL, TY>), dim3(b->sweep_cnt[l]), dim3(32 * TY), 0, s,
+                                 lv, b->sweep_tiles + b->sweep_off[l], r, rd, q == 0 ? cr : -1);
+            q += 1;
+          }
           r = rd;
         }
         role[l] = r;
@@ -515,6 +627,7 @@ void free_batch(gmg_batch* b) {
   (void)hipFree(b->lv);
   (void)hipFree(b->ov);
   (void)hipFree(b->sweep_tiles);
+  (void)hipFree(b->pair_tiles);
   (void)hipFree(b->rest_tiles);
   (void)hipFree(b->res_tiles);
   if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
@@ -642,10 +755,11 @@ gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps) {
   (void)hipFree(b->lv);
   (void)hipFree(b->ov);
   (void)hipFree(b->sweep_tiles);
+  (void)hipFree(b->pair_tiles);
   (void)hipFree(b->rest_tiles);
   (void)hipFree(b->res_tiles);
   b->lv = b->ov = nullptr;
-  b->sweep_tiles = b->rest_tiles = b->res_tiles = nullptr;
+  b->sweep_tiles = b->pair_tiles = b->rest_tiles = b->res_tiles = nullptr;
   if (b->graph.exec) {
     HIP_TRY(hipGraphExecDestroy(b->graph.exec));
     b->graph.exec = nullptr;

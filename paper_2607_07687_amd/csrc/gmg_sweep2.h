@@ -147,6 +147,10 @@ struct S2Args {
   const uint8_t* active;
   Geom gc;
   int cx, cy, cz;
+  // PROL: 0 adds no correction (the mask then reads zero everywhere; xc and
+  // gc must still describe readable memory, e.g. the level's own iterate and
+  // geometry with factors 1)
+  int corr = 1;
 };
 
 // Issue the loads of plane m for the column with lane offsets vo4, vo2, vo1
@@ -236,7 +240,8 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
                                                    S2_RSRC_W3),
                  __builtin_amdgcn_make_buffer_rsrc((void*)(a.L + 2 * g.n), 0,
                                                    (int)sizeof(TL) * nb, S2_RSRC_W3),
-                 __builtin_amdgcn_make_buffer_rsrc((void*)a.active, 0, nb, S2_RSRC_W3),
+                 __builtin_amdgcn_make_buffer_rsrc((void*)a.active, 0, a.corr ? nb : 0,
+                                                   S2_RSRC_W3),
                  __builtin_amdgcn_make_buffer_rsrc((void*)a.S, 0, 0, S2_RSRC_W3)};
   // LDS indices (padded by one): the thread's row R and its neighbours RN
   // (y+1) and RS (y-1); its pair column c and the pairs to the west cw and
@@ -410,8 +415,10 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     if (k < k1) step(k, la, lb);
   } else {
     // five steps per iteration: the five plane registers then rotate by
-    // renaming instead of by moves
-    for (; k + 4 < k1; k += 5) {
+    // renaming instead of by moves (with FP32 faces; with BF16 faces the
+    // unrolled loop needs more than 128 VGPRs and spills, the plain loop
+    // fewer than 100)
+    for (; sizeof(TL) == 4 && k + 4 < k1; k += 5) {
       step(k, la, la);
       step(k + 1, la, la);
       step(k + 2, la, la);

@@ -56,6 +56,36 @@ def test_batch_equals_single_solves(storage):
     b.close()
 
 
+@pytest.mark.parametrize("nu", [(3, 1), (1, 2)])
+def test_batch_other_sweep_counts(nu):
+    # odd sweep counts mix two-sweep passes with single sweeps, and leave the
+    # coarse levels' iterate in either of their two buffers: the batch must
+    # take the prolongation from the one the smoothing ended on
+    require_gpu()
+    specs = P.batch_specs(count=4, seed=5)
+    probs = [P.sphere_box(sp["n"], sp["centre"], sp["radius"], "uniform", sp["seed"])
+             for sp in specs]
+    Ls = [dev(L, "f64") for L, _, _ in probs]
+    ss = [dev(s, "f64") for _, s, _ in probs]
+    params = []
+    for L, _, per in probs:
+        prm = _params(L, per, "f32")
+        prm.nu_pre, prm.nu_post, prm.nu_coarse = nu[0], nu[1], nu[0] + nu[1]
+        params.append(prm)
+    b = G.gmg_batch_setup(params, Ls)
+    xs = [torch.zeros_like(s) for s in ss]
+    infos = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=30, max_inner=8)
+    for p, prm in enumerate(params):
+        h = G.gmg_setup(prm, Ls[p])
+        x1 = torch.zeros_like(ss[p])
+        r1 = G.gmg_solve_ir(h, x1, ss[p], rtol=1e-10, max_outer=30, max_inner=8)
+        say(f"  nu {nu} p{p} outer {infos[p]['outer']} final {infos[p]['history'][-1]:.2e}")
+        assert infos[p]["history"] == r1["history"]
+        assert torch.equal(xs[p], x1)
+        h.close()
+    b.close()
+
+
 def test_batch_matches_oracle_subset():
     require_gpu()
     specs = P.batch_specs(count=3, seed=3)
