@@ -105,7 +105,7 @@ __device__ __forceinline__ double residual_column(const Geom& g, const T* __rest
 // first, then the one below, and so on; per = 1 keeps the natural order.  A
 // bijection on [0, nzb): results do not depend on it.
 __device__ __forceinline__ int chunk_top_first(int b, int nzb, int per) {
-  if (per <= 1) return b;
+  if (per <= 1 || nzb % per != 0) return b;
   const int ng = nzb / per;  // chunks of the pass
   return (b % ng) * per + (per - 1 - b / ng);
 }
