@@ -43,6 +43,26 @@ KERNELS = {
 }
 
 
+def device_copy_gbs(stream, mib=256, reps=10):
+    """Bandwidth of a plain device-to-device copy of `mib` MiB (read + write
+    bytes over time, HIP events), the practical ceiling the kernels are also
+    reported against."""
+    n = mib * (1 << 20) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -387,6 +407,7 @@ def main():
     fused_ms = launch_ms(1)
     kind = "pair" if pair_kc else "fused"
     launch = pass_ms if pair_kc else fused_ms
+    copy_gbs = device_copy_gbs(stream)
     cells = 256 ** 3
     alg_bytes = SWEEP_BYTES_PER_CELL * cells
     achieved = alg_bytes / (launch * 1e-3) / 1e9
@@ -427,7 +448,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kind),
                      "traffic_unit": "HBM bytes per launch (counters)",
                      "avg_launch_us": launch * 1e3,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "level0_smoothing": {
             "two_sweep_pass_us": pass_ms * 1e3 if pass_ms else None,
             "fused_sweep_us": fused_ms * 1e3,
