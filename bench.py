@@ -47,6 +47,7 @@ def device_copy_gbs(stream, mib=256, reps=10):
     """Bandwidth of a plain device-to-device copy of `mib` MiB (read + write
     bytes over time, HIP events), the practical ceiling the kernels are also
     reported against."""
+    import torch
     n = mib * (1 << 20) // 4
     a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
