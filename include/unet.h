@@ -52,8 +52,9 @@ typedef struct unet_shape {
 
 /* y = act(conv(x, w) + bias).  taps = 27 (3x3x3) or 1 (1x1x1); relu 0/1.
  * out_f32: if non-NULL, FP32 output [voxels][y.ld] at channel y.off written
- * instead of the BF16 view y (y.p may then be NULL).  x.c multiple of 8,
- * y.c multiple of 16. */
+ * instead of the BF16 view y (y.p may then be NULL).  x.c multiple of 8 and
+ * at most 256, y.c multiple of 16, fewer than 2^31 voxels (UNET_EINVAL
+ * otherwise). */
 unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* bias,
                           int32_t taps, unet_act y, float* out_f32, int32_t relu,
                           void* stream);

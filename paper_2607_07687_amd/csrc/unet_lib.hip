@@ -129,43 +129,75 @@ __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* 
   const long long vbase = (long long)blockIdx.x * 256 + wave * 64;
   const int K = taps * cin;
   const int ksteps = (K + 31) / 32;
-  Vox vx[4];
-  bool vok[4];
+  // Each of the lane's four voxels: its index (the host keeps voxel counts
+  // below 2^31) and a mask of the taps that land inside the grid (bit t for
+  // tap t in (kd, kh, kw) order; zero padding elsewhere).  A tap's neighbour
+  // is then the voxel index plus an offset that is the same for every voxel.
+  int vi[4];
+  uint32_t vm[4];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
     const long long v = vbase + mb * 16 + (lane & 15);
-    vok[mb] = v < nvox;
-    vx[mb] = vox_of(vok[mb] ? v : 0, s);
+    const bool ok = v < nvox;
+    const Vox a = vox_of(ok ? v : 0, s);
+    vi[mb] = ok ? (int)v : 0;
+    uint32_t m = 0;
+    if (taps == 1) {
+      m = 1u;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        const int dd = a.d + t / 9 - 1, dh = a.h + (t / 3) % 3 - 1, dw = a.w + t % 3 - 1;
+        const bool in = dd >= 0 && dd < s.d && dh >= 0 && dh < s.h && dw >= 0 && dw < s.w;
+        m |= (in ? 1u : 0u) << t;
+      }
+    }
+    vm[mb] = ok ? m : 0u;
   }
+  const int hw = s.h * s.w;
+  // k / cin for k < 27 cin by a multiply and shift, exact for cin <= 384
+  const uint32_t rcin = ((1u << 22) + (uint32_t)cin - 1) / (uint32_t)cin;
+  const int kl = 8 * (lane >> 4);
+  // Operands of K step ks.  Every load is issued (at the voxel itself or
+  // at a clamped k when the value is padding), and padding is zeroed after
+  // the load, so that no branch sits between the loads of a step and the
+  // next step's loads can be in flight while this step's MFMAs run.
+  auto load = [&](int ks, bf16x8 (&a)[4], bf16x8 (&b)[NB]) {
+    const int k = ks * 32 + kl;
+    const bool kin = k < K;
+    const int kk = kin ? k : K - 8;
+    const int t = (int)(((uint32_t)kk * rcin) >> 22), ci = kk - t * cin;
+    const int off = (taps == 1) ? 0 : (t / 9 - 1) * hw + ((t / 3) % 3 - 1) * s.w + (t % 3 - 1);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const bool use = kin && ((vm[mb] >> t) & 1u);
+      const bf16x8 v = ld8(x + (long long)(use ? vi[mb] + off : vi[mb]) * xld + xoff + ci);
+      a[mb] = use ? v : zero8();
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 v = ld8(w + (long long)(nb * 16 + (lane & 15)) * K + kk);
+      b[nb] = kin ? v : zero8();
+    }
+  };
   f32x4 acc[4][NB];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int kl = 8 * (lane >> 4);
+  bf16x8 a0[4], b0[NB], a1[4], b1[NB];
+  load(0, a0, b0);
   for (int ks = 0; ks < ksteps; ++ks) {
-    const int k = ks * 32 + kl;
-    bf16x8 a[4], b[NB];
-    if (k < K) {
-      const int t = k / cin, ci = k - t * cin;
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const long long nb_v = vok[mb] ? tap_nbr(vx[mb], s, taps, t) : -1;
-        a[mb] = (nb_v >= 0) ? ld8(x + nb_v * xld + xoff + ci) : zero8();
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) b[nb] = ld8(w + (long long)(nb * 16 + (lane & 15)) * K + k);
-    } else {
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) a[mb] = zero8();
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) b[nb] = zero8();
-    }
+    load(ks + 1 < ksteps ? ks + 1 : ks, a1, b1);
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[mb], b0[nb], acc[mb][nb], 0, 0, 0);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) a0[mb] = a1[mb];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b0[nb] = b1[nb];
   }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -577,7 +609,9 @@ unet_status unet_mfma_selfcheck(const void* a, const void* b, float* out, void* 
 unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* bias, int32_t taps,
                           unet_act y, float* out_f32, int32_t relu, void* stream) {
   if (!shape_ok(s) || !w || (taps != 27 && taps != 1)) return ufail(UNET_EINVAL, "bad conv args");
-  if (!act_ok(x, 8)) return ufail(UNET_EINVAL, "bad input view (ld/off/c multiples of 8)");
+  if (!act_ok(x, 8) || x.c > 256)
+    return ufail(UNET_EINVAL, "bad input view (ld/off/c multiples of 8, c <= 256)");
+  if (nvox_of(s) >= (1LL << 31)) return ufail(UNET_EINVAL, "too many voxels (limit 2^31)");
   if (y.c % 16 || y.c > 128 || y.c <= 0 || y.ld % 8 || y.off % 8 || y.off + y.c > y.ld ||
       (!out_f32 && !y.p))
     return ufail(UNET_EINVAL, "bad output view (c multiple of 16, <= 128)");
