@@ -144,6 +144,10 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(PCGState* st, const double* p
 }
 
 // X[rd] = X[rs] + alpha p, r -= alpha q, z = r / s; partials of r.z and r.r.
+// The z-chunks go top first: k_pcg_pq, which runs before and after this
+// kernel, goes bottom first, so each kernel starts on the planes the other
+// touched last, the most likely to be still in the Infinity Cache.  Partials
+// keep the chunk's index, so the reductions are unchanged.
 template <typename T>
 __global__ __launch_bounds__(BT) void k_pcg_xr(Geom g, Roles<T> X, int rs, int rd,
                                                const T* __restrict__ p, T* __restrict__ r,
@@ -156,7 +160,8 @@ __global__ __launch_bounds__(BT) void k_pcg_xr(Geom g, Roles<T> X, int rs, int r
   const T* xs = X.get(rs);
   T* xd = X.get(rd);
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-  const int k0 = blockIdx.z * kchunk, k1 = min(g.nz, k0 + kchunk);
+  const int zb = (int)gridDim.z - 1 - (int)blockIdx.z;
+  const int k0 = zb * kchunk, k1 = min(g.nz, k0 + kchunk);
   double arz = 0.0, arr = 0.0;
   if (i < g.nx && j < g.ny) {
     for (int k = k0; k < k1; ++k) {
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(BT) void k_pcg_xr(Geom g, Roles<T> X, int rs, int r
     }
   }
   const int tid = threadIdx.x + BX * threadIdx.y;
-  const long long blk = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const long long blk = ((long long)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const double srz = block_sum(arz, tid, BT);
   __syncthreads();
   const double srr = block_sum(arr, tid, BT);
