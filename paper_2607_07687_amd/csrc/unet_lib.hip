@@ -11,6 +11,7 @@
 // masked MSE, Adam) is elementwise or a small reduction and HBM-bound.
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -210,6 +211,109 @@ __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* 
         const long long v = vbase + mb * 16 + 4 * (lane >> 4) + r;
         if (v >= nvox) continue;
         float val = acc[mb][nb][r] + bb;
+        if (relu) val = fmaxf(val, 0.f);
+        if (yf)
+          yf[v * yld + yoff + co] = val;
+        else
+          y[v * yld + yoff + co] = f2bf(val);
+      }
+    }
+}
+
+// The 3x3x3 convolution of CIN (16 or 32) input channels on grids with w a
+// multiple of 64 and h a multiple of 4: a workgroup's output tile is 64 (w)
+// x 4 (h) voxels of one plane, one row per wave.  The tile's input
+// neighbourhood (66 x 6 x 3 voxels, zeros outside the grid) is staged in LDS
+// once, and every tap's A operand is then read from LDS instead of being
+// gathered from global memory 27 times.  The K steps, the operands and the
+// MFMA order are those of k_conv_fwd, so the output is bitwise the same.
+constexpr int kTW = 64, kTH = 4;
+constexpr int kSW = kTW + 2, kSH = kTH + 2, kSlots = 3 * kSH * kSW;
+
+template <int CIN, int NB>
+__global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
+                                                       const uint16_t* __restrict__ x, int xld,
+                                                       int xoff, const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       uint16_t* __restrict__ y, int yld,
+                                                       int yoff, float* __restrict__ yf,
+                                                       int relu) {
+  static_assert(CIN == 16 || CIN == 32, "tiled conv: 16 or 32 input channels");
+  __shared__ __align__(16) uint16_t tile[kSlots * CIN];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tw = s.w / kTW, th = s.h / kTH;
+  int b = blockIdx.x;
+  const int w0 = (b % tw) * kTW;
+  b /= tw;
+  const int h0 = (b % th) * kTH;
+  b /= th;
+  const int d0 = b % s.d, n0 = b / s.d;
+  // stage the neighbourhood: 16-byte pieces of 8 channels, four loads in
+  // flight per thread before their stores
+  constexpr int P8 = CIN / 8, NP = kSlots * P8;
+  for (int p0 = threadIdx.x; p0 < NP; p0 += 4 * 256) {
+    uint4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = min(p0 + u * 256, NP - 1);
+      const int slot = p / P8, c8 = p - slot * P8;
+      const int sw = slot % kSW, sh = (slot / kSW) % kSH, sd = slot / (kSW * kSH);
+      const int dd = d0 - 1 + sd, hh = h0 - 1 + sh, ww = w0 - 1 + sw;
+      const bool in = dd >= 0 && dd < s.d && hh >= 0 && hh < s.h && ww >= 0 && ww < s.w;
+      const long long vox = in ? (((long long)n0 * s.d + dd) * s.h + hh) * s.w + ww : 0;
+      const uint4 g = *reinterpret_cast<const uint4*>(x + vox * xld + xoff + c8 * 8);
+      v[u] = in ? g : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = p0 + u * 256;
+      if (p < NP) *reinterpret_cast<uint4*>(tile + p * 8) = v[u];
+    }
+  }
+  __syncthreads();
+  constexpr int K = 27 * CIN;
+  constexpr int ksteps = (K + 31) / 32;
+  const int kl = 8 * (lane >> 4);
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < ksteps; ++ks) {
+    const int k = ks * 32 + kl;
+    const bool kin = k < K;
+    const int kk = kin ? k : K - 8;
+    const int t = kk / CIN, ci = kk % CIN;
+    const int dd = t / 9, dh = (t / 3) % 3, dw = t % 3;
+    bf16x8 a[4], bb[NB];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const int slot = (dd * kSH + wave + dh) * kSW + mb * 16 + (lane & 15) + dw;
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + slot * CIN + ci);
+      a[mb] = kin ? v : zero8();
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 v = ld8(w + (long long)(nb * 16 + (lane & 15)) * K + kk);
+      bb[nb] = kin ? v : zero8();
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
+  }
+  const long long vbase = (((long long)n0 * s.d + d0) * s.h + h0 + wave) * s.w + w0;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int co = nb * 16 + (lane & 15);
+      const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long v = vbase + mb * 16 + 4 * (lane >> 4) + r;
+        float val = acc[mb][nb][r] + bv;
         if (relu) val = fmaxf(val, 0.f);
         if (yf)
           yf[v * yld + yoff + co] = val;
@@ -621,6 +725,27 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
   const uint16_t* xp = (const uint16_t*)x.p;
   const uint16_t* wp = (const uint16_t*)w;
   uint16_t* yp = (uint16_t*)y.p;
+  // LDS-tiled form for the large grids (w a multiple of 64, h of 4), 16 or
+  // 32 input channels and 16 or 32 output channels
+  if (taps == 27 && s.w % kTW == 0 && s.h % kTH == 0 && (x.c == 16 || x.c == 32) &&
+      (y.c == 16 || y.c == 32)) {
+    const dim3 tg((unsigned)(nv / (kTW * kTH)));
+    auto go = [&](auto cinc, auto nbc) {
+      constexpr int CIN = decltype(cinc)::value, NB = decltype(nbc)::value;
+      hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB>), tg, dim3(256), 0, st, s, xp, x.ld, x.off, wp,
+                         bias, yp, y.ld, y.off, out_f32, relu);
+    };
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
+    using N1 = std::integral_constant<int, 1>;
+    using N2 = std::integral_constant<int, 2>;
+    if (x.c == 16)
+      (y.c == 16) ? go(I16{}, N1{}) : go(I16{}, N2{});
+    else
+      (y.c == 16) ? go(I32{}, N1{}) : go(I32{}, N2{});
+    UHIP(hipGetLastError());
+    return UNET_OK;
+  }
   switch (y.c / 16) {
     case 1:
       hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp, bias,
