@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* 
     }
 }
 
-// The 3x3x3 convolution of CIN (8, 16 or 32) input channels on grids with w a
+// The 3x3x3 convolution of CIN (8 to 64) input channels on grids with w a
 // multiple of 64 and h a multiple of 4: a workgroup's output tile is 64 (w)
 // x 4 (h) voxels of one plane, one row per wave.  The tile's input
 // neighbourhood (66 x 6 x 3 voxels, zeros outside the grid) is staged in LDS
@@ -238,7 +238,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
                                                        uint16_t* __restrict__ y, int yld,
                                                        int yoff, float* __restrict__ yf,
                                                        int relu) {
-  static_assert(CIN == 8 || CIN == 16 || CIN == 32, "tiled conv: 8, 16 or 32 input channels");
+  static_assert(CIN == 8 || CIN == 16 || CIN == 32 || CIN == 64,
+                "tiled conv: 8, 16, 32 or 64 input channels (64: 152 KB of LDS)");
   __shared__ __align__(16) uint16_t tile[kSlots * CIN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tw = s.w / kTW, th = s.h / kTH;
@@ -725,27 +726,33 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
   const uint16_t* xp = (const uint16_t*)x.p;
   const uint16_t* wp = (const uint16_t*)w;
   uint16_t* yp = (uint16_t*)y.p;
-  // LDS-tiled form for the large grids (w a multiple of 64, h of 4), 8, 16
-  // or 32 input channels and 16 or 32 output channels
-  if (taps == 27 && s.w % kTW == 0 && s.h % kTH == 0 && (x.c == 8 || x.c == 16 || x.c == 32) &&
-      (y.c == 16 || y.c == 32)) {
+  // LDS-tiled form for the large grids (w a multiple of 64, h of 4), 8 to 64
+  // input channels and 16 to 64 output channels
+  if (taps == 27 && s.w % kTW == 0 && s.h % kTH == 0 &&
+      (x.c == 8 || x.c == 16 || x.c == 32 || x.c == 64) &&
+      (y.c == 16 || y.c == 32 || y.c == 64)) {
     const dim3 tg((unsigned)(nv / (kTW * kTH)));
     auto go = [&](auto cinc, auto nbc) {
       constexpr int CIN = decltype(cinc)::value, NB = decltype(nbc)::value;
       hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB>), tg, dim3(256), 0, st, s, xp, x.ld, x.off, wp,
                          bias, yp, y.ld, y.off, out_f32, relu);
     };
-    using I8 = std::integral_constant<int, 8>;
-    using I16 = std::integral_constant<int, 16>;
-    using I32 = std::integral_constant<int, 32>;
-    using N1 = std::integral_constant<int, 1>;
-    using N2 = std::integral_constant<int, 2>;
+    auto by_out = [&](auto cinc) {
+      if (y.c == 16)
+        go(cinc, std::integral_constant<int, 1>{});
+      else if (y.c == 32)
+        go(cinc, std::integral_constant<int, 2>{});
+      else
+        go(cinc, std::integral_constant<int, 4>{});
+    };
     if (x.c == 8)
-      (y.c == 16) ? go(I8{}, N1{}) : go(I8{}, N2{});
+      by_out(std::integral_constant<int, 8>{});
     else if (x.c == 16)
-      (y.c == 16) ? go(I16{}, N1{}) : go(I16{}, N2{});
+      by_out(std::integral_constant<int, 16>{});
+    else if (x.c == 32)
+      by_out(std::integral_constant<int, 32>{});
     else
-      (y.c == 16) ? go(I32{}, N1{}) : go(I32{}, N2{});
+      by_out(std::integral_constant<int, 64>{});
     UHIP(hipGetLastError());
     return UNET_OK;
   }
