@@ -221,16 +221,15 @@ __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* 
 }
 
 // The 3x3x3 convolution of CIN (8 to 64) input channels on grids with w a
-// multiple of 64 and h a multiple of 4: a workgroup's output tile is 64 (w)
-// x 4 (h) voxels of one plane, one row per wave.  The tile's input
-// neighbourhood (66 x 6 x 3 voxels, zeros outside the grid) is staged in LDS
-// once, and every tap's A operand is then read from LDS instead of being
-// gathered from global memory 27 times.  The K steps, the operands and the
-// MFMA order are those of k_conv_fwd, so the output is bitwise the same.
-constexpr int kTW = 64, kTH = 4;
-constexpr int kSW = kTW + 2, kSH = kTH + 2, kSlots = 3 * kSH * kSW;
-
-template <int CIN, int NB>
+// multiple of 64 and h of 4 (TW = 64: output tiles of 64 (w) x 4 (h) voxels
+// of one plane, one row per wave), or w = 32 and h a multiple of 8 (TW = 32:
+// 32 x 8 tiles, two rows per wave, contiguous as the rows are the whole grid
+// width).  The tile's input neighbourhood ((TW + 2) x (TH + 2) x 3 voxels,
+// zeros outside the grid) is staged in LDS once, and every tap's A operand is
+// then read from LDS instead of being gathered from global memory 27 times.
+// The K steps, the operands and the MFMA order are those of k_conv_fwd, so
+// the output is bitwise the same.
+template <int CIN, int NB, int TW = 64>
 __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
                                                        const uint16_t* __restrict__ x, int xld,
                                                        int xoff, const uint16_t* __restrict__ w,
@@ -240,6 +239,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
                                                        int relu) {
   static_assert(CIN == 8 || CIN == 16 || CIN == 32 || CIN == 64,
                 "tiled conv: 8, 16, 32 or 64 input channels (64: 152 KB of LDS)");
+  static_assert(TW == 64 || TW == 32, "tiled conv: tiles 64 or 32 wide");
+  constexpr int kTW = TW, kTH = 256 / TW, kRW = 64 / TW;  // kRW: rows per wave
+  constexpr int kSW = kTW + 2, kSH = kTH + 2, kSlots = 3 * kSH * kSW;
   __shared__ __align__(16) uint16_t tile[kSlots * CIN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tw = s.w / kTW, th = s.h / kTH;
@@ -289,7 +291,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
     bf16x8 a[4], bb[NB];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      const int slot = (dd * kSH + wave + dh) * kSW + mb * 16 + (lane & 15) + dw;
+      // the wave's voxel mb * 16 + (lane & 15): row l / TW of its rows
+      const int l = mb * 16 + (lane & 15), row = l / kTW, wl = l % kTW;
+      const int slot = (dd * kSH + kRW * wave + row + dh) * kSW + wl + dw;
       const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + slot * CIN + ci);
       a[mb] = kin ? v : zero8();
     }
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
       for (int nb = 0; nb < NB; ++nb)
         acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
   }
-  const long long vbase = (((long long)n0 * s.d + d0) * s.h + h0 + wave) * s.w + w0;
+  const long long vbase = (((long long)n0 * s.d + d0) * s.h + h0 + kRW * wave) * s.w + w0;
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -726,16 +730,20 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
   const uint16_t* xp = (const uint16_t*)x.p;
   const uint16_t* wp = (const uint16_t*)w;
   uint16_t* yp = (uint16_t*)y.p;
-  // LDS-tiled form for the large grids (w a multiple of 64, h of 4), 8 to 64
-  // input channels and 16 to 64 output channels
-  if (taps == 27 && s.w % kTW == 0 && s.h % kTH == 0 &&
-      (x.c == 8 || x.c == 16 || x.c == 32 || x.c == 64) &&
+  // LDS-tiled form for grids with w a multiple of 64 and h of 4, or w = 32
+  // and h a multiple of 8; 8 to 64 input channels and 16 to 64 output channels
+  const bool t64 = s.w % 64 == 0 && s.h % 4 == 0, t32 = s.w == 32 && s.h % 8 == 0;
+  if (taps == 27 && (t64 || t32) && (x.c == 8 || x.c == 16 || x.c == 32 || x.c == 64) &&
       (y.c == 16 || y.c == 32 || y.c == 64)) {
-    const dim3 tg((unsigned)(nv / (kTW * kTH)));
+    const dim3 tg((unsigned)(nv / 256));
     auto go = [&](auto cinc, auto nbc) {
       constexpr int CIN = decltype(cinc)::value, NB = decltype(nbc)::value;
-      hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB>), tg, dim3(256), 0, st, s, xp, x.ld, x.off, wp,
-                         bias, yp, y.ld, y.off, out_f32, relu);
+      if (t64)
+        hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB, 64>), tg, dim3(256), 0, st, s, xp, x.ld,
+                           x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
+      else
+        hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB, 32>), tg, dim3(256), 0, st, s, xp, x.ld,
+                           x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
     };
     auto by_out = [&](auto cinc) {
       if (y.c == 16)

@@ -75,7 +75,9 @@ CONV_CASES = [(2, 8, 16, (5, 6, 7)), (1, 16, 32, (4, 4, 9)), (2, 32, 64, (3, 5, 
               # LDS-tiled kernel (walls of the tile's neighbourhood on every side)
               (1, 16, 16, (3, 8, 64)), (2, 32, 32, (2, 4, 64)), (1, 16, 32, (2, 4, 128)),
               (1, 32, 16, (3, 4, 64)), (2, 8, 16, (2, 4, 64)), (1, 8, 32, (3, 8, 64)),
-              (1, 64, 64, (2, 4, 64)), (1, 32, 64, (3, 4, 64)), (1, 64, 16, (2, 8, 64))]
+              (1, 64, 64, (2, 4, 64)), (1, 32, 64, (3, 4, 64)), (1, 64, 16, (2, 8, 64)),
+              # w = 32, h a multiple of 8: 32 x 8 tiles
+              (2, 32, 64, (2, 8, 32)), (1, 64, 64, (3, 16, 32)), (1, 16, 32, (2, 8, 32))]
 
 
 @pytest.mark.parametrize("n,cin,cout,dhw", CONV_CASES)
