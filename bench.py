@@ -230,7 +230,7 @@ def coarsening_sweep(m=64, aspects=(1, 2, 4, 8), rtol=1e-8, max_cycles=3000):
 def extra_configs():
     """The other workloads, each on one GPU: the 32^3 periodic FP64 solve to
     1e-10, anisotropic vs isotropic coarsening on the 512 x 192 x 192 sphere
-    channel, and 64 uneven problems refined to 1e-10 in one graph launch."""
+    channel, and 64 uneven problems refined to 1e-10 (one graph replay per refinement step)."""
     import torch
     from paper_2607_07687_amd import gmg as G
     from paper_2607_07687_amd import problems as P
@@ -275,7 +275,7 @@ def extra_configs():
     out["channel512x192x192_fp32"] = ch
     log(f"channel: {ch}")
     del Ld, sd
-    # 64 uneven problems, FP64 refinement to 1e-10, one graph launch
+    # 64 uneven problems, FP64 refinement to 1e-10, one graph replay per step
     probs = P.batch_problems(64, seed=3)
     Ls = [torch.from_numpy(L).cuda() for L, _, _ in probs]
     ss = [torch.from_numpy(s).cuda() for _, s, _ in probs]
@@ -297,7 +297,7 @@ def extra_configs():
                               "all_ok": all(i["status"] == "GMG_OK" for i in infos),
                               "max_outer": max(i["outer"] for i in infos),
                               "worst_final_rel": max(i["history"][-1] for i in infos),
-                              "graph_launches": 1}
+                              "graph_launches": 1 + max(i["outer"] for i in infos)}
     b.close()
     log(f"batch: {out['batch64_ir_fp64']}")
     return out

@@ -308,12 +308,15 @@ typedef struct gmg_batch gmg_batch;
 gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32_t nprob,
                            void* stream, gmg_batch** out);
 
-/* Iterative refinement (as gmg_solve_ir) of every problem of the batch, all
- * recorded into ONE HIP graph and launched once (the graph is kept and
- * replayed while x, sigma and the tolerances stay the same).  x, sigma: host
- * arrays of nprob device FP64 pointers.  Problems that converge become no-ops
- * inside the graph.  infos: host array of nprob results, or NULL.  Returns
- * GMG_ENOCONV if any problem missed rtol.  Synchronises the stream. */
+/* Iterative refinement (as gmg_solve_ir) of every problem of the batch.  With
+ * graphs on, the set-up and ONE refinement step of every problem (max_inner
+ * cycles, the FP64 update, the new residual and its check) are recorded as two
+ * HIP graphs (kept and replayed while x, sigma and the tolerances stay the
+ * same); the step graph is replayed until a device flag, read back after each
+ * replay, reports every problem finished, at most max_outer times.  Problems
+ * that converge become no-ops inside the graph.  x, sigma: host arrays of
+ * nprob device FP64 pointers.  infos: host array of nprob results, or NULL.
+ * Returns GMG_ENOCONV if any problem missed rtol.  Synchronises the stream. */
 gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* const* sigma,
                               double rtol, int32_t max_outer, int32_t max_inner,
                               double inner_rtol, gmg_ir_info* infos);

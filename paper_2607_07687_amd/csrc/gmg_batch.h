@@ -7,8 +7,10 @@
 // that has a level l, tile by tile.  The V-cycle runs depth by depth in
 // lockstep; a problem whose coarsest level is l smooths there during both the
 // descent and the ascent (nu_pre + nu_post = nu_coarse sweeps).  Per-problem
-// device flags turn converged problems into no-ops, so the whole refinement
-// loop (max_outer steps of max_inner cycles) is one recorded graph.
+// device flags turn converged problems into no-ops, so one refinement step of
+// every problem (max_inner cycles, the new FP64 residual and its check) is one
+// recorded graph.  The host replays it until a device flag reports every
+// problem finished, or max_outer times.
 //
 // Included once, at the end of gmg_lib.hip.
 #pragma once
@@ -326,6 +328,21 @@ __global__ __launch_bounds__(BT) void k_b_norm_count(const BOuter<TL>* __restric
   }
 }
 
+// *all = 1 when every problem of the batch has finished (converged or out of
+// refinement steps), else 0.  One block.
+template <typename TL>
+__global__ __launch_bounds__(256) void k_b_all_done(const BOuter<TL>* __restrict__ ov, int n,
+                                                    int* __restrict__ all) {
+  __shared__ int open;
+  if (threadIdx.x == 0) open = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) mine |= ov[p].ir->done ? 0 : 1;
+  if (mine) atomicOr(&open, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *all = open ? 0 : 1;
+}
+
 }  // namespace gmg
 
 // ---------------------------------------------------------------------------
@@ -349,8 +366,11 @@ struct gmg_batch {
   std::vector<int> sweep_off, sweep_cnt, rest_off, rest_cnt;
   std::vector<int> pair_off, pair_cnt, pair_ty;  // pair_cnt 0: separate sweeps
   int res_cnt;
-  // captured whole-solve graph and what it was recorded for
-  CapturedSeq graph;
+  // captured graphs (graph: setup and first check; step: one refinement step
+  // of every problem) and what they were recorded for
+  CapturedSeq graph, step;
+  int* all_done;    // device flag written by k_b_all_done
+  int* hall_done;   // pinned host copy
   std::vector<const void*> key;
   int g_outer, g_inner;
   double g_rtol, g_inner_rtol;
@@ -545,22 +565,28 @@ void batch_pass(const gmg_batch* b, hipStream_t s, const gmg::BLevel<TL>* lv, in
     go(std::integral_constant<int, 8>{});
 }
 
+// With `head`: the right-hand-side norms and active counts, the refinement
+// state, the first FP64 residual and its check.  Then `steps` refinement steps
+// (scale and round the residual, max_inner cycles, x += beta e, the new
+// residual and its check).  With `all`, k_b_all_done writes there at the end.
 template <typename TL>
-gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, double rtol, int max_outer,
-                               int max_inner, double inner_rtol) {
+gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, bool head, double rtol,
+                               int max_outer, int steps, int max_inner, double inner_rtol,
+                               int* all) {
   using namespace gmg;
   constexpr int TY = SweepTY<float>::v;
   const gmg_params& p = b->p0;
   const BLevel<TL>* lv = (const BLevel<TL>*)b->lv;
   const BOuter<TL>* ov = (const BOuter<TL>*)b->ov;
   const dim3 rblk(BX, BY, 1);
-  hipLaunchKernelGGL(k_b_norm_count<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
-  hipLaunchKernelGGL(k_b_ir_init<TL>, dim3(b->n), dim3(256), 0, s, ov, rtol, max_outer);
-  const OmegaRule rule = b->h[0]->rule;
-  for (int m = 0; m <= max_outer; ++m) {
+  if (head) {
+    hipLaunchKernelGGL(k_b_norm_count<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
+    hipLaunchKernelGGL(k_b_ir_init<TL>, dim3(b->n), dim3(256), 0, s, ov, rtol, max_outer);
     hipLaunchKernelGGL(k_b_resid64<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
     hipLaunchKernelGGL(k_b_ir_check<TL>, dim3(b->n), dim3(256), 0, s, ov);
-    if (m == max_outer) break;  // the last check only records the final residual
+  }
+  const OmegaRule rule = b->h[0]->rule;
+  for (int m = 0; m < steps; ++m) {
     hipLaunchKernelGGL(k_b_scale_cast<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
     hipLaunchKernelGGL(k_b_solve_init<TL>, dim3(b->n), dim3(256), 0, s, ov, inner_rtol, max_inner,
                        p.omega0);
@@ -614,7 +640,10 @@ gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, double rtol, int max
       hipLaunchKernelGGL(k_b_cycle_finish<TL>, dim3(b->n), dim3(256), 0, s, ov, rule, role[0]);
     }
     hipLaunchKernelGGL(k_b_ir_update<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
+    hipLaunchKernelGGL(k_b_resid64<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
+    hipLaunchKernelGGL(k_b_ir_check<TL>, dim3(b->n), dim3(256), 0, s, ov);
   }
+  if (all) hipLaunchKernelGGL(k_b_all_done<TL>, dim3(1), dim3(256), 0, s, ov, b->n, all);
   HIP_TRY(hipGetLastError());
   return GMG_OK;
 }
@@ -631,6 +660,9 @@ void free_batch(gmg_batch* b) {
   (void)hipFree(b->rest_tiles);
   (void)hipFree(b->res_tiles);
   if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+  if (b->step.exec) (void)hipGraphExecDestroy(b->step.exec);
+  (void)hipFree(b->all_done);
+  (void)hipHostFree(b->hall_done);
   delete b;
 }
 
@@ -764,6 +796,10 @@ gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps) {
     HIP_TRY(hipGraphExecDestroy(b->graph.exec));
     b->graph.exec = nullptr;
   }
+  if (b->step.exec) {
+    HIP_TRY(hipGraphExecDestroy(b->step.exec));
+    b->step.exec = nullptr;
+  }
   b->key.clear();
   return (b->storage == GMG_BF16) ? batch_build_tables<uint16_t>(b) : batch_build_tables<float>(b);
 }
@@ -797,32 +833,55 @@ gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* cons
       HIP_TRY(hipGraphExecDestroy(b->graph.exec));
       b->graph.exec = nullptr;
     }
+    if (b->step.exec) {
+      HIP_TRY(hipGraphExecDestroy(b->step.exec));
+      b->step.exec = nullptr;
+    }
   }
+  const bool bf = b->storage == GMG_BF16;
   if (b->p0.graphs) {
-    if (!b->graph.exec) {
-      // record the whole refinement loop of every problem into one graph
+    if (!b->all_done) {
+      HIP_TRY(hipMalloc((void**)&b->all_done, sizeof(int)));
+      HIP_TRY(hipHostMalloc((void**)&b->hall_done, sizeof(int), hipHostMallocDefault));
+    }
+    if (!b->graph.exec || !b->step.exec) {
+      // record the set-up and one refinement step of every problem as graphs
       gmg_handle* h0 = b->h[0];
       hipGraphExec_t ex = nullptr;
-      GMG_TRY(captured(h0, b->graph, nullptr, nullptr,
-                       [&]() {
-                         return b->storage == GMG_BF16
-                                    ? batch_enqueue_solve<uint16_t>(b, h0->s, rtol, max_outer,
-                                                                    max_inner, inner_rtol)
-                                    : batch_enqueue_solve<float>(b, h0->s, rtol, max_outer,
-                                                                 max_inner, inner_rtol);
-                       },
-                       &ex));
+      auto rec = [&](CapturedSeq& cs, bool head, int steps) {
+        return captured(h0, cs, nullptr, nullptr,
+                        [&]() {
+                          return bf ? batch_enqueue_solve<uint16_t>(b, h0->s, head, rtol,
+                                                                    max_outer, steps, max_inner,
+                                                                    inner_rtol, b->all_done)
+                                    : batch_enqueue_solve<float>(b, h0->s, head, rtol, max_outer,
+                                                                 steps, max_inner, inner_rtol,
+                                                                 b->all_done);
+                        },
+                        &ex);
+      };
+      GMG_TRY(rec(b->graph, true, 0));
+      GMG_TRY(rec(b->step, false, 1));
       b->key = key;
       b->g_outer = max_outer;
       b->g_inner = max_inner;
       b->g_rtol = rtol;
       b->g_inner_rtol = inner_rtol;
     }
+    // replay the step until every problem has finished; each step graph ends
+    // with the flag, and max_outer replays finish every problem regardless
     HIP_TRY(hipGraphLaunch(b->graph.exec, b->s));
+    for (int m = 0;; ++m) {
+      HIP_TRY(hipMemcpyAsync(b->hall_done, b->all_done, sizeof(int), hipMemcpyDeviceToHost, b->s));
+      HIP_TRY(hipStreamSynchronize(b->s));
+      if (*b->hall_done || m >= max_outer) break;
+      HIP_TRY(hipGraphLaunch(b->step.exec, b->s));
+    }
   } else {
-    GMG_TRY((b->storage == GMG_BF16
-                 ? batch_enqueue_solve<uint16_t>(b, b->s, rtol, max_outer, max_inner, inner_rtol)
-                 : batch_enqueue_solve<float>(b, b->s, rtol, max_outer, max_inner, inner_rtol)));
+    GMG_TRY((bf ? batch_enqueue_solve<uint16_t>(b, b->s, true, rtol, max_outer, max_outer,
+                                                max_inner, inner_rtol, nullptr)
+                : batch_enqueue_solve<float>(b, b->s, true, rtol, max_outer, max_outer, max_inner,
+                                             inner_rtol, nullptr)));
   }
   HIP_TRY(hipStreamSynchronize(b->s));
   bool all_ok = true;

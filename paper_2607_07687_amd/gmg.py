@@ -402,8 +402,9 @@ def gmg_batch_setup(params_list, L_list, stream=None):
 
 def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inner_rtol=1e-4,
                        raise_noconv=False):
-    """Refinement of every problem in one graph launch; x tensors updated in
-    place.  Returns the list of per-problem info dicts."""
+    """Refinement of every problem together (with graphs: one replay per
+    refinement step, until all have finished); x tensors updated in place.
+    Returns the list of per-problem info dicts."""
     if len(xs) != b.n or len(sigmas) != b.n:
         raise ValueError("need one x and one sigma per problem")
     for t in list(xs) + list(sigmas):

@@ -1,5 +1,5 @@
-"""GPU tests of the batched refinement solve (many uneven problems in one
-graph launch): every problem's result is bitwise identical to a separate
+"""GPU tests of the batched refinement solve (many uneven problems, one graph
+replay per refinement step): every problem's result is bitwise identical to a separate
 gmg_solve_ir of the same problem (same kernels, same reduction order), and
 agrees with the oracle's refinement driver; replays of the kept graph give
 the same results."""
@@ -136,3 +136,41 @@ def test_batch_autotune_keeps_results_bitwise():
     assert [i["history"] for i in i0] == [i["history"] for i in i1]
     assert all(torch.equal(a, c) for a, c in zip(xs, ys))
     b.close()
+
+
+@pytest.mark.parametrize("max_outer", [0, 2, 30])
+def test_batch_step_replays_match_eager_launches(max_outer):
+    # the step graph is replayed until every problem has finished or max_outer
+    # times: the results, step counts and statuses equal those of launching
+    # every kernel eagerly (graphs off), also when max_outer cuts the solve
+    require_gpu()
+    specs = P.batch_specs(count=4, seed=7)
+    probs = [P.sphere_box(sp["n"], sp["centre"], sp["radius"], "uniform", sp["seed"])
+             for sp in specs]
+    Ls = [dev(L, "f64") for L, _, _ in probs]
+    ss = [dev(s, "f64") for _, s, _ in probs]
+    out = []
+    for graphs in (1, 0):
+        params = []
+        for L, _, per in probs:
+            prm = _params(L, per, "f32")
+            prm.graphs = graphs
+            params.append(prm)
+        b = G.gmg_batch_setup(params, Ls)
+        xs = [torch.zeros_like(s) for s in ss]
+        say(f"  max_outer {max_outer} graphs {graphs}")
+        infos = G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=max_outer, max_inner=8)
+        out.append((infos, xs))
+        b.close()
+    (ig, xg), (ie, xe) = out
+    for a, c in zip(ig, ie):
+        assert a["status"] == c["status"] and a["outer"] == c["outer"]
+        assert a["history"] == c["history"]
+        assert a["outer"] <= max_outer
+    assert all(torch.equal(a, c) for a, c in zip(xg, xe))
+    for i in ig:
+        assert i["status"] == "GMG_OK" or i["outer"] == max_outer
+    if max_outer == 0:
+        assert all(i["status"] != "GMG_OK" for i in ig)
+    if max_outer == 30:
+        assert all(i["status"] == "GMG_OK" for i in ig)
