@@ -492,6 +492,12 @@ gmg_status batch_build_tables(gmg_batch* b) {
             for (int x0 = 0; x0 < g.nx; x0 += S2_TX)
               pt[l].push_back(BTile{di, x0, y0, kz, std::min(g.nz, kz + kc), 0});
       }
+      // longest tiles first: problems with different nz get z-chunks of
+      // different length, and the short ones then fill the last round of the
+      // CUs (tiles are independent: a pass reads one role and writes another)
+      std::stable_sort(pt[l].begin(), pt[l].end(), [](const BTile& u, const BTile& v) {
+        return u.k1 - u.k0 > v.k1 - v.k0;
+      });
       b->pair_ty[l] = ty;
     }
   }
