@@ -846,10 +846,9 @@ gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* cons
   }
   const bool bf = b->storage == GMG_BF16;
   if (b->p0.graphs) {
-    if (!b->all_done) {
-      HIP_TRY(hipMalloc((void**)&b->all_done, sizeof(int)));
+    if (!b->all_done) HIP_TRY(hipMalloc((void**)&b->all_done, sizeof(int)));
+    if (!b->hall_done)
       HIP_TRY(hipHostMalloc((void**)&b->hall_done, sizeof(int), hipHostMallocDefault));
-    }
     if (!b->graph.exec || !b->step.exec) {
       // record the set-up and one refinement step of every problem as graphs
       gmg_handle* h0 = b->h[0];
