@@ -51,7 +51,9 @@ extern "C" {
 
 typedef enum gmg_status {
   GMG_OK = 0,
-  GMG_EINVAL = 1,   /* null pointer, bad parameter, dtype mismatch */
+  GMG_EINVAL = 1,   /* null pointer, bad parameter, dtype mismatch, or a
+                       non-finite input (NaN/Inf face, sigma or initial
+                       guess, detected on the device; see each call) */
   GMG_ESHAPE = 2,   /* n_d < 1, or an odd size (or 1) in a periodic direction */
   GMG_ENOMEM = 3,   /* device or pinned-host allocation failed */
   GMG_EHIP = 4,     /* a HIP runtime error (message in gmg_last_error) */
@@ -132,7 +134,7 @@ typedef struct gmg_params {
  * cycle's own result, accepted or not), omegas[k] the factor cycle k used,
  * accepted[k] 1 if it was kept. */
 typedef struct gmg_solve_info {
-  int32_t status;        /* GMG_OK or GMG_ENOCONV                              */
+  int32_t status;        /* GMG_OK, GMG_ENOCONV or GMG_EINVAL (non-finite)     */
   int32_t cycles;        /* V-cycles run                                       */
   int32_t accepted_cycles;
   int32_t launches;      /* host launch rounds (diagnostic)                    */
@@ -160,7 +162,10 @@ gmg_status gmg_default_params(gmg_params* p);
  * `stream` is a hipStream_t (may be NULL).  On success *out owns all device
  * workspace (levels, work buffers, reduction partials, solver state) until
  * gmg_destroy.  Errors: GMG_EINVAL (NULL p/L/out, bad dtype combination or
- * parameter), GMG_ESHAPE, GMG_ENOMEM, GMG_EHIP.  Synchronises the stream. */
+ * parameter, or a face coefficient that is NaN or Inf, found on the device
+ * while copying; the low faces at index 0 of wall directions are not
+ * checked since they are treated as 0), GMG_ESHAPE, GMG_ENOMEM, GMG_EHIP.
+ * Synchronises the stream. */
 gmg_status gmg_setup(const gmg_params* p, const void* L, void* stream,
                      gmg_handle** out);
 
@@ -233,14 +238,18 @@ gmg_status gmg_vcycle(gmg_handle* h, void* x, const void* sigma,
  * taken on the device; the host only polls a flag between launch rounds.
  * If ||sigma|| = 0, x is returned unchanged with status GMG_OK.
  * Returns GMG_OK or GMG_ENOCONV (x then holds the last accepted iterate);
- * info (host, may be NULL) is filled in both cases.  Synchronises. */
+ * GMG_EINVAL if ||sigma|| or ||sigma - A x0|| is not finite (NaN or Inf in
+ * sigma or x0: no cycle runs and x is unchanged), or if a cycle's residual
+ * norm is not finite (an overflow: the solve stops there and x holds the
+ * last accepted iterate).  info (host, may be NULL) is filled in every case.
+ * Synchronises. */
 gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol,
                      int32_t max_cycles, gmg_solve_info* info);
 
 /* Filled by gmg_pcg.  history[k] is ||r||/||sigma|| of the recursive residual
  * after iteration k (the first GMG_MAX_HISTORY iterations). */
 typedef struct gmg_pcg_info {
-  int32_t status;        /* GMG_OK or GMG_ENOCONV                              */
+  int32_t status;        /* GMG_OK, GMG_ENOCONV or GMG_EINVAL (non-finite)     */
   int32_t iterations;
   double snorm;          /* ||sigma|| over active cells                        */
   double rnorm0;         /* ||sigma - A x0||                                   */
@@ -259,14 +268,15 @@ typedef struct gmg_pcg_info {
  * captured graph of four kernels replayed in rounds; the host reads back a
  * small header between rounds.  Allocates the level-0 work vectors (six
  * arrays) on first use.  info (host) may be NULL.  Returns GMG_ENOCONV if the
- * tolerance was not reached (x holds the last iterate). */
+ * tolerance was not reached (x holds the last iterate), GMG_EINVAL if a
+ * residual norm is not finite (NaN or Inf in sigma or x0). */
 gmg_status gmg_pcg(gmg_handle* h, void* x, const void* sigma, double rtol, int32_t max_iter,
                    gmg_pcg_info* info);
 
 /* Filled by gmg_solve_ir.  history[m] is ||sigma - A x||/||sigma|| (FP64,
  * exact faces) before outer step m, and after the last one. */
 typedef struct gmg_ir_info {
-  int32_t status;        /* GMG_OK or GMG_ENOCONV                              */
+  int32_t status;        /* GMG_OK, GMG_ENOCONV or GMG_EINVAL (non-finite)     */
   int32_t outer;         /* refinement steps applied                           */
   int32_t inner_total;   /* inner V-cycles over all steps                      */
   int32_t pad;
@@ -288,7 +298,9 @@ typedef struct gmg_ir_info {
  *   x += beta * e (FP64).
  * x (in: initial guess, out: solution) and sigma are device FP64 arrays of the
  * level-0 shape.  All decisions are taken on the device; the host polls one
- * flag per outer step.  Returns GMG_OK or GMG_ENOCONV; info may be NULL.
+ * flag per outer step.  Returns GMG_OK or GMG_ENOCONV; GMG_EINVAL if ||sigma||
+ * or an outer residual norm is not finite (NaN or Inf in sigma or x0; the
+ * refinement stops before applying any further step).  info may be NULL.
  * Synchronises the stream. */
 gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rtol,
                         int32_t max_outer, int32_t max_inner, double inner_rtol,
@@ -312,19 +324,26 @@ gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32
  * graphs on, the set-up and ONE refinement step of every problem (max_inner
  * cycles, the FP64 update, the new residual and its check) are recorded as two
  * HIP graphs (kept and replayed while x, sigma and the tolerances stay the
- * same); the step graph is replayed until a device flag, read back after each
- * replay, reports every problem finished, at most max_outer times.  Problems
- * that converge become no-ops inside the graph.  x, sigma: host arrays of
- * nprob device FP64 pointers.  infos: host array of nprob results, or NULL.
- * Returns GMG_ENOCONV if any problem missed rtol.  Synchronises the stream. */
+ * same).  The host launches the set-up graph, then replays the step graph
+ * until a device flag, read back into pinned memory after each replay (one
+ * stream synchronisation per replay), reports every problem finished, at
+ * most max_outer times: one graph launch per refinement step, not one launch
+ * for the whole solve.  Problems that converge become no-ops inside the
+ * graph.  x, sigma: host arrays of nprob device FP64 pointers.  infos: host
+ * array of nprob results, or NULL.  Returns GMG_ENOCONV if any problem missed
+ * rtol, GMG_EINVAL if a norm of some problem was not finite (that problem
+ * stops; the others finish).  Synchronises the stream. */
 gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* const* sigma,
                               double rtol, int32_t max_outer, int32_t max_inner,
                               double inner_rtol, gmg_ir_info* infos);
 
-/* Tune the z-chunk of the batched fused sweep once per distinct level shape
- * of the batch (timed with HIP events on the problems' own inner buffers),
- * apply it to every problem and rebuild the descriptor tables; the recorded
- * graph is dropped.  Results do not depend on the choice.  Synchronises. */
+/* Tune the z-chunk of the batched fused sweep (tile rows fixed at 8) once per
+ * distinct level shape of the batch (timed with HIP events on the problems'
+ * own inner buffers), apply it to every problem and rebuild the descriptor
+ * tables; the recorded graph is dropped.  The tiles of the batched two-sweep
+ * passes are not tuned: they follow a fixed rule (64 x 16 at depth 0, 64 x 8
+ * below, z-chunks sized to fill about two rounds of the CUs).  Results do
+ * not depend on the choice.  Synchronises. */
 gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps);
 
 /* Free the batch and all its problems.  NULL is accepted. */

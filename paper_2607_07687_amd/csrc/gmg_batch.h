@@ -1,5 +1,5 @@
 // Batched mixed-precision solve of many independent Poisson problems of
-// uneven sizes in ONE HIP-graph launch.
+// uneven sizes: one HIP-graph launch per refinement step of all problems.
 //
 // Every problem keeps its own handle (hierarchy, buffers, device states).  The
 // batched kernels below take descriptor tables instead of a single geometry:
@@ -154,6 +154,7 @@ __global__ __launch_bounds__(256) void k_b_cycle_finish(const BOuter<TL>* __rest
     st->omegas[c] = st->omega;
   }
   st->last = rn;
+  if (stop_non_finite(st, rn, c)) return;
   const int next = (st->cur + final_role) % 3;
   if (rn > st->rho) {
     st->omega = fmax(rule.omega_min, rule.theta_dec * st->omega);
@@ -200,7 +201,10 @@ __global__ __launch_bounds__(256) void k_b_ir_check(const BOuter<TL>* __restrict
   const double rn = sqrt(rr);
   ir->rnorm = rn;
   if (ir->outer < GMG_MAX_HISTORY) ir->hist[ir->outer] = (ir->snorm > 0.0) ? rn / ir->snorm : 0.0;
-  if (ir->snorm == 0.0 || rn <= ir->rtol * ir->snorm) {
+  if (!isfinite(rn)) {  // NaN or Inf in x0 (sigma and L were checked before)
+    ir->status = kStNonFinite;
+    ir->done = 1;
+  } else if (ir->snorm == 0.0 || rn <= ir->rtol * ir->snorm) {
     ir->status = 0;
     ir->done = 1;
   } else if (ir->outer >= ir->max_outer) {
@@ -296,8 +300,8 @@ __global__ __launch_bounds__(256) void k_b_ir_init(const BOuter<TL>* __restrict_
     ir->outer = 0;
     ir->inner_total = 0;
     ir->max_outer = max_outer;
-    ir->done = 0;
-    ir->status = 5;
+    ir->done = isfinite(ir->snorm) ? 0 : 1;
+    ir->status = isfinite(ir->snorm) ? 5 : kStNonFinite;
     o.st->done = 1;
   }
 }
@@ -890,11 +894,13 @@ gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* cons
   }
   HIP_TRY(hipStreamSynchronize(b->s));
   bool all_ok = true;
+  int first_bad = -1;
   for (int p = 0; p < b->n; ++p) {
     gmg_handle* h = b->h[p];
     HIP_TRY(hipMemcpy(h->hir, h->ir, sizeof(IRState), hipMemcpyDeviceToHost));
     const IRState& r = *h->hir;
     if (r.status != 0) all_ok = false;
+    if (r.status == kStNonFinite && first_bad < 0) first_bad = p;
     if (infos) {
       gmg_ir_info* info = &infos[p];
       std::memset(info, 0, sizeof(*info));
@@ -909,6 +915,9 @@ gmg_status gmg_batch_solve_ir(gmg_batch* b, double* const* x, const double* cons
         info->inner_cycles[m] = r.inner[m];
     }
   }
+  if (first_bad >= 0)
+    return fail(GMG_EINVAL, "residual norm not finite (NaN or Inf in sigma or x0) in problem " +
+                                std::to_string(first_bad));
   if (!all_ok) return fail(GMG_ENOCONV, "some problems reached max_outer before rtol");
   return GMG_OK;
 }

@@ -28,6 +28,7 @@ struct SolveState {
   int map[4];
   int pending;     // a candidate awaits its decision
   int redo;        // the speculative first sweep must be redone
+  int bad;         // set-up: a face coefficient given to gmg_setup is not finite
   double omega_spec;  // omega of the next cycle if the candidate is accepted
   double scr[4];   // scratch for one-off reductions (gmg_residual)
   double hist[GMG_MAX_HISTORY];
@@ -51,6 +52,11 @@ struct IRState {
   double hist[GMG_MAX_HISTORY];
   int inner[GMG_MAX_HISTORY];
 };
+
+// Status of a solve (or refinement) state that met a non-finite norm: NaN or
+// Inf in sigma, in the initial guess or in the faces, or an overflow.  The
+// solve stops at once; the host reports it as GMG_EINVAL.
+constexpr int kStNonFinite = GMG_EINVAL;
 
 // Adaptive-relaxation constants, passed by value.
 struct OmegaRule {

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(BT) void k_copy_role(Geom g, Roles<T> X, int rs, in
 // face at index 0 of every wall direction.
 template <typename TI, typename TL>
 __global__ __launch_bounds__(BT) void k_copy_faces(Geom g, const TI* __restrict__ Lin,
-                                                   TL* __restrict__ Lout) {
+                                                   TL* __restrict__ Lout, int* bad) {
   const int i = blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
@@ -275,6 +275,7 @@ __global__ __launch_bounds__(BT) void k_copy_faces(Geom g, const TI* __restrict_
   for (int d = 0; d < 3; ++d) {
     double v = (double)Lin[d * g.n + idx];
     if (!per[d] && c[d] == 0) v = 0.0;
+    if (!isfinite(v)) *bad = 1;  // the set-up then fails with GMG_EINVAL
     Lout[d * g.n + idx] = to_storage<TL>(v);
   }
 }
@@ -362,6 +363,7 @@ __global__ __launch_bounds__(256) void k_solve_init(const double* pa, long long 
   if (threadIdx.x == 0) {
     st->snorm = sqrt(ss);
     st->rho = st->rho0 = st->last = sqrt(rr);
+    const bool bad = !isfinite(st->snorm) || !isfinite(st->rho);
     st->omega = omega0;
     st->rtol = rtol;
     st->cur = 0;
@@ -374,10 +376,21 @@ __global__ __launch_bounds__(256) void k_solve_init(const double* pa, long long 
     st->pending = 0;
     st->redo = 0;
     st->omega_spec = omega0;
-    const bool conv = (st->snorm == 0.0) || (st->rho <= rtol * st->snorm);
-    st->status = conv ? 0 : 5;
-    st->done = (conv || max_cycles <= 0) ? 1 : 0;
+    const bool conv = !bad && ((st->snorm == 0.0) || (st->rho <= rtol * st->snorm));
+    st->status = bad ? kStNonFinite : (conv ? 0 : 5);
+    st->done = (bad || conv || max_cycles <= 0) ? 1 : 0;
   }
+}
+
+// A cycle's residual norm that is not finite stops the solve; the accepted
+// iterate (role 0) is kept.  Returns true if it did.
+__device__ __forceinline__ bool stop_non_finite(SolveState* st, double rn, int c) {
+  if (isfinite(rn)) return false;
+  if (c < GMG_MAX_HISTORY) st->acc[c] = 0;
+  st->cycles = c + 1;
+  st->status = kStNonFinite;
+  st->done = 1;
+  return true;
 }
 
 // End of a V-cycle: new residual norm, the adaptive-relaxation decision
@@ -395,6 +408,7 @@ __global__ __launch_bounds__(256) void k_cycle_finish(const double* p, long long
     st->omegas[c] = st->omega;
   }
   st->last = rn;
+  if (stop_non_finite(st, rn, c)) return;
   // the cycle's result sits in role `final_role`; accepting it makes that
   // buffer the new role 0
   const int next = (st->cur + final_role) % 3;
@@ -445,6 +459,7 @@ __global__ __launch_bounds__(256) void k_spec_finish(const double* p, long long 
     st->omegas[c] = st->omega;
   }
   st->last = rn;
+  if (stop_non_finite(st, rn, c)) return;
   if (rn > st->rho) {  // growth
     st->omega = fmax(rule.omega_min, rule.theta_dec * st->omega);
     if (c < GMG_MAX_HISTORY) st->acc[c] = rule.rollback ? 0 : 1;
@@ -508,8 +523,8 @@ __global__ __launch_bounds__(256) void k_ir_init(const double* ps, const double*
     ir->outer = 0;
     ir->inner_total = 0;
     ir->max_outer = max_outer;
-    ir->done = 0;
-    ir->status = 5;
+    ir->done = isfinite(ir->snorm) ? 0 : 1;
+    ir->status = isfinite(ir->snorm) ? 5 : kStNonFinite;
     inner->done = 1;
   }
 }
@@ -523,7 +538,10 @@ __global__ __launch_bounds__(256) void k_ir_check(const double* p, long long n, 
   const double rn = sqrt(rr);
   ir->rnorm = rn;
   if (ir->outer < GMG_MAX_HISTORY) ir->hist[ir->outer] = (ir->snorm > 0.0) ? rn / ir->snorm : 0.0;
-  if (ir->snorm == 0.0 || rn <= ir->rtol * ir->snorm) {
+  if (!isfinite(rn)) {  // NaN or Inf in x0 (sigma and L were checked before)
+    ir->status = kStNonFinite;
+    ir->done = 1;
+  } else if (ir->snorm == 0.0 || rn <= ir->rtol * ir->snorm) {
     ir->status = 0;
     ir->done = 1;
   } else if (ir->outer >= ir->max_outer) {
@@ -1212,7 +1230,7 @@ template <typename TI, typename TL>
 static void enq_copy_faces(gmg_handle* h, const void* Lin, void* Lout) {
   const Level& lv = h->lev[0];
   hipLaunchKernelGGL((k_copy_faces<TI, TL>), cell_grid(lv.g), kBlock, 0, h->s, lv.g,
-                     (const TI*)Lin, (TL*)Lout);
+                     (const TI*)Lin, (TL*)Lout, &h->st->bad);
 }
 
 template <typename TL>
@@ -1339,7 +1357,9 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
   HIP_TRY(hipGetLastError());
   DISPATCH_CYCLE(h, { h->tail = plan_tail<T, TL>(h); });
   if (p->smoother == GMG_SMOOTH_PCG) DISPATCH_CYCLE(h, { GMG_TRY((ensure_pcg<T, TL>(h, h->nlev))); });
+  HIP_TRY(hipMemcpyAsync(&h->hst->bad, &h->st->bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
   HIP_TRY(hipStreamSynchronize(h->s));
+  if (h->hst->bad) return fail(GMG_EINVAL, "a face coefficient is not finite (NaN or Inf)");
   return GMG_OK;
 }
 
@@ -1808,6 +1828,8 @@ gmg_status gmg_pcg(gmg_handle* h, void* x, const void* sigma, double rtol, int32
     info->rnorm = s.rnorm;
     for (int k = 0; k < std::min(s.it, GMG_MAX_HISTORY); ++k) info->history[k] = s.hist[k];
   }
+  if (s.status == kStNonFinite)
+    return fail(GMG_EINVAL, "residual norm not finite (NaN or Inf in sigma or x0)");
   return s.status == GMG_OK ? GMG_OK : fail(GMG_ENOCONV, "PCG did not reach the tolerance");
 }
 
@@ -1898,6 +1920,9 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
       info->accepted[c] = s.acc[c];
     }
   }
+  if (s.status == kStNonFinite)
+    return fail(GMG_EINVAL, "residual norm not finite (NaN or Inf in sigma or x0, or an "
+                            "overflow); x holds the last accepted iterate");
   if (s.status != 0) return fail(GMG_ENOCONV, "max_cycles reached before rtol");
   return GMG_OK;
 }
@@ -1958,6 +1983,8 @@ gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rt
     for (int m = 0; m < nh; ++m) info->history[m] = r.hist[m];
     for (int m = 0; m < std::min(r.outer, GMG_MAX_HISTORY); ++m) info->inner_cycles[m] = r.inner[m];
   }
+  if (r.status == kStNonFinite)
+    return fail(GMG_EINVAL, "residual norm not finite (NaN or Inf in sigma or x0)");
   if (r.status != 0) return fail(GMG_ENOCONV, "max_outer reached before rtol");
   return GMG_OK;
 }

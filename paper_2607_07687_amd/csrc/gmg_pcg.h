@@ -103,10 +103,11 @@ __global__ __launch_bounds__(256) void k_pcg_begin(PCGState* st, const double* p
   st->rtol = rtol;
   st->it = 0;
   st->max_it = max_it;
-  const bool conv = rtol > 0.0 && st->snorm > 0.0 && st->rnorm / st->snorm <= rtol;
-  const bool zero_rhs = rtol > 0.0 && st->snorm == 0.0;
-  st->done = (conv || zero_rhs || max_it <= 0) ? 1 : 0;
-  st->status = (conv || zero_rhs) ? GMG_OK : GMG_ENOCONV;
+  const bool bad = !isfinite(st->snorm) || !isfinite(st->rnorm);
+  const bool conv = !bad && rtol > 0.0 && st->snorm > 0.0 && st->rnorm / st->snorm <= rtol;
+  const bool zero_rhs = !bad && rtol > 0.0 && st->snorm == 0.0;
+  st->done = (bad || conv || zero_rhs || max_it <= 0) ? 1 : 0;
+  st->status = bad ? kStNonFinite : ((conv || zero_rhs) ? GMG_OK : GMG_ENOCONV);
 }
 
 // p' = z + beta p, q = B p' = -A p' on active cells; partials of p'.q.
@@ -203,7 +204,10 @@ __global__ __launch_bounds__(256) void k_pcg_next(PCGState* st, const double* pa
   const double rel = (st->snorm > 0.0) ? st->rnorm / st->snorm : 0.0;
   if (it < GMG_MAX_HISTORY) st->hist[it] = rel;
   st->it = it + 1;
-  if (st->rtol > 0.0 && rel <= st->rtol) {
+  if (!isfinite(st->rnorm)) {
+    st->done = 1;
+    st->status = kStNonFinite;
+  } else if (st->rtol > 0.0 && rel <= st->rtol) {
     st->done = 1;
     st->status = GMG_OK;
   } else if (st->it >= st->max_it) {

@@ -178,6 +178,62 @@ def _ptr(t, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _torch_dtype(code):
+    """torch dtype of caller arrays in gmg_dtype `code` (BF16: 2-byte raw bits)."""
+    import torch
+    return {GMG_F32: torch.float32, GMG_F64: torch.float64}.get(code)
+
+
+def _meta(t, what, numel, dtype, optional=False):
+    """dtype (a torch dtype, or an element size in bytes for raw BF16 bits)
+    and element count of one tensor argument."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{what} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if isinstance(dtype, int):
+        if t.element_size() != dtype:
+            raise ValueError(f"{what} must have {dtype}-byte elements, got {t.dtype}")
+    elif t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+
+
+def _place(t, what, device=None):
+    """Contiguity and device of one tensor argument; returns its pointer."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous GPU tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{what} is on {t.device}, the handle on {device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _args(*specs, device=None):
+    """Check tensor arguments before any library call and return their
+    pointers.  specs: (tensor, name, numel, dtype[, optional]).  First the
+    dtype and element count of every argument, then contiguity and device.
+    The library cannot check sizes itself: a short or mistyped buffer would
+    be read and written past its end by the kernels."""
+    for sp in specs:
+        _meta(sp[0], sp[1], sp[2], sp[3], sp[4] if len(sp) > 4 else False)
+    return [_place(sp[0], sp[1], device) for sp in specs]
+
+
+def _arr(t, what, numel, dtype, device=None, optional=False):
+    """One checked tensor argument (see _args)."""
+    return _args((t, what, numel, dtype, optional), device=device)[0]
+
+
+def _cells(n):
+    return int(n[0]) * int(n[1]) * int(n[2])
+
+
 def _stream(stream, device):
     import torch
     if stream is None:
@@ -205,12 +261,30 @@ def gmg_default_params(n, periodic=(False, False, False), dtype=GMG_F32, **kw):
 
 
 class Handle:
-    """Owns a gmg_handle*; destroyed by close() or garbage collection."""
+    """Owns a gmg_handle*; destroyed by close() or garbage collection.
+    Keeps what the bindings check arrays against: the parameters, the device
+    and the cell shape (nx, ny, nz) of every level."""
 
-    def __init__(self, ptr, params, stream):
+    def __init__(self, ptr, params, stream, device=None, shapes=None):
         self._ptr = ptr
         self.params = params
         self.stream = stream
+        self.device = device
+        self.shapes = shapes if shapes is not None else [tuple(params.n)]
+
+    def cells(self, level=0):
+        if not 0 <= level < len(self.shapes):
+            raise ValueError(f"level {level} out of range (0..{len(self.shapes) - 1})")
+        return _cells(self.shapes[level])
+
+    def spec(self, t, what, level=0, cycle=True, optional=False):
+        """Check spec (see _args) of a cell array of `level` in the cycle
+        precision, or in the caller precision `dtype` if not cycle."""
+        code = self.params.cycle_dtype if cycle else self.params.dtype
+        return (t, what, self.cells(level), _torch_dtype(code), optional)
+
+    def arrs(self, *specs):
+        return _args(*specs, device=self.device)
 
     @property
     def ptr(self):
@@ -235,10 +309,13 @@ def gmg_setup(params, L, stream=None):
     params.dtype).  Returns a Handle."""
     if _dtype_code(L) != params.dtype:
         raise TypeError("L dtype does not match params.dtype")
+    Lp = _arr(L, "L", 3 * _cells(params.n), _torch_dtype(params.dtype))
     s = _stream(stream, L.device)
     out = ctypes.c_void_p()
-    _check(load().gmg_setup(ctypes.byref(params), _ptr(L, "L"), s, ctypes.byref(out)))
-    return Handle(out, params, s)
+    _check(load().gmg_setup(ctypes.byref(params), Lp, s, ctypes.byref(out)))
+    h = Handle(out, params, s, L.device)
+    h.shapes = [gmg_level_shape(h, l)[0] for l in range(gmg_num_levels(h))]
+    return h
 
 
 def gmg_num_levels(h):
@@ -255,30 +332,39 @@ def gmg_level_shape(h, level):
 
 
 def gmg_level_faces(h, level, out):
-    _check(load().gmg_level_faces(h.ptr, level, _ptr(out, "out")))
+    ls = h.params.l_storage
+    dt = 2 if ls == GMG_BF16 else _torch_dtype(ls)
+    p = _arr(out, "out", 3 * h.cells(level), dt, h.device)
+    _check(load().gmg_level_faces(h.ptr, level, p))
     return out
 
 
 def gmg_residual(h, x, sigma, r=None, norms=True):
     """Returns (rnorm, snorm) if norms else None; fills r if given."""
+    xp, sp, rp = h.arrs(h.spec(x, "x", cycle=False), h.spec(sigma, "sigma", cycle=False),
+                        h.spec(r, "r", cycle=False, optional=True))
     rn, sn = ctypes.c_double(), ctypes.c_double()
-    _check(load().gmg_residual(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), _ptr(r, "r"),
+    _check(load().gmg_residual(h.ptr, xp, sp, rp,
                                ctypes.byref(rn) if norms else None,
                                ctypes.byref(sn) if norms else None))
     return (rn.value, sn.value) if norms else None
 
 
 def gmg_smooth(h, level, x, sigma, sweeps):
-    _check(load().gmg_smooth(h.ptr, level, _ptr(x, "x"), _ptr(sigma, "sigma"), sweeps))
+    xp, sp = h.arrs(h.spec(x, "x", level), h.spec(sigma, "sigma", level))
+    _check(load().gmg_smooth(h.ptr, level, xp, sp, sweeps))
 
 
 def gmg_restrict_residual(h, level, x, sigma, sigma_c, x_c=None):
-    _check(load().gmg_restrict_residual(h.ptr, level, _ptr(x, "x"), _ptr(sigma, "sigma"),
-                                        _ptr(sigma_c, "sigma_c"), _ptr(x_c, "x_c")))
+    xp, sp, scp, xcp = h.arrs(h.spec(x, "x", level), h.spec(sigma, "sigma", level),
+                              h.spec(sigma_c, "sigma_c", level + 1),
+                              h.spec(x_c, "x_c", level + 1, optional=True))
+    _check(load().gmg_restrict_residual(h.ptr, level, xp, sp, scp, xcp))
 
 
 def gmg_prolong_correct(h, level, x_c, x):
-    _check(load().gmg_prolong_correct(h.ptr, level, _ptr(x_c, "x_c"), _ptr(x, "x")))
+    xcp, xp = h.arrs(h.spec(x_c, "x_c", level + 1), h.spec(x, "x", level))
+    _check(load().gmg_prolong_correct(h.ptr, level, xcp, xp))
 
 
 def gmg_get_omega(h):
@@ -293,8 +379,8 @@ def gmg_set_omega(h, omega):
 
 def gmg_vcycle(h, x, sigma, want_norm=False):
     rn = ctypes.c_double()
-    _check(load().gmg_vcycle(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"),
-                             ctypes.byref(rn) if want_norm else None))
+    xp, sp = h.arrs(h.spec(x, "x", cycle=False), h.spec(sigma, "sigma", cycle=False))
+    _check(load().gmg_vcycle(h.ptr, xp, sp, ctypes.byref(rn) if want_norm else None))
     return rn.value if want_norm else None
 
 
@@ -311,8 +397,8 @@ def gmg_solve(h, x, sigma, rtol, max_cycles, raise_noconv=False):
     """Adaptive solve in place on x.  Returns the info dict (status
     'GMG_ENOCONV' is returned, not raised, unless raise_noconv)."""
     info = gmg_solve_info()
-    st = load().gmg_solve(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), float(rtol),
-                          int(max_cycles), ctypes.byref(info))
+    xp, sp = h.arrs(h.spec(x, "x", cycle=False), h.spec(sigma, "sigma", cycle=False))
+    st = load().gmg_solve(h.ptr, xp, sp, float(rtol), int(max_cycles), ctypes.byref(info))
     if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
         _check(st)
     return info_dict(info)
@@ -323,8 +409,8 @@ def gmg_pcg(h, x, sigma, rtol, max_iter, raise_noconv=False):
     place on x.  Returns dict(status, iterations, snorm, rnorm0, rnorm,
     history)."""
     info = gmg_pcg_info()
-    st = load().gmg_pcg(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), float(rtol), int(max_iter),
-                        ctypes.byref(info))
+    xp, sp = h.arrs(h.spec(x, "x", cycle=False), h.spec(sigma, "sigma", cycle=False))
+    st = load().gmg_pcg(h.ptr, xp, sp, float(rtol), int(max_iter), ctypes.byref(info))
     if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
         _check(st)
     n = min(info.iterations, GMG_MAX_HISTORY)
@@ -336,10 +422,11 @@ def gmg_solve_ir(h, x, sigma, rtol=1e-10, max_outer=50, max_inner=8, inner_rtol=
                  raise_noconv=False):
     """FP64 iterative refinement around FP32 V-cycles, in place on the FP64
     tensor x.  Returns the info dict."""
+    import torch
     info = gmg_ir_info()
-    st = load().gmg_solve_ir(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), float(rtol),
-                             int(max_outer), int(max_inner), float(inner_rtol),
-                             ctypes.byref(info))
+    xp, sp = h.arrs((x, "x", h.cells(0), torch.float64), (sigma, "sigma", h.cells(0), torch.float64))
+    st = load().gmg_solve_ir(h.ptr, xp, sp, float(rtol), int(max_outer), int(max_inner),
+                             float(inner_rtol), ctypes.byref(info))
     if st != GMG_OK and not (st == GMG_ENOCONV and not raise_noconv):
         _check(st)
     n = min(info.outer + 1, GMG_MAX_HISTORY)
@@ -358,12 +445,15 @@ def _ir_dict(info):
 
 
 class Batch:
-    """Owns a gmg_batch*."""
+    """Owns a gmg_batch*; keeps the cell count of every problem and the
+    device for the argument checks."""
 
-    def __init__(self, ptr, n, stream):
+    def __init__(self, ptr, n, stream, cells=None, device=None):
         self._ptr = ptr
         self.n = n
         self.stream = stream
+        self.cells = cells
+        self.device = device
 
     @property
     def ptr(self):
@@ -387,17 +477,19 @@ def gmg_batch_setup(params_list, L_list, stream=None):
     n = len(params_list)
     if len(L_list) != n or n == 0:
         raise ValueError("need one L per parameter set")
+    dev = L_list[0].device
     for p, L in zip(params_list, L_list):
         if _dtype_code(L) != p.dtype:
             raise TypeError("L dtype does not match params.dtype")
+    ptrs = [t.value for t in _args(*[(L, f"L[{q}]", 3 * _cells(p.n), _torch_dtype(p.dtype))
+                                     for q, (p, L) in enumerate(zip(params_list, L_list))],
+                                   device=dev)]
     parr = (gmg_params * n)(*params_list)
-    larr = (ctypes.c_void_p * n)(*[L.data_ptr() for L in L_list])
-    for L in L_list:
-        _ptr(L, "L")
-    s = _stream(stream, L_list[0].device)
+    larr = (ctypes.c_void_p * n)(*ptrs)
+    s = _stream(stream, dev)
     out = ctypes.c_void_p()
     _check(load().gmg_batch_setup(parr, larr, n, s, ctypes.byref(out)))
-    return Batch(out, n, s)
+    return Batch(out, n, s, [_cells(p.n) for p in params_list], dev)
 
 
 def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inner_rtol=1e-4,
@@ -405,12 +497,14 @@ def gmg_batch_solve_ir(b, xs, sigmas, rtol=1e-10, max_outer=6, max_inner=8, inne
     """Refinement of every problem together (with graphs: one replay per
     refinement step, until all have finished); x tensors updated in place.
     Returns the list of per-problem info dicts."""
+    import torch
     if len(xs) != b.n or len(sigmas) != b.n:
         raise ValueError("need one x and one sigma per problem")
-    for t in list(xs) + list(sigmas):
-        _ptr(t, "x/sigma")
-    xarr = (ctypes.c_void_p * b.n)(*[t.data_ptr() for t in xs])
-    sarr = (ctypes.c_void_p * b.n)(*[t.data_ptr() for t in sigmas])
+    specs = ([(t, f"x[{q}]", b.cells[q], torch.float64) for q, t in enumerate(xs)] +
+             [(t, f"sigma[{q}]", b.cells[q], torch.float64) for q, t in enumerate(sigmas)])
+    ptrs = [t.value for t in _args(*specs, device=b.device)]
+    xarr = (ctypes.c_void_p * b.n)(*ptrs[:b.n])
+    sarr = (ctypes.c_void_p * b.n)(*ptrs[b.n:])
     infos = (gmg_ir_info * b.n)()
     st = load().gmg_batch_solve_ir(b.ptr, xarr, sarr, float(rtol), int(max_outer),
                                    int(max_inner), float(inner_rtol), infos)
@@ -424,8 +518,8 @@ def gmg_autotune(h, x, sigma, reps=5):
     also the two-sweep pass where allowed.  Returns per-level dicts (shape,
     ty, kchunk, us, defaults, pair_kchunk (0: separate sweeps), pair_ty, us_pair)."""
     rep = gmg_tune_report()
-    _check(load().gmg_autotune(h.ptr, _ptr(x, "x"), _ptr(sigma, "sigma"), int(reps),
-                               ctypes.byref(rep)))
+    xp, sp = h.arrs(h.spec(x, "x", cycle=False), h.spec(sigma, "sigma", cycle=False))
+    _check(load().gmg_autotune(h.ptr, xp, sp, int(reps), ctypes.byref(rep)))
     out = []
     for l in range(rep.nlevels):
         n, _ = gmg_level_shape(h, l)

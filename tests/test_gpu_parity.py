@@ -329,8 +329,8 @@ def test_abi_errors():
     h = G.gmg_setup(p, L)
     with pytest.raises(G.GMGError):
         G.gmg_set_omega(h, -1.0)
-    with pytest.raises(G.GMGError):
-        G.gmg_restrict_residual(h, 0, L[0], L[0], L[0])  # single level: no coarser
+    with pytest.raises(ValueError):  # single level: the binding finds no coarser level
+        G.gmg_restrict_residual(h, 0, L[0], L[0], L[0])
     h.close()
 
 
