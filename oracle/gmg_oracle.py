@@ -35,7 +35,11 @@ Parity status of each function against the paper:
 * the adaptive-omega constants (decrease factor, increase factor, bounds,
   rollback): the paper fixes only that omega reacts to growth or decay after
   each V-cycle, so the constants are PARITY UNPINNED against the paper; the
-  accepted-residual monotonicity they are meant to ensure is pinned.
+  accepted-residual monotonicity they are meant to ensure is pinned;
+* the coarsest-level stopping factor and sweep cap (coarse_rtol, coarse_max):
+  the paper says only that the coarsest level is where the smoother removes
+  the low wavenumbers, so their values are PARITY UNPINNED against the paper;
+  the rule itself is pinned by a brute-force reconstruction.
 """
 from __future__ import annotations
 
@@ -257,23 +261,48 @@ def build_hierarchy(L, periodic, anisotropic=True, min_coarse=4, max_levels=0,
 # V-cycle and adaptive solve (Sec. 3 and 3.1)
 # ----------------------------------------------------------------------------
 
-def vcycle(levels, x, sigma, omega, nu_pre=2, nu_post=2, nu_coarse=4, l=0):
+def coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max):
+    """Smoothing on the coarsest level, where the smoother itself has to
+    remove the lowest wavenumbers (Sec. 3.2).  coarse_rtol = 0: exactly
+    nu_coarse sweeps.  coarse_rtol > 0: sweeps until the level's residual norm
+    (active cells, FP64) is at most coarse_rtol times its value on entry, at
+    least one sweep and at most coarse_max.  No direct solve either way.
+    Returns (x, sweeps)."""
+    if coarse_rtol <= 0.0:
+        for _ in range(nu_coarse):
+            x = rb_sweep(x, sigma, L, per, omega)
+        return x, nu_coarse
+    r0 = norm2(residual(x, sigma, L, per))
+    n = 0
+    while n < coarse_max:
+        x = rb_sweep(x, sigma, L, per, omega)
+        n += 1
+        if norm2(residual(x, sigma, L, per)) <= coarse_rtol * r0:
+            break
+    return x, n
+
+
+def vcycle(levels, x, sigma, omega, nu_pre=2, nu_post=2, nu_coarse=4, l=0, coarse_rtol=0.0,
+           coarse_max=64, stats=None):
     """One V(nu_pre, nu_post) cycle from level l with the same omega
-    everywhere.  The coarsest level gets nu_coarse sweeps and no direct solve.
-    Returns the new x (a new array)."""
+    everywhere.  The coarsest level is smoothed by ``coarsest_sweeps`` (no
+    direct solve).  Returns the new x (a new array); the sweep count of the
+    coarsest level is appended to ``stats`` if given."""
     lev = levels[l]
     L, per = lev["L"], lev["periodic"]
     x = np.array(x, dtype=np.float64, copy=True)
     if lev["c"] is None:
-        for _ in range(nu_coarse):
-            x = rb_sweep(x, sigma, L, per, omega)
+        x, n = coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max)
+        if stats is not None:
+            stats.append(n)
         return x
     for _ in range(nu_pre):
         x = rb_sweep(x, sigma, L, per, omega)
     r = residual(x, sigma, L, per)
     sigma_c = restrict(r, lev["c"])
     x_c = np.zeros_like(sigma_c)
-    x_c = vcycle(levels, x_c, sigma_c, omega, nu_pre, nu_post, nu_coarse, l + 1)
+    x_c = vcycle(levels, x_c, sigma_c, omega, nu_pre, nu_post, nu_coarse, l + 1, coarse_rtol,
+                 coarse_max, stats)
     corr = prolong(x_c, lev["c"])
     x[lev["active"]] += corr[lev["active"]]
     for _ in range(nu_post):
@@ -281,8 +310,8 @@ def vcycle(levels, x, sigma, omega, nu_pre=2, nu_post=2, nu_coarse=4, l=0):
     return x
 
 
-DEFAULTS = dict(nu_pre=2, nu_post=2, nu_coarse=4, omega0=1.0, omega_min=0.1,
-                omega_max=1.0, theta_dec=0.5, theta_inc=1.2, rollback=True)
+DEFAULTS = dict(nu_pre=2, nu_post=2, nu_coarse=4, coarse_rtol=0.0, coarse_max=64, omega0=1.0,
+                omega_min=0.1, omega_max=1.0, theta_dec=0.5, theta_inc=1.2, rollback=True)
 
 
 def solve(levels, x0, sigma, rtol, max_cycles, **kw):
@@ -320,7 +349,7 @@ def solve(levels, x0, sigma, rtol, max_cycles, **kw):
         if k >= max_cycles:
             break
         xn = vcycle(levels, x, sigma, omega, p["nu_pre"], p["nu_post"],
-                    p["nu_coarse"])
+                    p["nu_coarse"], coarse_rtol=p["coarse_rtol"], coarse_max=p["coarse_max"])
         rn = norm2(residual(xn, sigma, L, per))
         omegas.append(omega)
         if rn > rho:

@@ -143,6 +143,32 @@ def predict(net, sm, x_buf, out):
     return out
 
 
+def warm_solve(h, net, sm, x, x_buf, rtol=1e-6, max_outer=30):
+    """Solve with the learned warm start and plain GMG as the fallback.
+
+    x0 = s * U(sigma / s, L) is written into x (FP64); its residual judges
+    it: if ||sigma - A x0|| > ||sigma|| (worse than the zero guess) x is
+    zeroed before the solve.  The refinement solve then runs from x; if it
+    misses rtol within max_outer steps from a prediction, x is zeroed and
+    the solve runs again from zero.  Returns (info of the solve whose x is
+    returned, fallback reason or None)."""
+    nx, ny, nz = sm.n
+    pack([sm], x_buf)
+    y = net.forward(x_buf, 1, nz, ny, nx)
+    UN.unet_scale_f64(y, sm.scale, x)
+    rn, sn = G.gmg_residual(h, x, sm.sigma64)
+    reason = None
+    if not (rn <= sn):  # also catches a non-finite prediction
+        x.zero_()
+        reason = "prediction worse than zero"
+    info = G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)
+    if info["status"] != "GMG_OK" and reason is None:
+        x.zero_()
+        reason = "warm-started solve missed the tolerance"
+        info = G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)
+    return info, reason
+
+
 def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
     """Wall time of plain GMG (x0 = 0) against U-Net inference + GMG from its
     prediction, on the same GPU; medians over reps.  Both solves are the FP64
@@ -165,9 +191,9 @@ def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
             UN.unet_scale_f64(y, sm.scale, x)
 
         G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)  # warm-up (graph capture)
-        warm()
-        G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)
+        warm_solve(h, net, sm, x, xb, rtol, max_outer)
         tp, tw, ti = [], [], []
+        reasons = set()
         for _ in range(reps):
             x.zero_()
             torch.cuda.synchronize()
@@ -181,17 +207,19 @@ def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
             ti.append(time.perf_counter() - t0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            warm()
-            iw = G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)
+            iw, why = warm_solve(h, net, sm, x, xb, rtol, max_outer)
             torch.cuda.synchronize()
             tw.append(time.perf_counter() - t0)
+            if why:
+                reasons.add(why)
         # relative residual of the prediction alone (first history entry)
-        rel0 = iw["history"][0] if iw["history"] else float("nan")
+        rel0 = iw["history"][0] if iw["history"] and not reasons else float("nan")
         res.append(dict(plain_ms=1e3 * float(np.median(tp)), warm_ms=1e3 * float(np.median(tw)),
                         infer_ms=1e3 * float(np.median(ti)),
                         plain_outer=ip["outer"], plain_inner=ip["inner_total"],
                         warm_outer=iw["outer"], warm_inner=iw["inner_total"],
-                        plain_status=ip["status"], warm_status=iw["status"], warm_rel_r0=rel0))
+                        plain_status=ip["status"], warm_status=iw["status"], warm_rel_r0=rel0,
+                        fallback=sorted(reasons)))
         h.close()
         r = res[-1]
         print(f"eval {len(res)} {sm.n[0]}^3: plain {r['plain_ms']:.2f} ms ({r['plain_inner']} "

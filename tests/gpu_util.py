@@ -43,5 +43,18 @@ def rel(a, b):
     return na / nb
 
 
+def assert_close(a, b, tol, what=""):
+    """Agreement both norm-wise and element by element:
+    ||a - b||_2 <= tol ||b||_2 and max |a - b| <= tol max |b|.  The second
+    bound keeps a few wrong cells from hiding inside a large field's norm."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    e2 = rel(a, b)
+    mb = float(np.abs(b).max()) if b.size else 0.0
+    einf = float(np.abs(a - b).max()) / mb if mb > 0 else float(np.abs(a - b).max(initial=0.0))
+    assert e2 <= tol and einf <= tol, f"{what} rel2 {e2:.3e} relinf {einf:.3e} tol {tol:.1e}"
+    return max(e2, einf)
+
+
 def say(msg):
     print(msg, flush=True)

@@ -72,3 +72,4 @@ def test_shape_errors_detected_before_any_device_work():
     assert lib.gmg_setup(ctypes.byref(p), ctypes.c_void_p(8), None, ctypes.byref(out)) == G.GMG_ESHAPE
     p = G.gmg_default_params((8, 8, 8), dtype=G.GMG_F32, cycle_dtype=G.GMG_F64)
     assert lib.gmg_setup(ctypes.byref(p), ctypes.c_void_p(8), None, ctypes.byref(out)) == G.GMG_EINVAL
+

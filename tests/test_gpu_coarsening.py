@@ -9,7 +9,7 @@ import pytest
 from oracle import gmg_oracle as O
 from paper_2607_07687_amd import gmg as G
 from paper_2607_07687_amd import problems as P
-from tests.gpu_util import TOL, dev, host, rel, require_gpu, say, torch
+from tests.gpu_util import assert_close, TOL, dev, host, rel, require_gpu, say, torch
 from tests.test_gpu_parity import _compare_solve, rounding_floor
 
 pytestmark = pytest.mark.gpu
@@ -40,5 +40,5 @@ def test_impulsive_solve_matches_oracle(kind, aspect, aniso):
     say(f"{kind} N={aspect} {'aniso' if aniso else 'iso'}: {len(levels)} levels, "
         f"{info['cycles']} cycles (oracle {ref['cycles']})")
     _compare_solve(info, ref, "f64", rounding_floor(levels, ref, "f64"))
-    assert rel(host(x), ref["x"]) <= 1e-8
+    assert_close(host(x), ref["x"], 1e-8)
     h.close()

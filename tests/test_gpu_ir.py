@@ -9,7 +9,7 @@ import pytest
 from oracle import gmg_oracle as O
 from paper_2607_07687_amd import gmg as G
 from paper_2607_07687_amd import problems as P
-from tests.gpu_util import dev, host, rel, require_gpu, say, torch
+from tests.gpu_util import assert_close, dev, host, rel, require_gpu, say, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -40,8 +40,11 @@ def test_solve_ir_matches_oracle(name, make, storage):
         f"{ro['inner_total']}; final {rg['history'][-1]:.2e}")
     assert rg["status"] == "GMG_OK" and ro["status"] == "ok"
     assert rg["history"][-1] <= 1e-10
-    assert abs(rg["outer"] - ro["outer"]) <= 1
-    assert abs(rg["history"][0] - ro["history"][0]) <= 1e-12 * ro["history"][0]
+    # same number of steps: each step contracts by ~1e-4 (FP32 faces) or
+    # ~2^-9 (BF16), so the last residual is far from the tolerance on both
+    # sides; each step's own arithmetic is compared in the test below
+    assert rg["outer"] == ro["outer"]
+    assert rg["history"][0] == pytest.approx(ro["history"][0], rel=1e-12)  # = 1 from zero
     # the FP64 residual of the returned x, evaluated by the library in FP64
     rn, sn = G.gmg_residual(h, x, sd)
     assert rn <= 1e-10 * sn
@@ -49,6 +52,59 @@ def test_solve_ir_matches_oracle(name, make, storage):
     e = (host(x) - ro["x"])[act]
     xr = ro["x"][act] - ro["x"][act].mean()
     assert np.linalg.norm(e - e.mean()) <= 1e-8 * np.linalg.norm(xr)
+    h.close()
+
+
+def _residual_bound(x, s, L, per):
+    """Element-wise rounding bound of an FP64 residual evaluation:
+    |fl(r) - r| <= 32 eps (|sigma| + sum over faces |L| (|x| + |x_nb|)), a
+    generous gamma_n for the 13 products and sums of one cell's residual."""
+    B = np.abs(s).astype(np.float64)
+    for d in range(3):
+        ax = O.AX[d]
+        Lh = O.high_face(L[d], d, per)
+        B += Lh * (np.abs(x) + np.abs(np.roll(x, -1, axis=ax)))
+        B += L[d] * (np.abs(x) + np.abs(np.roll(x, 1, axis=ax)))
+    return 32 * np.finfo(np.float64).eps * B
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_solve_ir_each_step_matches_oracle(name, make, storage):
+    # after m = 1, 2, 3 outer steps from zero: the library's FP64 residual of
+    # its own iterate equals the oracle's residual of that same iterate
+    # (within the rounding of an FP64 residual evaluation), and the next
+    # step the library takes from it equals the oracle's one step from it
+    # (FP32 inner cycles against the oracle's FP64 ones: 1e-5)
+    require_gpu()
+    say(f"ir steps {name} {storage}")
+    L, s, per = make()
+    n = (L.shape[3], L.shape[2], L.shape[1])
+    params = G.gmg_default_params(n, per, G.GMG_F64, cycle_dtype=G.GMG_F32,
+                                  l_storage=G.GMG_BF16 if storage == "bf16" else G.GMG_F32)
+    h = G.gmg_setup(params, dev(L, "f64"))
+    sd = dev(s, "f64")
+    L64 = O.normalize_faces(L, per)
+    kw = dict(max_inner=8, inner_rtol=1e-4)
+    for m in (1, 2, 3):
+        x = torch.zeros_like(sd)
+        rg = G.gmg_solve_ir(h, x, sd, rtol=0.0, max_outer=m, **kw)
+        assert rg["outer"] == m and rg["status"] == "GMG_ENOCONV"
+        xm = host(x)
+        r = torch.empty_like(sd)
+        rn, sn = G.gmg_residual(h, x, sd, r)
+        ro = O.residual(xm, s, L64, per)
+        err = np.abs(host(r) - ro)
+        bound = _residual_bound(xm, s, L64, per)
+        ratio = np.divide(err, bound, out=np.zeros_like(err), where=bound > 0)
+        say(f"  m={m}: |r| {rn:.3e}, max err/bound {float(ratio.max()):.2f}")
+        assert np.all(err <= bound)
+        assert abs(rn - O.norm2(ro)) <= 1e-10 * O.norm2(ro) + float(np.sqrt((bound ** 2).sum()))
+        # one more step from this iterate on both sides
+        x1 = x.clone()
+        G.gmg_solve_ir(h, x1, sd, rtol=0.0, max_outer=1, **kw)
+        one = O.solve_ir(L, per, xm, s, rtol=0.0, max_outer=1, inner_storage=storage, **kw)
+        assert_close(host(x1) - xm, one["x"] - xm, 1e-5, f"step after m={m}")
     h.close()
 
 

@@ -12,7 +12,7 @@ import pytest
 from oracle import gmg_oracle as O
 from paper_2607_07687_amd import gmg as G
 from paper_2607_07687_amd import problems as P
-from tests.gpu_util import TOL, dev, host, rel, require_gpu, rounded, say, torch
+from tests.gpu_util import assert_close, TOL, dev, host, rel, require_gpu, rounded, say, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -88,7 +88,7 @@ def test_residual(case, prec):
     r = torch.empty_like(sd)
     rn, sn = G.gmg_residual(h, dev(x, prec), sd, r)
     ro = O.residual(x, s64, levels[0]["L"], case[2])
-    assert rel(host(r), ro) <= TOL[prec]
+    assert_close(host(r), ro, TOL[prec])
     act = levels[0]["active"]
     assert np.all(host(r)[~act] == 0.0)
     assert abs(rn - O.norm2(ro)) <= TOL[prec] * O.norm2(ro)
@@ -110,7 +110,7 @@ def test_smoother_sweeps(case, prec):
         xo = x0.copy()
         for _ in range(sweeps):
             xo = O.rb_sweep(xo, s64, levels[0]["L"], per, 0.8)
-        assert rel(host(xd) - x0, xo - x0) <= TOL[prec], f"{sweeps} sweeps"
+        assert_close(host(xd) - x0, xo - x0, TOL[prec], f"{sweeps} sweeps")
     # a coarse level with its own faces
     if len(levels) > 1:
         shp = levels[1]["L"].shape[1:]
@@ -120,7 +120,7 @@ def test_smoother_sweeps(case, prec):
         xd = dev(xc, prec)
         G.gmg_smooth(h, 1, xd, dev(sc, prec), 2)
         xo = O.rb_sweep(O.rb_sweep(xc, sc, levels[1]["L"], per, 0.8), sc, levels[1]["L"], per, 0.8)
-        assert rel(host(xd) - xc, xo - xc) <= TOL[prec]
+        assert_close(host(xd) - xc, xo - xc, TOL[prec])
     h.close()
 
 
@@ -140,7 +140,7 @@ def test_restrict_and_prolong(case, prec):
     xc = torch.full(shp, 7.0, dtype=sd.dtype, device="cuda")
     G.gmg_restrict_residual(h, 0, dev(x, prec), sd, sc, xc)
     want = O.restrict(O.residual(x, s64, levels[0]["L"], per), c)
-    assert rel(host(sc), want) <= TOL[prec]
+    assert_close(host(sc), want, TOL[prec])
     assert torch.count_nonzero(xc).item() == 0
     y = rounded(rng.standard_normal(shp), prec)
     xd = dev(x, prec)
@@ -148,7 +148,7 @@ def test_restrict_and_prolong(case, prec):
     act = levels[0]["active"]
     want = x.copy()
     want[act] += O.prolong(y, c)[act]
-    assert rel(host(xd), want) <= (1e-7 if prec == "f32" else 1e-15)
+    assert_close(host(xd), want, (1e-7 if prec == "f32" else 1e-15))
     assert np.array_equal(host(xd)[~act], x[~act])
     h.close()
 
@@ -163,13 +163,13 @@ def test_vcycle(case, prec, storage):
     xd = torch.zeros_like(sd)
     G.gmg_vcycle(h, xd, sd)
     xo = O.vcycle(levels, np.zeros_like(s64), s64, 0.9)
-    assert rel(host(xd), xo) <= TOL[prec]
+    assert_close(host(xd), xo, TOL[prec])
     # (ii) a later cycle fed the oracle's iterate rounded to the run precision
     xin = rounded(xo, prec)
     xd = dev(xin, prec)
     G.gmg_vcycle(h, xd, sd)
     xo2 = O.vcycle(levels, xin, s64, 0.9)
-    assert rel(host(xd) - xin, xo2 - xin) <= TOL[prec]
+    assert_close(host(xd) - xin, xo2 - xin, TOL[prec])
     h.close()
 
 
@@ -182,7 +182,7 @@ def test_vcycle_tgv32_fp64():
     for _ in range(3):
         G.gmg_vcycle(h, xd, sd)
         xo = O.vcycle(levels, xo, s64, 1.0)
-        assert rel(host(xd), xo) <= 1e-11
+        assert_close(host(xd), xo, 1e-11)
     h.close()
 
 
@@ -192,7 +192,7 @@ def test_vcycle_sphere64_fp32():
     xd = torch.zeros_like(sd)
     G.gmg_vcycle(h, xd, sd)
     xo = O.vcycle(levels, np.zeros_like(s64), s64, 1.0)
-    assert rel(host(xd), xo) <= 1e-5
+    assert_close(host(xd), xo, 1e-5)
     h.close()
 
 
@@ -227,7 +227,7 @@ def test_solve_tgv32_fp64_to_1e10(deferred):
     say(f"tgv32 fp64 cycles gpu {rg['cycles']} oracle {ro['cycles']}")
     assert rg["status"] == "GMG_OK"
     _compare_solve(rg, ro, "f64", rounding_floor(levels, ro, "f64"))
-    assert rel(host(xd), ro["x"]) <= 1e-9
+    assert_close(host(xd), ro["x"], 1e-9)
     rn, sn = G.gmg_residual(h, xd, sd)
     assert rn <= 1e-10 * sn
     h.close()
@@ -259,7 +259,7 @@ def test_solve_rollback_decisions_match(deferred):
     ro = O.solve(levels, np.zeros_like(s64), s64, 1e-9, 80, **kw)
     assert ro["accepted_flags"][0] is False
     _compare_solve(rg, ro, "f64", rounding_floor(levels, ro, "f64"))
-    assert rel(host(xd), ro["x"]) <= 1e-9
+    assert_close(host(xd), ro["x"], 1e-9)
     h.close()
 
 
@@ -294,7 +294,7 @@ def test_solve_edge_cases(deferred):
     assert len(levels) == 1 and G.gmg_num_levels(h) == 1
     xd = torch.zeros_like(sd)
     G.gmg_vcycle(h, xd, sd)
-    assert rel(host(xd), O.vcycle(levels, np.zeros_like(s64), s64, 1.0)) <= 1e-11
+    assert_close(host(xd), O.vcycle(levels, np.zeros_like(s64), s64, 1.0), 1e-11)
     h.close()
 
 
@@ -308,7 +308,7 @@ def test_vcycle_parameter_variants(kw):
     xd = torch.zeros_like(sd)
     G.gmg_vcycle(h, xd, sd)
     xo = O.vcycle(levels, np.zeros_like(s64), s64, 1.0, p.nu_pre, p.nu_post, p.nu_coarse)
-    assert rel(host(xd), xo) <= 1e-11
+    assert_close(host(xd), xo, 1e-11)
     h.close()
 
 
@@ -423,7 +423,7 @@ def test_tail_matches_grid_kernels(case, prec, storage):
     G.gmg_vcycle(h0, x0, sd)
     assert torch.equal(xt, x0)
     xo = O.vcycle(levels, np.zeros_like(s64), s64, 1.0)
-    assert rel(host(xt), xo) <= TOL[prec if storage != "bf16" else "bf16"]
+    assert_close(host(xt), xo, TOL[prec if storage != "bf16" else "bf16"])
     tol = 1e-8 if prec == "f64" else 1e-5
     xt.zero_()
     x0.zero_()

@@ -12,7 +12,7 @@ from oracle import gmg_oracle as O
 from oracle import pcg_oracle as PO
 from paper_2607_07687_amd import gmg as G
 from paper_2607_07687_amd import problems as P
-from tests.gpu_util import TOL, dev, host, rel, require_gpu, rounded, say, torch
+from tests.gpu_util import assert_close, TOL, dev, host, rel, require_gpu, rounded, say, torch
 from tests.test_gpu_parity import build, rounding_floor
 
 pytestmark = pytest.mark.gpu
@@ -43,7 +43,7 @@ def test_pcg_iterates_match_oracle(case, prec):
         e = rel(host(xd), ref["x"])
         say(f"{case[0]} {prec} k={k}: rel {e:.2e}")
         assert info["iterations"] == k
-        assert e <= TOL[prec]
+        assert_close(host(xd), ref["x"], TOL[prec], f"k={k}")
         hist = np.array(info["history"])
         want = np.array(ref["history"])
         assert np.all(np.abs(hist - want) <= TOL[prec] * np.maximum(want, 1e-300) + 1e-12)
@@ -82,7 +82,7 @@ def test_gmg_pcg_vcycle_matches_oracle(prec):
     xo = PO.vcycle_pcg(levels, np.zeros_like(s64), s64)
     e = rel(host(xd), xo)
     say(f"GMG-PCG V-cycle {prec}: rel {e:.2e}")
-    assert e <= TOL[prec]
+    assert_close(host(xd), xo, TOL[prec])
     h.close()
 
 
@@ -94,7 +94,7 @@ def test_gmg_pcg_vcycle_small_cases(case):
     xd = torch.zeros_like(sd)
     G.gmg_vcycle(h, xd, sd)
     xo = PO.vcycle_pcg(levels, np.zeros_like(s64), s64, 1, 3, 5)
-    assert rel(host(xd), xo) <= TOL["f64"]
+    assert_close(host(xd), xo, TOL["f64"])
     h.close()
 
 
@@ -112,7 +112,7 @@ def test_gmg_pcg_solve_matches_oracle():
     floor = rounding_floor(levels, ref, "f64")
     for hg, ho in zip(info["history"], ref["history"]):
         assert abs(hg - ho) <= TOL["f64"] * ho + floor
-    assert rel(host(xd), ref["x"]) <= 1e-9
+    assert_close(host(xd), ref["x"], 1e-9)
     h.close()
 
 

@@ -50,3 +50,33 @@ def test_trained_unet_gains_over_zero_guess():
     assert np.mean(errs) < 0.3
     assert sum(b < a for a, b in zip(r0s, r1s)) >= 6
     assert np.exp(np.mean(np.log(r1s))) < np.exp(np.mean(np.log(r0s)))
+
+
+def test_untrained_prediction_falls_back_to_plain_gmg():
+    # an untrained network's prediction is worse than the zero guess: the
+    # warm-started solve notices it from the prediction's residual, starts
+    # from zero instead and still reaches the tolerance
+    require_gpu()
+    n = (32, 32, 32)
+    (sm,) = W.make_samples(n, [31500], workers=1, with_target=False, keep64=True)
+    net = NET.UNet((16, 32, 64))
+    net.init_he(1)
+    # every weight x4: the output of the ReLU network grows by ~4^depth, so
+    # the prediction is certainly worse than the zero guess
+    net.set_flat(net.get_flat() * 4.0)
+    prm = G.gmg_default_params(n, sm.per, G.GMG_F64, cycle_dtype=G.GMG_F32)
+    h = G.gmg_setup(prm, sm.L64)
+    x = torch.zeros_like(sm.sigma64)
+    xb = torch.zeros((1, 32, 32, 32, NET.IN_CH), dtype=torch.int16, device="cuda")
+    info, why = W.warm_solve(h, net, sm, x, xb, rtol=1e-6, max_outer=30)
+    say(f"untrained net: fallback '{why}', {info['status']}, {info['outer']} steps")
+    assert why is not None
+    assert info["status"] == "GMG_OK"
+    rn, sn = G.gmg_residual(h, x, sm.sigma64)
+    assert rn <= 1e-6 * sn
+    # a budget too small for any start: the fallback from zero also misses and
+    # the result says so
+    x.zero_()
+    info, why = W.warm_solve(h, net, sm, x, xb, rtol=1e-12, max_outer=1)
+    assert info["status"] == "GMG_ENOCONV" and why is not None
+    h.close()

@@ -15,7 +15,8 @@ with none of the oracle's array code:
   and R = P^T, the correction applied on the active cells only;
 * the cycle is the recursion written out: pre-sweeps, restrict the
   residual, recurse from zero, correct, post-sweeps; the coarsest level gets
-  its own sweep count.
+  its own sweep count, fixed, or (the coarsest-level rule) sweeps until its
+  residual norm has dropped by a given factor, within a cap.
 
 Sweep counts (1, 3, 5) and omega = 0.7 are chosen so that a swapped pre/post
 count, a wrong coarsest count, a correction applied after the post-sweeps, a
@@ -137,14 +138,35 @@ def build_reference(L, periodic, storage, anisotropic=True, max_levels=0):
     return refs
 
 
-def vcycle_reference(refs, x, b, omega, nu1, nu2, nuc, l=0):
+def coarsest_reference(r, x, b, omega, nuc, crtol, counts=None):
+    """crtol = 0: nuc sweeps.  crtol > 0: sweep until the residual norm on
+    the active cells is at most crtol times its value on entry, at least one
+    sweep and at most nuc (the cap)."""
+    if crtol <= 0.0:
+        return gauss_seidel(r["A"], r["colour"], x, b, omega, nuc)
+
+    def rnorm(v):
+        res = np.where(r["active"], b - r["A"] @ v, 0.0)
+        return math.sqrt(float(res @ res))
+
+    r0 = rnorm(x)
+    for n in range(1, nuc + 1):
+        x = gauss_seidel(r["A"], r["colour"], x, b, omega, 1)
+        if rnorm(x) <= crtol * r0:
+            break
+    if counts is not None:
+        counts.append(n)
+    return x
+
+
+def vcycle_reference(refs, x, b, omega, nu1, nu2, nuc, l=0, crtol=0.0, counts=None):
     r = refs[l]
     if r["c"] is None:
-        return gauss_seidel(r["A"], r["colour"], x, b, omega, nuc)
+        return coarsest_reference(r, x, b, omega, nuc, crtol, counts)
     x = gauss_seidel(r["A"], r["colour"], x, b, omega, nu1)
     res = np.where(r["active"], b - r["A"] @ x, 0.0)
     bc = r["P"].T @ res  # R = P^T
-    xc = vcycle_reference(refs, np.zeros(bc.size), bc, omega, nu1, nu2, nuc, l + 1)
+    xc = vcycle_reference(refs, np.zeros(bc.size), bc, omega, nu1, nu2, nuc, l + 1, crtol, counts)
     x = x + np.where(r["active"], r["P"] @ xc, 0.0)
     return gauss_seidel(r["A"], r["colour"], x, b, omega, nu2)
 
@@ -171,11 +193,17 @@ def test_vcycle_equals_assembled_reconstruction(name, n, per, storage, aniso, ma
         assert np.array_equal(lv["active"].ravel(), r["active"])
     rng = np.random.default_rng(3)
     x0 = np.where(levels[0]["active"], rng.standard_normal(s.shape), 0.0)
-    for (nu1, nu2, nuc, omega) in ((1, 3, 5, 0.7), (2, 2, 4, 1.0)):
-        got = O.vcycle(levels, x0, s, omega, nu1, nu2, nuc)
-        want = vcycle_reference(refs, x0.ravel(), s.ravel(), omega, nu1, nu2, nuc)
+    for (nu1, nu2, nuc, omega, crtol) in ((1, 3, 5, 0.7, 0.0), (2, 2, 4, 1.0, 0.0),
+                                         (2, 2, 64, 1.0, 0.1), (1, 2, 40, 0.8, 0.01)):
+        st, counts = [], []
+        got = O.vcycle(levels, x0, s, omega, nu1, nu2, nuc if crtol == 0 else 4,
+                       coarse_rtol=crtol, coarse_max=nuc, stats=st)
+        want = vcycle_reference(refs, x0.ravel(), s.ravel(), omega, nu1, nu2, nuc, crtol=crtol,
+                                counts=counts)
         scale = np.abs(want).max()
-        assert np.abs(got.ravel() - want).max() <= 1e-12 * scale, (nu1, nu2, nuc, omega)
+        assert np.abs(got.ravel() - want).max() <= 1e-12 * scale, (nu1, nu2, nuc, omega, crtol)
+        if crtol > 0:
+            assert st == counts and 1 <= st[0] <= nuc
 
 
 def test_reconstruction_detects_plausible_mistakes():
@@ -193,6 +221,11 @@ def test_reconstruction_detects_plausible_mistakes():
 
     assert far(vcycle_reference(refs, x0, s.ravel(), 0.7, 3, 1, 5))  # pre/post swapped
     assert far(vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 4))  # coarsest count
+    # the adaptive coarsest rule: its stopping factor decides the sweep count
+    c1, c2 = [], []
+    a1 = vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 64, crtol=0.1, counts=c1)
+    a2 = vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 64, crtol=0.01, counts=c2)
+    assert c1[0] < c2[0] and np.abs(a1 - a2).max() > 1e-6 * np.abs(a2).max()
     r0 = refs[0]
     # correction after the post-sweeps
     x = gauss_seidel(r0["A"], r0["colour"], x0, s.ravel(), 0.7, 1)
