@@ -193,6 +193,27 @@ gmg_status gmg_level_faces(gmg_handle* h, int32_t level, void* L_out);
 gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma,
                         void* r, double* rnorm, double* snorm);
 
+/* gmg_residual without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the same
+ * kernels and the same results, with the reduction partials in a
+ * fixed-size array that the library keeps in each device's memory until the
+ * process ends, and the norms written to device memory.  It allocates
+ * nothing and never synchronises: all work is enqueued on the handle's
+ * stream, so the call can be captured into a HIP graph.
+ * x, sigma, r: as in gmg_residual (r: device output or NULL).
+ * rnorm, snorm: DEVICE pointers to one double each, or NULL: receive
+ * ||r||_2 and ||sigma||_2 over the active cells (FP64 accumulation), as
+ * gmg_residual returns them on the host.
+ * Limit: level 0 may need at most 2^18 reduction blocks (128 x 2 columns by
+ * 16 z-planes each; every grid up to 1024^3 cells fits); larger grids get
+ * GMG_EINVAL before any work is enqueued.  The array is shared by every call
+ * on that device: calls whose work overlaps on the device (different
+ * streams, or different threads without ordering) race and may return wrong
+ * norms.  Uses the array of the device current at the call, which must be
+ * the device of the handle. */
+gmg_status gmg_residual_noalloc(gmg_handle* h, const void* x, const void* sigma, void* r,
+                                double* rnorm, double* snorm);
+
 /* `sweeps` red-black Gauss-Seidel sweeps (Sec. 3.1) in place on level
  * `level`, at the handle's current omega: each sweep updates every active
  * cell of colour (i+j+k) mod 2 == 0 at once, x(I) += omega r(I) / D(I) from

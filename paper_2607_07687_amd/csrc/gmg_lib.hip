@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1577,6 +1578,46 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
   return drop_graphs(h);
 }
 
+// ---------------------------------------------------------------------------
+// Residual without allocation
+// ---------------------------------------------------------------------------
+
+// Scratch of gmg_residual_noalloc: [0, P) partials of ||r||^2, [P, 2P)
+// partials of ||sigma||^2 (P = kNoAllocPart, one per block of the reduction
+// grid), [2P, 2P + 2) the two sums.  Every element a call reads it has
+// written first, so nothing needs clearing between calls.
+constexpr long long kNoAllocPart = 1LL << 18;
+static __device__ __align__(256) double scratch[2 * kNoAllocPart + 2];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+}  // namespace
+
+// Device address of the current device's `scratch`, looked up once per
+// device (the symbol's host-side name is not a device address).
+static gmg_status scratch_address(double** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GMG_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GMG_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GMG_OK;
+}
+
+// out = sqrt(sum of the n partials), on the device.
+__global__ __launch_bounds__(256) void k_sum_sqrt_to(const double* p, long long n, double* out) {
+  const double s = reduce_partials(p, n);
+  if (threadIdx.x == 0) *out = sqrt(s);
+}
+
 extern "C" {
 
 gmg_status gmg_default_params(gmg_params* p) {
@@ -1693,6 +1734,45 @@ gmg_status gmg_residual(gmg_handle* h, const void* x, const void* sigma, void* r
   HIP_TRY(hipStreamSynchronize(h->s));
   if (rnorm) *rnorm = std::sqrt(tmp[0]);
   if (snorm) *snorm = std::sqrt(tmp[1]);
+  return GMG_OK;
+}
+
+gmg_status gmg_residual_noalloc(gmg_handle* h, const void* x, const void* sigma, void* r,
+                                double* rnorm, double* snorm) {
+  if (!h || !x || !sigma) return fail(GMG_EINVAL, "NULL argument");
+  const Level& lv = h->lev[0];
+  const dim3 gr = red_grid(lv.g);
+  if (nblocks(gr) > kNoAllocPart)
+    return fail(GMG_EINVAL, "gmg_residual_noalloc: level 0 needs " +
+                                std::to_string(nblocks(gr)) + " reduction blocks, the scratch holds " +
+                                std::to_string(kNoAllocPart));
+  double* sc = nullptr;
+  GMG_TRY(scratch_address(&sc));
+  double* pr = rnorm ? sc : nullptr;
+  double* ps = sc + kNoAllocPart;
+  if (h->p.dtype == GMG_F64 && h->p.cycle_dtype == GMG_F32) {
+    Roles<double> X{{(double*)x, (double*)x, (double*)x}, nullptr};
+    hipLaunchKernelGGL((k_residual<double, double>), gr, kBlock, 0, h->s, lv.g, X, 0,
+                       (const double*)sigma, (const double*)h->L0x, (double*)r, pr, kResChunk,
+                       nullptr, 1);
+    if (snorm)
+      hipLaunchKernelGGL((k_masked_sumsq<double>), gr, kBlock, 0, h->s, lv.g,
+                         (const double*)sigma, lv.active, ps, kResChunk);
+  } else {
+    DISPATCH_CYCLE(h, {
+      Roles<T> X{{(T*)x, (T*)x, (T*)x}, nullptr};
+      hipLaunchKernelGGL((k_residual<T, TL>), gr, kBlock, 0, h->s, lv.g, X, 0, (const T*)sigma,
+                         (const TL*)lv.L, (T*)r, pr, kResChunk, nullptr, 1);
+      if (snorm)
+        hipLaunchKernelGGL((k_masked_sumsq<T>), gr, kBlock, 0, h->s, lv.g, (const T*)sigma,
+                           lv.active, ps, kResChunk);
+    });
+  }
+  if (rnorm)
+    hipLaunchKernelGGL(k_sum_sqrt_to, dim3(1), dim3(256), 0, h->s, pr, nblocks(gr), rnorm);
+  if (snorm)
+    hipLaunchKernelGGL(k_sum_sqrt_to, dim3(1), dim3(256), 0, h->s, ps, nblocks(gr), snorm);
+  HIP_TRY(hipGetLastError());
   return GMG_OK;
 }
 

@@ -92,6 +92,8 @@ _SIGS = [
     ("gmg_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
+    ("gmg_residual_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("gmg_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int32]),
     ("gmg_restrict_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
@@ -348,6 +350,21 @@ def gmg_residual(h, x, sigma, r=None, norms=True):
                                ctypes.byref(rn) if norms else None,
                                ctypes.byref(sn) if norms else None))
     return (rn.value, sn.value) if norms else None
+
+
+def gmg_residual_noalloc(h, x, sigma, r=None, norms=None):
+    """gmg_residual without allocation and without synchronising: fills r if
+    given and, if `norms` (a float64 GPU tensor of 2 elements) is given,
+    writes ||r|| to norms[0] and ||sigma|| to norms[1] on the device."""
+    import torch
+    xp, sp, rp = h.arrs(h.spec(x, "x", cycle=False), h.spec(sigma, "sigma", cycle=False),
+                        h.spec(r, "r", cycle=False, optional=True))
+    np_ = _arr(norms, "norms", 2, torch.float64, h.device, optional=True)
+    rnp = snp = None
+    if np_ is not None:
+        rnp = ctypes.c_void_p(norms.data_ptr())
+        snp = ctypes.c_void_p(norms.data_ptr() + norms.element_size())
+    _check(load().gmg_residual_noalloc(h.ptr, xp, sp, rp, rnp, snp))
 
 
 def gmg_smooth(h, level, x, sigma, sweeps):
