@@ -24,9 +24,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GMG V-cycles/s + time to 1e-6 rel. residual at 256³ FP32; % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell of one launch of either level-0 smoothing
-# kernel (FP32): read x (4), sigma (4), the three face arrays (12); write x
-# (4).  The fused sweep does one sweep per launch, the two-sweep pass two.
+# algorithmic bytes per cell and red-black sweep (FP32): read x (4), sigma
+# (4), the three face arrays (12) and write x (4) once per sweep.  A launch
+# moves this times the sweeps it performs (the fused sweep one, the
+# two-sweep pass two).  The pass's own minimum, one read of everything and
+# one write of x for both sweeps, is the same 24 B per cell per launch.
 SWEEP_BYTES_PER_CELL = 24.0
 
 # hardware-counter summaries of the level-0 smoothing kernels (rocprofv3
@@ -98,28 +100,80 @@ def measured_traffic(kind="fused"):
     return kib * 1024.0
 
 
-def cpu_baseline(cycles=2):
-    """The CPU oracle, untuned, on a bounded sample of the benchmark workload
-    itself: `cycles` V-cycles, each followed by the residual norm, on the
-    same 256^3 sphere problem rounded to FP32 (hierarchy built untimed)."""
+def _oracle_cycles(L, s, per, cycles, **kw):
+    """Seconds for `cycles` oracle V-cycles, each with its residual norm, on
+    FP32-rounded inputs (hierarchy built untimed)."""
     from oracle import gmg_oracle as O
-    from paper_2607_07687_amd import problems as P
-
-    L, s, per = P.sphere_256(seed=1)
     L = L.astype(np.float32).astype(np.float64)
     s = s.astype(np.float32).astype(np.float64)
-    levels = O.build_hierarchy(L, per, storage="f32")
+    levels = O.build_hierarchy(L, per, storage="f32", **kw)
     del L
     x = np.zeros_like(s)
     t0 = time.perf_counter()
     for _ in range(cycles):
         x = O.vcycle(levels, x, s, 1.0)
         O.norm2(O.residual(x, s, levels[0]["L"], per))
+    return time.perf_counter() - t0
+
+
+def _oracle_batch_problem(i):
+    """One problem of the uneven batch refined to 1e-10 by the oracle."""
+    from oracle import gmg_oracle as O
+    from paper_2607_07687_amd import problems as P
+    sp = P.batch_specs(64, 3)[i]
+    L, s, per = P.sphere_box(sp["n"], sp["centre"], sp["radius"], "uniform", sp["seed"])
+    res = O.solve_ir(L, per, np.zeros_like(s), s, rtol=1e-10, max_outer=30, max_inner=8)
+    return res["outer"], res["inner_total"], res["status"]
+
+
+def cpu_baseline(cycles=2, others=True):
+    """The CPU oracle, untuned, on bounded samples of the workloads: `cycles`
+    V-cycles (each with its residual norm) of the 256^3 benchmark problem
+    (the reported value), and beside it the 32^3 periodic FP64 solve to 1e-10
+    in full, 2 V-cycles of the 512 x 192 x 192 channel and the 64-problem
+    batch refined to 1e-10 in a process pool over the host cores."""
+    from oracle import gmg_oracle as O
+    from paper_2607_07687_amd import problems as P
+
+    L, s, per = P.sphere_256(seed=1)
+    dt = _oracle_cycles(L, s, per, cycles)
+    del L, s
+    out = {"value": cycles / dt, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
+           "sample": f"{cycles} oracle V-cycles, each with its residual norm, on the 256^3 "
+                     f"benchmark problem: {dt:.1f} s; NumPy elementwise, one thread; "
+                     f"host has {os.cpu_count()} logical CPUs"}
+    if not others:
+        return out
+    legs = {}
+    log("oracle: 32^3 periodic FP64 solve")
+    L, s, per = P.tgv_periodic(32, seed=0)
+    levels = O.build_hierarchy(L, per)
+    t0 = time.perf_counter()
+    res = O.solve(levels, np.zeros_like(s), s, 1e-10, 100)
+    legs["tgv32_fp64_solve"] = {"value": 1e3 * (time.perf_counter() - t0), "unit": "ms to 1e-10",
+                                "cycles": res["cycles"], "cores": 1,
+                                "sample": "full oracle solve from x = 0, FP64"}
+    log("oracle: 512 x 192 x 192 channel cycles")
+    L, s, per = P.sphere_channel(seed=2)
+    dt = _oracle_cycles(L, s, per, cycles)
+    del L, s
+    legs["channel512_fp32_aniso"] = {"value": cycles / dt, "unit": "V-cycles/s", "cores": 1,
+                                     "sample": f"{cycles} oracle V-cycles with residual norms, "
+                                               f"anisotropic hierarchy: {dt:.1f} s"}
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1))
+    log(f"oracle: 64-problem batch over {workers} processes")
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        rs = list(ex.map(_oracle_batch_problem, range(64)))
     dt = time.perf_counter() - t0
-    return {"value": cycles / dt, "unit": "V-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cycles} oracle V-cycles, each with its residual norm, on the 256^3 "
-                      f"benchmark problem: {dt:.1f} s; NumPy elementwise, one thread; "
-                      f"host has {os.cpu_count()} logical CPUs"}
+    legs["batch64_ir_fp64"] = {"value": 1e3 * dt, "unit": "ms to 1e-10 (all 64 problems)",
+                               "cores": workers, "all_ok": all(r[2] == "ok" for r in rs),
+                               "max_outer": max(r[0] for r in rs),
+                               "sample": f"the 64 problems refined to 1e-10 by the oracle, "
+                                         f"one per task in a pool of {workers} processes"}
+    out["other_configs"] = legs
+    return out
 
 
 def timed(fn, reps=3):
@@ -206,24 +260,86 @@ def coarsening_sweep(m=64, aspects=(1, 2, 4, 8), rtol=1e-8, max_cycles=3000):
             sd = torch.from_numpy(s).cuda()
             del L, s
             row = {"n": list(n)}
-            for aniso in (1, 0):
-                h = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F64, anisotropic=aniso), Ld)
-                x = torch.zeros_like(sd)
-                G.gmg_solve(h, x, sd, rtol, 1)  # capture the cycle graph
-                x.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                info = G.gmg_solve(h, x, sd, rtol, max_cycles)
-                torch.cuda.synchronize()
-                row["aniso" if aniso else "iso"] = {
-                    "levels": G.gmg_num_levels(h), "cycles": info["cycles"],
-                    "status": info["status"], "ms": 1e3 * (time.perf_counter() - t0)}
-                h.close()
-            row["cycle_ratio_iso_over_aniso"] = row["iso"]["cycles"] / max(1, row["aniso"]["cycles"])
+            # the default coarsest-level rule, and fixed nu_coarse = 4 sweeps
+            for rule, crtol in (("", None), ("_fixed4", 0.0)):
+                for aniso in (1, 0):
+                    kw = {} if crtol is None else {"coarse_rtol": crtol, "nu_coarse": 4}
+                    h = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F64, anisotropic=aniso,
+                                                         **kw), Ld)
+                    x = torch.zeros_like(sd)
+                    G.gmg_solve(h, x, sd, rtol, 1)  # capture the cycle graph
+                    x.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info = G.gmg_solve(h, x, sd, rtol, max_cycles)
+                    torch.cuda.synchronize()
+                    row[("aniso" if aniso else "iso") + rule] = {
+                        "levels": G.gmg_num_levels(h), "cycles": info["cycles"],
+                        "status": info["status"], "ms": 1e3 * (time.perf_counter() - t0)}
+                    h.close()
+                row["cycle_ratio_iso_over_aniso" + rule] = \
+                    row["iso" + rule]["cycles"] / max(1, row["aniso" + rule]["cycles"])
             out[f"{kind}_N{N}"] = row
             log(f"{kind} N={N} {tuple(n)}: aniso {row['aniso']['cycles']} cycles "
                 f"({row['aniso']['levels']} levels), iso {row['iso']['cycles']} "
-                f"({row['iso']['levels']} levels)")
+                f"({row['iso']['levels']} levels); fixed 4 coarsest sweeps: aniso "
+                f"{row['aniso_fixed4']['cycles']}, iso {row['iso_fixed4']['cycles']}")
+    return out
+
+
+def sequence_solves(n=(256, 64, 64), steps=12, rtol=1e-6):
+    """Time-correlated pressure solves (the regime of Table 1): a sphere
+    accelerating through a walled 4:1:1 box, one solve per time step after
+    replacing the hierarchy's faces in place (gmg_update_faces): FP64
+    refinement around FP32 V-cycles to rtol (these smooth pressures sit
+    below the FP32 residual floor), from zero, from the previous step's
+    pressure, and from its linear extrapolation 2 p(t-1) - p(t-2).  Reports
+    V-cycles per solve (mean over the steps after the second), refinement
+    steps, the final relative residual and the wall time per step (face
+    update + solve) per cell."""
+    import torch
+    from paper_2607_07687_amd import gmg as G
+    from paper_2607_07687_amd import problems as P
+    seq = [P.moving_body_problem("sphere", n, k) for k in range(steps)]
+    per = seq[0][2]
+    Ls = [torch.from_numpy(L).cuda() for L, _, _ in seq]
+    ss = [torch.from_numpy(s).cuda() for _, s, _ in seq]
+    del seq
+    h = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F64, cycle_dtype=G.GMG_F32), Ls[0])
+    cells = n[0] * n[1] * n[2]
+    out = {"n": list(n), "steps": steps, "rtol": rtol,
+           "solve": "FP64 refinement around FP32 V(2,2) cycles"}
+    for mode in ("cold", "previous", "extrapolated"):
+        x = torch.zeros_like(ss[0])
+        p1 = torch.zeros_like(x)
+        p2 = torch.zeros_like(x)
+        cyc, outer, fin, ms = [], [], [], []
+        G.gmg_solve_ir(h, x, ss[0], rtol, 30)  # graph capture
+        for k in range(steps):
+            if mode == "cold" or k == 0:
+                x.zero_()
+            elif mode == "previous" or k == 1:
+                x.copy_(p1)
+            else:
+                torch.sub(p1 * 2.0, p2, out=x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G.gmg_update_faces(h, Ls[k])
+            info = G.gmg_solve_ir(h, x, ss[k], rtol, 30)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+            cyc.append(info["inner_total"])
+            outer.append(info["outer"])
+            fin.append(info["history"][-1])
+            assert info["status"] == "GMG_OK", (mode, k, info["status"])
+            p2.copy_(p1)
+            p1.copy_(x)
+        out[mode] = {"cycles_per_solve": float(np.mean(cyc[2:])), "cycles": cyc,
+                     "refinement_steps": outer, "worst_final_rel": max(fin),
+                     "ms_per_step": float(np.median(ms[2:])),
+                     "ns_per_cell_step": 1e6 * float(np.median(ms[2:])) / cells}
+        log(f"sequence {mode}: cycles {cyc}, {out[mode]['ms_per_step']:.2f} ms per step")
+    h.close()
     return out
 
 
@@ -293,11 +409,19 @@ def extra_configs():
         return G.gmg_batch_solve_ir(b, xs, ss, rtol=1e-10, max_outer=30, max_inner=8)
     run()  # records the graph
     ms, infos = timed(run, 3)
+    outer = [i["outer"] for i in infos]
+    inner = [i["inner_total"] for i in infos]
     out["batch64_ir_fp64"] = {"problems": 64, "cells": cells, "time_to_1e-10_ms": ms,
                               "all_ok": all(i["status"] == "GMG_OK" for i in infos),
-                              "max_outer": max(i["outer"] for i in infos),
+                              "max_outer": max(outer),
+                              "outer_histogram": {str(k): outer.count(k)
+                                                  for k in sorted(set(outer))},
+                              "inner_cycles_min_median_max": [min(inner),
+                                                              float(np.median(inner)),
+                                                              max(inner)],
+                              "slowest_problem": int(np.argmax(inner)),
                               "worst_final_rel": max(i["history"][-1] for i in infos),
-                              "graph_launches": 1 + max(i["outer"] for i in infos)}
+                              "graph_launches": 1 + max(outer)}
     b.close()
     log(f"batch: {out['batch64_ir_fp64']}")
     return out
@@ -311,6 +435,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-runs", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--deferred-norm", type=int, default=None, choices=(0, 1),
+                    help="override the library's default deferred_norm for the 256^3 solve")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration), 4 level-0 "
                          "sweeps at 256^3 as two two-sweep passes, then 4 as fused sweeps, "
@@ -336,6 +462,8 @@ def main():
     del L, s
     n = (256, 256, 256)
     params = G.gmg_default_params(n, per, G.GMG_F32)
+    if args.deferred_norm is not None:
+        params.deferred_norm = args.deferred_norm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = G.gmg_setup(params, Ld)
@@ -369,7 +497,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert info["cycles"] == args.steps, info["cycles"]
-    log(f"{args.steps} cycles in {dt * 1e3:.2f} ms")
+    floor_sweeps = G.gmg_coarse_sweeps(h)
+    log(f"{args.steps} cycles in {dt * 1e3:.2f} ms (coarsest sweeps in the last: {floor_sweeps})")
 
     # time to 1e-6 from x = 0 (median of runs)
     ttt, cyc = [], []
@@ -383,7 +512,9 @@ def main():
         cyc.append(res["cycles"])
         assert res["status"] == "GMG_OK", res["status"]
     rn, sn = G.gmg_residual(h, x, sd)
-    log(f"time to 1e-6: {sorted(ttt)} ms, cycles {cyc}, final rel {rn / sn:.3e}")
+    coarse_last = G.gmg_coarse_sweeps(h)
+    log(f"time to 1e-6: {sorted(ttt)} ms, cycles {cyc}, final rel {rn / sn:.3e}, "
+        f"coarsest sweeps in the last cycle {coarse_last}")
 
     # dominant kernel: the level-0 smoothing launch the solve uses (the
     # two-sweep pass, or the fused sweep where the tuner turned passes off),
@@ -410,8 +541,11 @@ def main():
     launch = pass_ms if pair_kc else fused_ms
     copy_gbs = device_copy_gbs(stream)
     cells = 256 ** 3
-    alg_bytes = SWEEP_BYTES_PER_CELL * cells
+    sweeps_per_launch = 2 if pair_kc else 1
+    alg_bytes = SWEEP_BYTES_PER_CELL * sweeps_per_launch * cells
     achieved = alg_bytes / (launch * 1e-3) / 1e9
+    one_read_gbs = SWEEP_BYTES_PER_CELL * cells / (launch * 1e-3) / 1e9
+    traffic = measured_traffic(kind)
     h.close()
     if pair_kc:
         kname = (f"k_rb_sweep2<float,float,{tiles[0].get('pair_ty', 16)},false> "
@@ -435,33 +569,47 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "sphere256_walls_fp32", "n": list(n), "levels": nlev,
-                   "cycle": "V(2,2), 4 coarsest sweeps, adaptive omega with rollback",
+                   "cycle": f"V({params.nu_pre},{params.nu_post}), coarsest level swept until "
+                            f"its residual falls by {params.coarse_rtol:g} (at most "
+                            f"{params.coarse_max} sweeps), adaptive omega with rollback",
+                   "deferred_norm": int(params.deferred_norm),
                    "sphere_diameter": 64, "rhs": "flux divergence of U[-1,1] face velocity"},
         "time_to_tol_ms": float(np.median(ttt)),
         "cycles_to_tol": int(np.median(cyc)),
         "final_rel_residual": rn / sn,
         "setup_ms": setup_ms,
+        "coarsest_sweeps_last_cycle": {"solve_to_1e-6": coarse_last,
+                                       "timed_run": floor_sweeps},
         "tiles": [{"level": t["level"], "ty": t["ty"], "kchunk": t["kchunk"],
                    "pass_ty": t.get("pair_ty", 16), "pass_kchunk": t.get("pair_kchunk", 0)}
                   for t in tiles],
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kind),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (counters)",
                      "avg_launch_us": launch * 1e3,
                      "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_rule": f"{SWEEP_BYTES_PER_CELL:g} B per cell per sweep x "
+                                       f"{sweeps_per_launch} sweep(s) per launch x {cells} cells",
+                     "one_read_min_gbs": one_read_gbs,
+                     "one_read_min_frac": one_read_gbs / HBM_PEAK_GBS,
+                     "traffic_gbs": traffic / (launch * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac": traffic / (launch * 1e-3) / 1e9 / HBM_PEAK_GBS
+                     if traffic else None,
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "level0_smoothing": {
             "two_sweep_pass_us": pass_ms * 1e3 if pass_ms else None,
             "fused_sweep_us": fused_ms * 1e3,
             "us_per_sweep": (pass_ms / 2 if pass_ms else fused_ms) * 1e3,
-            "fused_sweep_frac": alg_bytes / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fused_sweep_frac": SWEEP_BYTES_PER_CELL * cells / (fused_ms * 1e-3) / 1e9
+            / HBM_PEAK_GBS,
             "fused_sweep_traffic": measured_traffic("fused")},
     }
     if not args.no_extras:
         out["other_configs"] = extra_configs()
         out["other_configs"]["solver_table"] = solver_comparison()
         out["other_configs"]["coarsening_sweep"] = coarsening_sweep()
+        out["other_configs"]["moving_sphere_sequence"] = sequence_solves()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -83,7 +83,8 @@ typedef struct gmg_params {
   int32_t max_levels;    /* cap on the number of levels, 0 = none (default)   */
   int32_t nu_pre;        /* red-black sweeps before restriction (default 2)   */
   int32_t nu_post;       /* sweeps after the correction (default 2)           */
-  int32_t nu_coarse;     /* sweeps on the coarsest level, no direct solve (4) */
+  int32_t nu_coarse;     /* sweeps on the coarsest level when coarse_rtol is 0,
+                            no direct solve (4)                                */
   int32_t rollback;      /* 1: a V-cycle that grows the residual is discarded
                             (default 1)                                        */
   int32_t graphs;        /* 1: replay the solve's V-cycle (and refinement step)
@@ -126,6 +127,18 @@ typedef struct gmg_params {
   double omega_max;      /* upper bound (1.0)                                 */
   double theta_dec;      /* factor applied on residual growth (0.5)           */
   double theta_inc;      /* factor applied on residual decay (1.2)            */
+  double coarse_rtol;    /* smoothing of the coarsest level of a hierarchy of
+                            two or more levels (red-black smoother): sweeps
+                            until its residual norm (active cells, FP64 sum)
+                            is at most coarse_rtol times its value on entry,
+                            at least one and at most coarse_max.  Sec. 3.2:
+                            the coarsest grid is where the smoother removes
+                            the lowest wavenumbers.  Needs a coarsest level
+                            of at most 2^20 cells (else gmg_setup returns
+                            GMG_ESHAPE).  0: exactly nu_coarse sweeps.  A
+                            single-level grid always takes nu_coarse sweeps
+                            per cycle.  Must be in [0, 1) (default 0.1)      */
+  int32_t coarse_max;    /* sweep cap of that rule, 1 .. 4096 (default 64)    */
 } gmg_params;
 
 #define GMG_MAX_HISTORY 512
@@ -168,6 +181,17 @@ gmg_status gmg_default_params(gmg_params* p);
  * Synchronises the stream. */
 gmg_status gmg_setup(const gmg_params* p, const void* L, void* stream,
                      gmg_handle** out);
+
+/* New face coefficients for an existing hierarchy: the per-time-step update
+ * of a moving or deforming body, whose faces change every step while the
+ * grid does not (the paper's solver restricts L afresh on every level each
+ * time step, Sec. 3.2).  L: device, [3][nz][ny][nx] in params.dtype, as for
+ * gmg_setup; copied and restricted into the handle's storage on every level
+ * (same results as a new gmg_setup with this L), the caller may free it
+ * afterwards.  Allocates nothing; recorded graphs stay valid.  Synchronises
+ * the stream.  A non-finite face gives GMG_EINVAL and leaves the hierarchy
+ * unusable until a valid update. */
+gmg_status gmg_update_faces(gmg_handle* h, const void* L);
 
 /* Free everything the handle owns.  NULL is accepted. */
 gmg_status gmg_destroy(gmg_handle* h);
@@ -241,6 +265,12 @@ gmg_status gmg_prolong_correct(gmg_handle* h, int32_t level,
  * omega0 at the start of each gmg_solve).  get synchronises. */
 gmg_status gmg_get_omega(gmg_handle* h, double* omega);
 gmg_status gmg_set_omega(gmg_handle* h, double omega);
+
+/* Number of red-black sweeps the coarsest level received in the handle's
+ * most recent V-cycle that reached it through the single-workgroup tail
+ * (nu_coarse, or the count chosen by the coarse_rtol rule, Sec. 3.2);
+ * 0 before any.  Synchronises the handle's stream. */
+gmg_status gmg_coarse_sweeps(gmg_handle* h, int32_t* sweeps);
 
 /* One V(nu_pre, nu_post) cycle (Sec. 3) in place on x (device, dtype ==
  * cycle_dtype) at the current omega, with no adaptation:

@@ -261,17 +261,26 @@ def build_hierarchy(L, periodic, anisotropic=True, min_coarse=4, max_levels=0,
 # V-cycle and adaptive solve (Sec. 3 and 3.1)
 # ----------------------------------------------------------------------------
 
-def coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max):
+def coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max, act=None):
     """Smoothing on the coarsest level, where the smoother itself has to
     remove the lowest wavenumbers (Sec. 3.2).  coarse_rtol = 0: exactly
-    nu_coarse sweeps.  coarse_rtol > 0: sweeps until the level's residual norm
-    (active cells, FP64) is at most coarse_rtol times its value on entry, at
-    least one sweep and at most coarse_max.  No direct solve either way.
-    Returns (x, sweeps)."""
+    nu_coarse sweeps.  coarse_rtol > 0: first sigma loses its mean over the
+    active cells ``act`` (with walls and periodic directions only the level
+    is singular, constants being in the null space, and only a zero-mean
+    right-hand side is solvable; the restricted residual has zero mean in
+    exact arithmetic), then sweeps until the residual norm over the active
+    cells is at most coarse_rtol times its value on entry, at least one
+    sweep and at most coarse_max.  No direct solve either way.  Returns
+    (x, sweeps)."""
     if coarse_rtol <= 0.0:
         for _ in range(nu_coarse):
             x = rb_sweep(x, sigma, L, per, omega)
         return x, nu_coarse
+    if act is None:
+        act = active_set(L, per)
+    sigma = np.array(sigma, dtype=np.float64, copy=True)
+    if act.any():
+        sigma[act] -= sigma[act].mean()
     r0 = norm2(residual(x, sigma, L, per))
     n = 0
     while n < coarse_max:
@@ -282,17 +291,20 @@ def coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max)
     return x, n
 
 
-def vcycle(levels, x, sigma, omega, nu_pre=2, nu_post=2, nu_coarse=4, l=0, coarse_rtol=0.0,
+def vcycle(levels, x, sigma, omega, nu_pre=2, nu_post=2, nu_coarse=4, l=0, coarse_rtol=0.1,
            coarse_max=64, stats=None):
     """One V(nu_pre, nu_post) cycle from level l with the same omega
-    everywhere.  The coarsest level is smoothed by ``coarsest_sweeps`` (no
-    direct solve).  Returns the new x (a new array); the sweep count of the
-    coarsest level is appended to ``stats`` if given."""
+    everywhere.  The coarsest level of a hierarchy of two or more levels is
+    smoothed by ``coarsest_sweeps`` (no direct solve); a single-level
+    hierarchy has no coarse-grid correction, and its cycle is nu_coarse plain
+    sweeps.  Returns the new x (a new array); the sweep count of the coarsest
+    level is appended to ``stats`` if given."""
     lev = levels[l]
     L, per = lev["L"], lev["periodic"]
     x = np.array(x, dtype=np.float64, copy=True)
     if lev["c"] is None:
-        x, n = coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max)
+        x, n = coarsest_sweeps(x, sigma, L, per, omega, nu_coarse,
+                               coarse_rtol if l > 0 else 0.0, coarse_max, lev["active"])
         if stats is not None:
             stats.append(n)
         return x
@@ -310,7 +322,7 @@ def vcycle(levels, x, sigma, omega, nu_pre=2, nu_post=2, nu_coarse=4, l=0, coars
     return x
 
 
-DEFAULTS = dict(nu_pre=2, nu_post=2, nu_coarse=4, coarse_rtol=0.0, coarse_max=64, omega0=1.0,
+DEFAULTS = dict(nu_pre=2, nu_post=2, nu_coarse=4, coarse_rtol=0.1, coarse_max=64, omega0=1.0,
                 omega_min=0.1, omega_max=1.0, theta_dec=0.5, theta_inc=1.2, rollback=True)
 
 

@@ -1,16 +1,24 @@
 // Batched mixed-precision solve of many independent Poisson problems of
-// uneven sizes: one HIP-graph launch per refinement step of all problems.
+// uneven sizes.
 //
 // Every problem keeps its own handle (hierarchy, buffers, device states).  The
 // batched kernels below take descriptor tables instead of a single geometry:
 // one launch covers, for instance, the fused sweep of level l of every problem
-// that has a level l, tile by tile.  The V-cycle runs depth by depth in
-// lockstep; a problem whose coarsest level is l smooths there during both the
-// descent and the ascent (nu_pre + nu_post = nu_coarse sweeps).  Per-problem
-// device flags turn converged problems into no-ops, so one refinement step of
-// every problem (max_inner cycles, the new FP64 residual and its check) is one
-// recorded graph.  The host replays it until a device flag reports every
-// problem finished, or max_outer times.
+// that has a level l, tile by tile.  The grid-wide levels of a V-cycle run
+// depth by depth in lockstep; the levels of each problem below its tail start
+// (at most tail_cells cells, down to the coarsest) run in one launch of
+// k_tail_batch, one workgroup per problem, which also applies the
+// coarsest-level rule (coarse_rtol) per problem.  A problem without a tail
+// (a single level) smooths its coarsest level during both the descent and
+// the ascent (nu_pre + nu_post = nu_coarse sweeps).  Per-problem device flags
+// turn converged problems into no-ops, so one refinement step of every
+// problem (max_inner cycles, the new FP64 residual and its check) is one
+// recorded graph.  The host launches a graph of the set-up and the first
+// steps, then replays the one-step graph with a flag read-back between
+// replays until every problem has finished, or max_outer steps.  Tile
+// shapes: the separate sweep's z-chunk per level shape comes from
+// gmg_batch_autotune; the two-sweep pass tiles follow the fixed rule in
+// batch_build_tables.
 //
 // Included once, at the end of gmg_lib.hip.
 #pragma once
@@ -23,6 +31,7 @@ struct BLevel {
   Geom g, gc;          // level and next-coarser geometry (gc = g on the coarsest)
   int cx, cy, cz;      // factor to the next level (1 on the coarsest)
   int coarsest;
+  int next_tail;       // level l+1 is run by the tail, which leaves its result in x[0]
   int vec2;            // nx even: 2-wide loads in the fused sweep
   const TL* L;
   const uint8_t* active;
@@ -74,8 +83,8 @@ __global__ __launch_bounds__(32 * TY) void k_b_sweep(const BLevel<TL>* __restric
   if (*d.done) return;
   __shared__ SweepSmem<float, TY> sm;
   const Roles<float> X{{d.x[0], d.x[1], d.x[2]}, d.sel};
-  const float* xc =
-      (corr_role >= 0 && !d.coarsest) ? (corr_role ? d.x_next1 : d.x_next0) : nullptr;
+  const int cr = d.next_tail ? 0 : corr_role;
+  const float* xc = (corr_role >= 0 && !d.coarsest) ? (cr ? d.x_next1 : d.x_next0) : nullptr;
   const float omega = (float)(*d.omega);
   if (d.vec2) {
     SweepArgs<float, TL, TY, 2> a{d.g, X.get(rs), d.sigma, d.L, xc, d.active, d.gc,
@@ -104,7 +113,8 @@ __global__ __launch_bounds__(S2Cfg<TY>::NTB) void k_b_sweep2(const BLevel<TL>* _
   const Roles<float> X{{d.x[0], d.x[1], d.x[2]}, d.sel};
   const float omega = (float)(*d.omega);
   const bool corr = PROL && !d.coarsest;
-  const float* xc = corr ? (corr_role ? d.x_next1 : d.x_next0) : X.get(rs);
+  const int cr = d.next_tail ? 0 : corr_role;
+  const float* xc = corr ? (cr ? d.x_next1 : d.x_next0) : X.get(rs);
   const S2Args<float, TL> a{d.g,      X.get(rs),       d.sigma,         d.L,
                             xc,       d.active,        corr ? d.gc : d.g, corr ? d.cx : 1,
                             corr ? d.cy : 1, corr ? d.cz : 1, corr ? 1 : 0};
@@ -357,7 +367,12 @@ struct gmg_batch {
   int n;
   gmg_handle** h;
   hipStream_t s;
-  int depth;        // max levels over the problems
+  int depth;        // max over the problems of the levels run by grid kernels
+  void* tails;      // TailArgs<float, TL>[ntail]: problems with a tail, those
+                    // staged in LDS first, then those run in global memory
+  int ntail;
+  int ntail_lds;    // of which staged in LDS
+  int tail_lds;     // dynamic LDS of k_tail_batch (the largest tail)
   int storage;      // GMG_F32 or GMG_BF16
   gmg_params p0;
   // device descriptor tables
@@ -391,8 +406,11 @@ gmg_status batch_build_tables(gmg_batch* b) {
   std::vector<std::vector<BTile>> sw(b->depth), rt(b->depth);
   std::vector<BTile> rs;
   std::vector<int> lv_index(b->n * kMaxLevels, -1);
+  std::vector<TailArgs<float, TL>> tails, gtails;
+  int tail_lds = 0;
   for (int p = 0; p < b->n; ++p) {
     gmg_handle* h = b->h[p];
+    const int lt = h->tail;  // levels lt .. nlev-1 run in the problem's tail
     for (int l = 0; l < h->nlev; ++l) {
       const Level& L = h->lev[l];
       BLevel<TL> d;
@@ -404,6 +422,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
       d.cy = coarsest ? 1 : L.c[1];
       d.cz = coarsest ? 1 : L.c[2];
       d.coarsest = coarsest ? 1 : 0;
+      d.next_tail = (l + 1 == lt && lt < h->nlev) ? 1 : 0;
       d.vec2 = (L.g.nx % 2 == 0) ? 1 : 0;
       d.L = (const TL*)L.L;
       d.active = L.active;
@@ -428,6 +447,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
       const int di = (int)lvs.size();
       lv_index[p * kMaxLevels + l] = di;
       lvs.push_back(d);
+      if (l >= lt) continue;  // the tail's level: no grid tiles
       // sweep tiles
       for (int kz = 0; kz < L.g.nz; kz += L.kchunk)
         for (int ty = 0; ty < L.g.ny; ty += TY)
@@ -438,6 +458,11 @@ gmg_status batch_build_tables(gmg_batch* b) {
         for (int K = 0; K < h->lev[l + 1].g.nz; ++K)
           for (int ty = 0; ty < L.g.ny; ty += BY)
             for (int tx = 0; tx < L.g.nx; tx += BX) rt[l].push_back(BTile{di, tx, ty, K, K, 0});
+    }
+    if (lt < h->nlev) {
+      int bytes = 0;
+      (h->tail_global ? gtails : tails).push_back(tail_args<float, TL>(h, lt, &h->st->done, &bytes));
+      tail_lds = std::max(tail_lds, bytes);
     }
     // level-0 residual / update tiles in the same order as the single-problem grid
     const Level& L0 = h->lev[0];
@@ -478,7 +503,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
       long long xy = 0;
       for (int p = 0; p < b->n; ++p) {
         const gmg_handle* h = b->h[p];
-        if (l >= h->nlev) continue;
+        if (l >= h->tail) continue;
         const Geom& g = h->lev[l].g;
         if (g.nx % 2 != 0 || g.n > S2_MAX_CELLS) ok = false;
         xy += (long long)((g.nx + S2_TX - 1) / S2_TX) * ((g.ny + ty - 1) / ty);
@@ -487,7 +512,7 @@ gmg_status batch_build_tables(gmg_batch* b) {
       const int chunks = std::max(1, (int)std::lround(2.0 * kCUs / (double)xy));
       for (int p = 0; p < b->n; ++p) {
         const gmg_handle* h = b->h[p];
-        if (l >= h->nlev) continue;
+        if (l >= h->tail) continue;
         const Geom& g = h->lev[l].g;
         const int di = lv_index[p * kMaxLevels + l];
         const int kc = std::min(g.nz, std::max(2, (g.nz + chunks - 1) / chunks));
@@ -542,6 +567,17 @@ gmg_status batch_build_tables(gmg_batch* b) {
   if (!ptf.empty())
     HIP_TRY(hipMemcpy(b->pair_tiles, ptf.data(), ptf.size() * sizeof(BTile), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->res_tiles, rs.data(), rs.size() * sizeof(BTile), hipMemcpyHostToDevice));
+  b->ntail_lds = (int)tails.size();
+  tails.insert(tails.end(), gtails.begin(), gtails.end());
+  b->ntail = (int)tails.size();
+  b->tail_lds = tail_lds;
+  if (b->ntail) {
+    HIP_TRY(hipMalloc(&b->tails, tails.size() * sizeof(TailArgs<float, TL>)));
+    HIP_TRY(hipMemcpy(b->tails, tails.data(), tails.size() * sizeof(TailArgs<float, TL>),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_tail_batch<float, TL, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds));
+  }
   return GMG_OK;
 }
 
@@ -624,6 +660,14 @@ gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, bool head, double rt
           hipLaunchKernelGGL(k_b_restrict<TL>, dim3(b->rest_cnt[l]), rblk, 0, s, lv,
                              b->rest_tiles + b->rest_off[l], r);
       }
+      if (b->ntail_lds)
+        hipLaunchKernelGGL((k_tail_batch<float, TL, false>), dim3(b->ntail_lds),
+                           dim3(kTailThreads), b->tail_lds, s,
+                           (const TailArgs<float, TL>*)b->tails);
+      if (b->ntail > b->ntail_lds)
+        hipLaunchKernelGGL((k_tail_batch<float, TL, true>), dim3(b->ntail - b->ntail_lds),
+                           dim3(kTailThreads), 0, s,
+                           (const TailArgs<float, TL>*)b->tails + b->ntail_lds);
       for (int l = b->depth - 1; l >= 0; --l) {  // ascent (coarsest levels finish smoothing)
         int r = role[l];
         // the prolongation source: the role level l+1's smoothing ended on
@@ -669,6 +713,7 @@ void free_batch(gmg_batch* b) {
   (void)hipFree(b->pair_tiles);
   (void)hipFree(b->rest_tiles);
   (void)hipFree(b->res_tiles);
+  (void)hipFree(b->tails);
   if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
   if (b->step.exec) (void)hipGraphExecDestroy(b->step.exec);
   (void)hipFree(b->all_done);
@@ -697,10 +742,10 @@ gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32
     if (q.l_storage != p0.l_storage || q.nu_pre != p0.nu_pre || q.nu_post != p0.nu_post ||
         q.nu_coarse != p0.nu_coarse || q.rollback != p0.rollback || q.omega0 != p0.omega0 ||
         q.omega_min != p0.omega_min || q.omega_max != p0.omega_max ||
-        q.theta_dec != p0.theta_dec || q.theta_inc != p0.theta_inc)
-      return fail(GMG_EINVAL, "batch problems must share storage, sweeps and the omega rule");
-    if (q.nu_coarse != q.nu_pre + q.nu_post)
-      return fail(GMG_EINVAL, "batch needs nu_coarse == nu_pre + nu_post");
+        q.theta_dec != p0.theta_dec || q.theta_inc != p0.theta_inc ||
+        q.coarse_rtol != p0.coarse_rtol || q.coarse_max != p0.coarse_max)
+      return fail(GMG_EINVAL,
+                  "batch problems must share storage, sweeps, the coarse rule and the omega rule");
   }
   gmg_batch* b = new (std::nothrow) gmg_batch();
   if (!b) return fail(GMG_ENOMEM, "host allocation failed");
@@ -727,7 +772,12 @@ gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32
       free_batch(b);
       return st;
     }
-    b->depth = std::max(b->depth, h->nlev);
+    if (h->tail == h->nlev && params[p].nu_coarse != params[p].nu_pre + params[p].nu_post) {
+      free_batch(b);
+      return fail(GMG_EINVAL, "a batch problem without a tail (a single level) needs "
+                              "nu_coarse == nu_pre + nu_post");
+    }
+    b->depth = std::max(b->depth, h->tail);
   }
   const gmg_status st = (b->storage == GMG_BF16) ? batch_build_tables<uint16_t>(b)
                                                  : batch_build_tables<float>(b);
@@ -800,7 +850,8 @@ gmg_status gmg_batch_autotune(gmg_batch* b, int32_t reps) {
   (void)hipFree(b->pair_tiles);
   (void)hipFree(b->rest_tiles);
   (void)hipFree(b->res_tiles);
-  b->lv = b->ov = nullptr;
+  (void)hipFree(b->tails);
+  b->lv = b->ov = b->tails = nullptr;
   b->sweep_tiles = b->pair_tiles = b->rest_tiles = b->res_tiles = nullptr;
   if (b->graph.exec) {
     HIP_TRY(hipGraphExecDestroy(b->graph.exec));

@@ -29,6 +29,7 @@ struct SolveState {
   int pending;     // a candidate awaits its decision
   int redo;        // the speculative first sweep must be redone
   int bad;         // set-up: a face coefficient given to gmg_setup is not finite
+  int coarse_sweeps;  // sweeps of the coarsest level in the last V-cycle's tail
   double omega_spec;  // omega of the next cycle if the candidate is accepted
   double scr[4];   // scratch for one-off reductions (gmg_residual)
   double hist[GMG_MAX_HISTORY];

@@ -610,6 +610,7 @@ namespace {
 constexpr int kMaxLevels = 32;
 constexpr int kPairTYDefault = 16;  // tile rows of the two-sweep pass by default
 constexpr int kTailMaxCells = 32768;
+constexpr long long kTailGlobalCells = 1LL << 20;  // coarsest level run by the tail from global memory
 constexpr int kResChunk = 16;  // z-planes per block in the norm reductions
 
 struct Level {
@@ -701,6 +702,7 @@ struct gmg_handle {
   int nlev;
   Level lev[kMaxLevels];
   int tail;      // first level cycled by k_tail (nlev: none)
+  int tail_global;  // 1: the tail is the coarsest level alone, in global memory
   void* L0x;     // exact FP64 level-0 faces (dtype F64 with F32 cycles)
   void* w[3];    // level-0 work iterates (cycle dtype); the caller's x is the fourth
   double* spec_part;  // first-sweep residual partials of the deferred decision
@@ -827,6 +829,33 @@ static void launch_pair(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd,
                            kchunk, &h->st->omega, done);
     };
     if (ty == 16)
+      go(std::integral_constant<int, 16>{});
+    else
+      go(std::integral_constant<int, 8>{});
+  }
+}
+
+// Workgroups of level l's two-sweep pass launch.
+static long long pass_blocks(const Level& lv) {
+  return (long long)((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + lv.pair_ty - 1) / lv.pair_ty) *
+         ((lv.g.nz + lv.pair_kc - 1) / lv.pair_kc);
+}
+
+// The deferred decision's first pass of level l (no correction): X[rd] =
+// sweep(sweep(X[rs])) with the input-residual partials, omega and gate of o.
+template <typename T, typename TL>
+static void launch_pair_opt(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd,
+                            const T* sigma, const int* done, const SweepOpt& o) {
+  if constexpr (std::is_same<T, float>::value) {
+    const Level& lv = h->lev[l];
+    auto go = [&](auto tyc) {
+      constexpr int TY = decltype(tyc)::value;
+      hipLaunchKernelGGL((k_rb_sweep2_res<T, TL, TY>), dim3(pass_blocks(lv)),
+                         dim3(S2Cfg<TY>::NTB), 0, h->s, lv.g, X, rs, rd, sigma, (const TL*)lv.L,
+                         lv.active, lv.pair_kc, o.omega ? o.omega : &h->st->omega, done,
+                         o.res_part, o.gate);
+    };
+    if (lv.pair_ty == 16)
       go(std::integral_constant<int, 16>{});
     else
       go(std::integral_constant<int, 8>{});
@@ -972,12 +1001,17 @@ static int enq_pcg_smooth(gmg_handle* h, int l, const Roles<T>& X, int rs, int r
 
 // Levels lt .. nlev-1 in one single-workgroup launch (gmg_tail.h).
 template <typename T, typename TL>
-static void enq_tail(gmg_handle* h, int lt, const int* done) {
+static TailArgs<T, TL> tail_args(gmg_handle* h, int lt, const int* done, int* lds_bytes) {
   TailArgs<T, TL> a{};
   a.nl = h->nlev - lt;
   a.nu_pre = h->p.nu_pre;
   a.nu_post = h->p.nu_post;
   a.nu_coarse = h->p.nu_coarse;
+  a.coarse_rtol = h->p.coarse_rtol;
+  a.coarse_max = h->p.coarse_max;
+  a.omega = &h->st->omega;
+  a.done = done;
+  a.sweeps = &h->st->coarse_sweeps;
   int off = 0;
   for (int q = 0; q < a.nl; ++q) {
     const Level& lv = h->lev[lt + q];
@@ -990,6 +1024,7 @@ static void enq_tail(gmg_handle* h, int lt, const int* done) {
     t.cx = lv.c[0] ? lv.c[0] : 1;
     t.cy = lv.c[1] ? lv.c[1] : 1;
     t.cz = lv.c[2] ? lv.c[2] : 1;
+    if (h->tail_global) continue;
     const long long n = lv.g.n;
     t.ox = off;
     t.os = t.ox + tail_round16(n * (long long)sizeof(T));
@@ -997,26 +1032,42 @@ static void enq_tail(gmg_handle* h, int lt, const int* done) {
     t.oa = t.oL + tail_round16(3 * n * (long long)sizeof(TL));
     off = t.oa + tail_round16(n);
   }
-  hipLaunchKernelGGL((k_tail<T, TL>), dim3(1), dim3(kTailThreads), off, h->s, a, &h->st->omega,
-                     done);
+  *lds_bytes = off;
+  return a;
+}
+
+template <typename T, typename TL>
+static void enq_tail(gmg_handle* h, int lt, const int* done) {
+  int off = 0;
+  const TailArgs<T, TL> a = tail_args<T, TL>(h, lt, done, &off);
+  if (h->tail_global)
+    hipLaunchKernelGGL((k_tail<T, TL, true>), dim3(1), dim3(kTailThreads), 0, h->s, a);
+  else
+    hipLaunchKernelGGL((k_tail<T, TL, false>), dim3(1), dim3(kTailThreads), off, h->s, a);
 }
 
 // First level of the tail: the first level >= 1 from which every level has
 // at most tail_cells cells and all of them fit the tail's LDS budget and
-// level count (nlev: no tail).  Also lifts the kernel's dynamic-LDS limit.
+// level count.  Failing that, a hierarchy of two or more levels with the
+// red-black smoother runs its coarsest level alone through the tail in
+// global memory (tail_global) if it has at most kTailGlobalCells cells;
+// otherwise nlev (no tail).  Also lifts the kernel's dynamic-LDS limit.
 template <typename T, typename TL>
 static int plan_tail(gmg_handle* h) {
-  if (h->p.smoother == GMG_SMOOTH_PCG) return h->nlev;
+  h->tail_global = 0;
+  if (h->p.smoother == GMG_SMOOTH_PCG || h->nlev < 2) return h->nlev;
   for (int l = 1; l < h->nlev; ++l) {
     if (h->lev[l].g.n > h->p.tail_cells || h->nlev - l > kTailMax ||
         tail_bytes<T, TL>(h, l) > kTailLds)
       continue;
-    if (hipFuncSetAttribute((const void*)k_tail<T, TL>,
+    if (hipFuncSetAttribute((const void*)k_tail<T, TL, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kTailLds) != hipSuccess)
-      return h->nlev;
+      break;
     return l;
   }
-  return h->nlev;
+  if (h->lev[h->nlev - 1].g.n > kTailGlobalCells) return h->nlev;
+  h->tail_global = 1;
+  return h->nlev - 1;
 }
 
 // Deferred decision of gmg_solve (see k_spec_finish): the cycle's first
@@ -1026,6 +1077,7 @@ static int plan_tail(gmg_handle* h) {
 struct SpecPlan {
   double* part;
   long long np;
+  bool pass;  // the first smoothing step is a two-sweep pass
 };
 
 // V-cycle from level 0.  X0 is the level-0 role-0 buffer (with `sel`, the
@@ -1048,19 +1100,41 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     int r = 0;
     const int nsw = coarsest ? p.nu_coarse : p.nu_pre;
     if (l == 0 && sp) {
+      // the first smoothing step (a two-sweep pass where level 0 uses them,
+      // else one sweep) reads the candidate (role 1) with the speculative
+      // omega and leaves its input's residual partials; the decision on the
+      // previous cycle follows, and a gated step redoes it from the accepted
+      // iterate (role 0) when that decision differs from the speculation
       SweepOpt first;
       first.res_part = sp->part;
       first.omega = &h->st->omega_spec;
-      enq_sweep<T, TL>(h, 0, X, 1, 2, sg, nullptr, done, first);
-      hipLaunchKernelGGL(k_spec_finish, dim3(1), dim3(256), 0, h->s, sp->part, sp->np, h->st,
-                         h->rule);
       SweepOpt again;
       again.gate = &h->st->redo;
-      enq_sweep<T, TL>(h, 0, X, 0, 2, sg, nullptr, done, again);
+      int s = 0;
+      if (sp->pass) {
+        launch_pair_opt<T, TL>(h, 0, X, 1, 2, sg, done, first);
+        hipLaunchKernelGGL(k_spec_finish, dim3(1), dim3(256), 0, h->s, sp->part, sp->np, h->st,
+                           h->rule);
+        launch_pair_opt<T, TL>(h, 0, X, 0, 2, sg, done, again);
+        s = 2;
+      } else {
+        enq_sweep<T, TL>(h, 0, X, 1, 2, sg, nullptr, done, first);
+        hipLaunchKernelGGL(k_spec_finish, dim3(1), dim3(256), 0, h->s, sp->part, sp->np, h->st,
+                           h->rule);
+        enq_sweep<T, TL>(h, 0, X, 0, 2, sg, nullptr, done, again);
+        s = 1;
+      }
       r = 2;
-      for (int s = 1; s < nsw; ++s) {
+      while (s < nsw) {  // work roles 2 <-> 3
         const int rd = (r == 2) ? 3 : 2;
-        enq_sweep<T, TL>(h, 0, X, r, rd, sg, nullptr, done);
+        if (nsw - s >= 2 && h->lev[0].pair_kc > 0) {
+          launch_pair<T, TL>(h, 0, X, r, rd, sg, nullptr, done, h->lev[0].pair_ty,
+                             h->lev[0].pair_kc);
+          s += 2;
+        } else {
+          enq_sweep<T, TL>(h, 0, X, r, rd, sg, nullptr, done);
+          s += 1;
+        }
         r = rd;
       }
     } else if (pcg) {
@@ -1088,9 +1162,16 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     int r = role[l];
     if (l == 0 && sp) {  // work roles 2 <-> 3, the last step writes the candidate role 1
       if (p.nu_post > 0) {
-        for (int s = 0; s < p.nu_post; ++s) {
-          const int rd = (s == p.nu_post - 1) ? 1 : ((r == 2) ? 3 : 2);
-          enq_sweep<T, TL>(h, 0, X, r, rd, sg, s == 0 ? xc : nullptr, done);
+        for (int s = 0; s < p.nu_post;) {
+          const bool pass = p.nu_post - s >= 2 && lv.pair_kc > 0;
+          const int step = pass ? 2 : 1;
+          const int rd = (s + step == p.nu_post) ? 1 : ((r == 2) ? 3 : 2);
+          if (pass)
+            launch_pair<T, TL>(h, 0, X, r, rd, sg, s == 0 ? xc : nullptr, done, lv.pair_ty,
+                               lv.pair_kc);
+          else
+            enq_sweep<T, TL>(h, 0, X, r, rd, sg, s == 0 ? xc : nullptr, done);
+          s += step;
           r = rd;
         }
       } else {
@@ -1181,6 +1262,10 @@ static gmg_status validate(const gmg_params* p) {
     return fail(GMG_EINVAL, "bad sweep counts");
   if (p->tail_cells < 0 || p->tail_cells > kTailMaxCells)
     return fail(GMG_EINVAL, "tail_cells must be in [0, 32768]");
+  if (!(p->coarse_rtol >= 0.0 && p->coarse_rtol < 1.0))
+    return fail(GMG_EINVAL, "coarse_rtol must be in [0, 1)");
+  if (p->coarse_rtol > 0.0 && (p->coarse_max < 1 || p->coarse_max > 4096))
+    return fail(GMG_EINVAL, "coarse_max must be in [1, 4096]");
   if (p->smoother != GMG_SMOOTH_RBGS && p->smoother != GMG_SMOOTH_PCG)
     return fail(GMG_EINVAL, "smoother must be GMG_SMOOTH_RBGS or GMG_SMOOTH_PCG");
   if (p->deferred_norm != 0 && p->deferred_norm != 1)
@@ -1247,6 +1332,28 @@ static void enq_build_levels(gmg_handle* h) {
     hipLaunchKernelGGL((k_active<TL>), cell_grid(lv.g), kBlock, 0, h->s, lv.g, (const TL*)lv.L,
                        lv.active);
   }
+}
+
+// Level-0 faces from the caller's L (and the exact FP64 copy of a
+// refinement handle), then every coarser level's faces and active mask.
+static gmg_status enq_load_faces(gmg_handle* h, const void* L) {
+  const gmg_params* p = &h->p;
+  void* L0 = h->lev[0].L;
+  if (p->dtype == GMG_F64) {
+    if (p->l_storage == GMG_F64) enq_copy_faces<double, double>(h, L, L0);
+    else if (p->l_storage == GMG_BF16) enq_copy_faces<double, uint16_t>(h, L, L0);
+    else enq_copy_faces<double, float>(h, L, L0);
+    if (h->L0x) enq_copy_faces<double, double>(h, L, h->L0x);
+  } else {
+    if (p->l_storage == GMG_BF16) enq_copy_faces<float, uint16_t>(h, L, L0);
+    else enq_copy_faces<float, float>(h, L, L0);
+  }
+  HIP_TRY(hipGetLastError());
+  if (p->l_storage == GMG_F64) enq_build_levels<double>(h);
+  else if (p->l_storage == GMG_BF16) enq_build_levels<uint16_t>(h);
+  else enq_build_levels<float>(h);
+  HIP_TRY(hipGetLastError());
+  return GMG_OK;
 }
 
 static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, gmg_handle* h) {
@@ -1331,32 +1438,21 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
   std::memset(h->hst, 0, sizeof(SolveState));
   h->hst->omega = p->omega0;
   HIP_TRY(hipMemcpyAsync(h->st, h->hst, sizeof(SolveState), hipMemcpyHostToDevice, h->s));
-  // level-0 faces
-  void* L0 = h->lev[0].L;
-  if (p->dtype == GMG_F64) {
-    if (p->l_storage == GMG_F64) enq_copy_faces<double, double>(h, L, L0);
-    else if (p->l_storage == GMG_BF16) enq_copy_faces<double, uint16_t>(h, L, L0);
-    else enq_copy_faces<double, float>(h, L, L0);
-    if (p->cycle_dtype == GMG_F32) {
-      const long long n0 = h->lev[0].g.n;
-      HIP_TRY(hipMalloc(&h->L0x, 3 * n0 * sizeof(double)));
-      enq_copy_faces<double, double>(h, L, h->L0x);
-      HIP_TRY(hipMalloc(&h->ir, sizeof(IRState)));
-      HIP_TRY(hipHostMalloc((void**)&h->hir, sizeof(IRState), hipHostMallocDefault));
-      HIP_TRY(hipMalloc(&h->r64, n0 * sizeof(double)));
-      HIP_TRY(hipMalloc(&h->b32, n0 * sizeof(float)));
-      HIP_TRY(hipMalloc(&h->e32, n0 * sizeof(float)));
-    }
-  } else {
-    if (p->l_storage == GMG_BF16) enq_copy_faces<float, uint16_t>(h, L, L0);
-    else enq_copy_faces<float, float>(h, L, L0);
+  if (p->dtype == GMG_F64 && p->cycle_dtype == GMG_F32) {
+    const long long n0 = h->lev[0].g.n;
+    HIP_TRY(hipMalloc(&h->L0x, 3 * n0 * sizeof(double)));
+    HIP_TRY(hipMalloc(&h->ir, sizeof(IRState)));
+    HIP_TRY(hipHostMalloc((void**)&h->hir, sizeof(IRState), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&h->r64, n0 * sizeof(double)));
+    HIP_TRY(hipMalloc(&h->b32, n0 * sizeof(float)));
+    HIP_TRY(hipMalloc(&h->e32, n0 * sizeof(float)));
   }
-  HIP_TRY(hipGetLastError());
-  if (p->l_storage == GMG_F64) enq_build_levels<double>(h);
-  else if (p->l_storage == GMG_BF16) enq_build_levels<uint16_t>(h);
-  else enq_build_levels<float>(h);
-  HIP_TRY(hipGetLastError());
+  GMG_TRY(enq_load_faces(h, L));
   DISPATCH_CYCLE(h, { h->tail = plan_tail<T, TL>(h); });
+  if (p->coarse_rtol > 0.0 && p->smoother == GMG_SMOOTH_RBGS && h->nlev >= 2 &&
+      h->tail == h->nlev)
+    return fail(GMG_ESHAPE, "the coarsest-level rule (coarse_rtol > 0) needs a coarsest level of "
+                            "at most 2^20 cells; set coarse_rtol = 0 for fixed sweeps");
   if (p->smoother == GMG_SMOOTH_PCG) DISPATCH_CYCLE(h, { GMG_TRY((ensure_pcg<T, TL>(h, h->nlev))); });
   HIP_TRY(hipMemcpyAsync(&h->hst->bad, &h->st->bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
   HIP_TRY(hipStreamSynchronize(h->s));
@@ -1407,19 +1503,27 @@ static gmg_status captured(gmg_handle* h, CapturedSeq& cs, const void* k0, const
   return GMG_OK;
 }
 
+// Whether the deferred decision's first smoothing step is a two-sweep pass.
+static bool spec_pass(const gmg_handle* h) {
+  return h->p.cycle_dtype == GMG_F32 && h->p.nu_pre >= 2 && h->lev[0].pair_kc > 0;
+}
+
 // Whether gmg_solve defers each cycle's decision to the next cycle's first
-// sweep (red-black smoother, at least one pre-sweep and two levels).
+// smoothing step (red-black smoother, at least one pre-sweep and two levels;
+// the split sweep cannot leave partials).
 static bool spec_ok(const gmg_handle* h) {
   return h->p.deferred_norm && h->p.smoother == GMG_SMOOTH_RBGS && h->p.nu_pre >= 1 &&
-         h->nlev >= 2 && h->w[2] && h->spec_part && h->lev[0].ty != 1;
+         h->nlev >= 2 && h->w[2] && h->spec_part && (spec_pass(h) || h->lev[0].ty != 1);
 }
 
 template <typename T, typename TL>
 static gmg_status enq_solve_cycle(gmg_handle* h, T* xa, const T* sigma) {
   const Level& lv = h->lev[0];
   const long long np = nblocks(red_grid(lv.g));
-  if (spec_ok(h)) {  // the cycle's norm is taken by the next cycle's first sweep
-    const SpecPlan sp{h->spec_part, sweep_blocks(lv, sizeof(T) == 8 ? 4 : lv.ty)};
+  if (spec_ok(h)) {  // the cycle's norm is taken by the next cycle's first smoothing step
+    const bool pass = spec_pass(h);
+    const SpecPlan sp{h->spec_part,
+                      pass ? pass_blocks(lv) : sweep_blocks(lv, sizeof(T) == 8 ? 4 : lv.ty), pass};
     const Roles<T> XM{{xa, (T*)h->w[0], (T*)h->w[1], (T*)h->w[2]}, nullptr, h->st->map};
     enq_vcycle<T, TL>(h, xa, nullptr, sigma, &h->st->done, &sp, &XM);
     HIP_TRY(hipGetLastError());
@@ -1643,6 +1747,8 @@ gmg_status gmg_default_params(gmg_params* p) {
   p->omega_max = 1.0;
   p->theta_dec = 0.5;
   p->theta_inc = 1.2;
+  p->coarse_rtol = 0.1;
+  p->coarse_max = 64;
   return GMG_OK;
 }
 
@@ -1660,6 +1766,26 @@ gmg_status gmg_setup(const gmg_params* p, const void* L, void* stream, gmg_handl
     return s;
   }
   *out = h;
+  return GMG_OK;
+}
+
+gmg_status gmg_update_faces(gmg_handle* h, const void* L) {
+  if (!h || !L) return fail(GMG_EINVAL, "NULL argument");
+  h->hst->bad = 0;
+  HIP_TRY(hipMemcpyAsync(&h->st->bad, &h->hst->bad, sizeof(int), hipMemcpyHostToDevice, h->s));
+  GMG_TRY(enq_load_faces(h, L));
+  for (int l = 0; l < h->nlev; ++l) {  // the PCG preconditioner diag(-A), where it exists
+    if (!h->pcg[l][5]) continue;
+    const Level& lv = h->lev[l];
+    DISPATCH_CYCLE(h, {
+      hipLaunchKernelGGL((k_pcg_diag<T, TL>), cell_grid(lv.g), kBlock, 0, h->s, lv.g,
+                         (const TL*)lv.L, (T*)h->pcg[l][5]);
+    });
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&h->hst->bad, &h->st->bad, sizeof(int), hipMemcpyDeviceToHost, h->s));
+  HIP_TRY(hipStreamSynchronize(h->s));
+  if (h->hst->bad) return fail(GMG_EINVAL, "a face coefficient is not finite (NaN or Inf)");
   return GMG_OK;
 }
 
@@ -1827,6 +1953,14 @@ gmg_status gmg_prolong_correct(gmg_handle* h, int32_t level, const void* x_c, vo
 gmg_status gmg_get_omega(gmg_handle* h, double* omega) {
   if (!h || !omega) return fail(GMG_EINVAL, "NULL argument");
   HIP_TRY(hipMemcpyAsync(omega, &h->st->omega, sizeof(double), hipMemcpyDeviceToHost, h->s));
+  HIP_TRY(hipStreamSynchronize(h->s));
+  return GMG_OK;
+}
+
+gmg_status gmg_coarse_sweeps(gmg_handle* h, int32_t* sweeps) {
+  if (!h || !sweeps) return fail(GMG_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(sweeps, &h->st->coarse_sweeps, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         h->s));
   HIP_TRY(hipStreamSynchronize(h->s));
   return GMG_OK;
 }

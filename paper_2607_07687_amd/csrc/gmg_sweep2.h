@@ -208,12 +208,35 @@ __device__ __forceinline__ T pick(const T (&v)[2], int e) {
   return e ? v[1] : v[0];
 }
 
+// Residual sigma - A S of element e of a pair on a completed plane (x: the
+// pair's S values xc and its neighbours; faces low and high per direction),
+// summed in the order of stencil_Ax (per direction the high-face term, then
+// the low-face one); `act` is D != 0.
+template <typename T>
+__device__ __forceinline__ T s2_residual(T xc, T xe, T xw, T xn, T xs, T xt, T xb, T lxm, T lxp,
+                                         T lym, T lyp, T lzm, T lzp, T sg, bool& act) {
+  T ax = T(0), d = T(0);
+  ax += lxp * (xe - xc);
+  ax += lxm * (xw - xc);
+  d += lxm + lxp;
+  ax += lyp * (xn - xc);
+  ax += lym * (xs - xc);
+  d += lym + lyp;
+  ax += lzp * (xt - xc);
+  ax += lzm * (xb - xc);
+  d += lzm + lzp;
+  act = -d != T(0);
+  return sg - ax;
+}
+
 // Sweeps 1 and 2 of the tile with origin (i0, j0) over the z-planes [k0, k1)
-// (PROL: with the coarse correction folded into S).
-template <typename T, typename TL, int TY, bool PROL>
-__device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T, TL>& a,
-                                               T* __restrict__ W, int i0, int j0, int k0,
-                                               int k1, T omega) {
+// (PROL: with the coarse correction folded into S).  RES: also the sum of the
+// squared residuals of S over the tile's own active cells and planes (the
+// norm of the pass's input), returned to thread 0 (0 elsewhere).
+template <typename T, typename TL, int TY, bool PROL, bool RES = false>
+__device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T, TL>& a,
+                                                 T* __restrict__ W, int i0, int j0, int k0,
+                                                 int k1, T omega) {
   using C = S2Cfg<TY>;
   const Geom& g = a.g;
   const int t = threadIdx.x;
@@ -261,6 +284,7 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
   // it is the parity of r: hw with SPLIT)
   const int par = C::SPLIT ? hw : (xa + y) & 1;
 
+  double racc = 0.0;               // RES: squared input residuals of own cells
   S2Plane<T> P0, P1, P2, P3, P4;  // planes k .. k+4 at step k
   T r1a = T(0), r1b = T(0);       // sweep-1 red of planes k+1, k+2
   T b1a = T(0), b1b = T(0);       // sweep-1 black of planes k, k+1
@@ -305,6 +329,22 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     P3.lxh = sm.lx0[q][R][ce];
     P3.lyh[0] = sm.ly[q][RN][cs];
     P3.lyh[1] = sm.ly[q][RN][cs + 1];
+    if constexpr (RES) {
+      // plane k+3 is complete: the residual of S on both cells of the pair
+      // (own cells of the tile on the chunk's own planes), from the values
+      // stage 1 reads
+      if (out_ok && k + 3 >= k0 && k + 3 < k1) {
+        bool a0, a1;
+        const T q0 = s2_residual<T>(P3.s[0], P3.s[1], sm.s[q][R][cs - 1], sm.s[q][RN][cs],
+                                    sm.s[q][RS][cs], P4.s[0], P2.s[0], P3.lx[0], P3.lx[1],
+                                    P3.ly[0], P3.lyh[0], P3.lz[0], P4.lz[0], P3.sg[0], a0);
+        const T q1 = s2_residual<T>(P3.s[1], sm.s[q][R][cs + 2], P3.s[0], sm.s[q][RN][cs + 1],
+                                    sm.s[q][RS][cs + 1], P4.s[1], P2.s[1], P3.lx[1], P3.lxh,
+                                    P3.ly[1], P3.lyh[1], P3.lz[1], P4.lz[1], P3.sg[1], a1);
+        if (a0) racc += (double)q0 * (double)q0;
+        if (a1) racc += (double)q1 * (double)q1;
+      }
+    }
     T r1n = T(0), b1n = T(0), r2n = T(0);
     // The four stages of step k all update element e = 1 - (par + k) mod 2
     // of their pairs: the red one on planes k+3 and k+1, the black one on
@@ -427,6 +467,8 @@ __device__ __forceinline__ void rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T
     }
     for (; k < k1; ++k) step(k, la, la);
   }
+  if constexpr (RES) return block_sum(racc, threadIdx.x, C::NTB);
+  return 0.0;
 }
 
 }  // namespace gmg
@@ -447,4 +489,26 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
   const int k0 = tz * kchunk;
   gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0,
                                  min(g.nz, k0 + kchunk), (T)(*omega_p));
+}
+
+// The first pass of a cycle under the deferred decision: the same pass
+// without correction, which also leaves one FP64 partial of ||sigma - A S||^2
+// (its input's residual over the active cells) per workgroup, in dispatch
+// order, in res_part; with a gate it runs only when *gate != 0.
+template <typename T, typename TL, int TY>
+__global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
+    gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
+    const TL* __restrict__ L, const uint8_t* __restrict__ active, int kchunk,
+    const double* omega_p, const int* done, double* res_part, const int* gate) {
+  if (gmg::stopped(done)) return;
+  if (gate != nullptr && *gate == 0) return;
+  __shared__ gmg::S2Smem<T, TY> sm;
+  gmg::S2Args<T, TL> a{g, X.get(rs), sigma, L, X.get(rs), active, g, 1, 1, 1, 0};
+  const int ntx = (g.nx + gmg::S2_TX - 1) / gmg::S2_TX, nty = (g.ny + TY - 1) / TY;
+  const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int k0 = tz * kchunk;
+  const double s = gmg::rb_sweep2_tile<T, TL, TY, false, true>(
+      sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0, min(g.nz, k0 + kchunk), (T)(*omega_p));
+  if (res_part != nullptr && threadIdx.x == 0) res_part[blockIdx.x] = s;
 }

@@ -4,17 +4,30 @@
 // 16^3 grid costs about as much as one on 128^3, and a V-cycle visits the
 // small levels with a dozen launches.  Here one workgroup of kTailThreads
 // threads runs everything from the first tail level down: pre-sweeps,
-// residual restriction, the coarsest sweeps, prolongation + correction and
-// post-sweeps, with workgroup barriers in place of kernel boundaries.  All
-// tail levels (x, sigma, faces, active mask) are held in LDS for the whole
-// launch; x and sigma go back to global memory at the end.
+// residual restriction, the coarsest-level smoothing, prolongation +
+// correction and post-sweeps, with workgroup barriers in place of kernel
+// boundaries.  Tail levels (x, sigma, faces, active mask) are held in LDS for
+// the whole launch and x and sigma go back to global memory at the end; a
+// level too large for LDS (only ever the coarsest one, alone) is worked on
+// in global memory by the same code.
+//
+// The coarsest level is smoothed either by nu_coarse sweeps or, with
+// coarse_rtol > 0, until its residual norm has fallen to coarse_rtol times its
+// value on entry (at least one sweep, at most coarse_max): the paper's
+// anisotropic coarsening (Sec. 3.2) reaches a coarsest grid on which the
+// smoother alone removes the lowest wavenumbers, and this rule lets it do
+// so.  The rule first removes the mean of the level's right-hand side over
+// its active cells (zero in exact arithmetic on these singular levels; what
+// rounding leaves there no sweep can remove), and its norms are FP64 sums in
+// a fixed order.
 //
 // Arithmetic is that of the grid-wide kernels: the same relax_cell per cell,
 // colour by colour (a colour's cells depend only on the other colour, so an
 // in-place half-sweep equals the simultaneous one), the residual from
 // stencil_Ax, and the restriction sum of each coarse cell taken in the order
 // of the tiled restriction kernel (z first per fine column, then x-pairs,
-// then y-pairs).
+// then y-pairs).  With one workgroup per problem the same body serves a batch
+// of independent problems (k_tail_batch).
 #pragma once
 
 #include "gmg_device.h"
@@ -41,6 +54,11 @@ struct TailArgs {
   TailLevel<T, TL> lv[kTailMax];
   int nl;  // levels in the tail; the last is the coarsest
   int nu_pre, nu_post, nu_coarse;
+  double coarse_rtol;  // > 0: the coarsest-level stopping rule (see above)
+  int coarse_max;
+  const double* omega;  // relaxation factor (device)
+  const int* done;      // solve finished: the launch is a no-op (may be NULL)
+  int* sweeps;          // receives the coarsest level's sweep count (may be NULL)
 };
 
 // LDS bytes of one level: x, sigma (T), three faces (TL), mask, each part
@@ -70,8 +88,14 @@ struct TailView {  // one level in LDS
   uint8_t* a;
 };
 
-template <typename T, typename TL>
+// GLOBAL: the level is used in place in global memory; otherwise it lives in
+// LDS at its offsets.  A compile-time choice, so that the LDS pointers are
+// known to be LDS pointers and the accesses become LDS instructions.
+template <typename T, typename TL, bool GLOBAL>
 __device__ __forceinline__ TailView<T, TL> tail_view(char* lds, const TailLevel<T, TL>& v) {
+  if constexpr (GLOBAL)
+    return TailView<T, TL>{v.g, v.x, v.sigma, const_cast<TL*>(v.L),
+                           const_cast<uint8_t*>(v.active)};
   return TailView<T, TL>{v.g, (T*)(lds + v.ox), (T*)(lds + v.os), (TL*)(lds + v.oL),
                          (uint8_t*)(lds + v.oa)};
 }
@@ -186,6 +210,152 @@ __device__ __forceinline__ void tail_prolong(const TailView<T, TL>& f, const Tai
   __syncthreads();
 }
 
+// The coarsest level is smoothed by the workgroup's first wavefront alone:
+// its few cells do not fill more, and between two half-sweeps a wavefront
+// needs only its own memory operations completed (a fence, no barrier).
+constexpr int kWave = 64;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Half-sweep of colour `colour` by one wavefront, in place (tail_half_sweep
+// with a wavefront's stride).
+template <typename T, typename TL>
+__device__ __forceinline__ void wave_half_sweep(const TailView<T, TL>& v, int colour, T omega,
+                                                int lane) {
+  const Geom& g = v.g;
+  const int nx = g.nx, ny = g.ny;
+  const int sy = nx, sz = nx * ny, n = sz * g.nz;
+  const int pr = (nx + 1) >> 1;
+  const int np = pr * ny * g.nz;
+  const float rpr = 1.0f / (float)pr, rny = 1.0f / (float)ny;
+  const TL* Lx = v.L;
+  const TL* Ly = v.L + n;
+  const TL* Lz = v.L + 2 * n;
+  T* x = v.x;
+  for (int p = lane; p < np; p += kWave) {
+    const int row = tail_div(p, pr, rpr);
+    const int m = p - row * pr;
+    const int k = tail_div(row, ny, rny);
+    const int j = row - k * ny;
+    const int i = 2 * m + ((j + k + colour) & 1);
+    if (i >= nx) continue;
+    const int q = row * nx + i;
+    const bool xe_in = i + 1 < nx || g.px, xw_in = i > 0 || g.px;
+    const bool yn_in = j + 1 < ny || g.py, ys_in = j > 0 || g.py;
+    const bool zt_in = k + 1 < g.nz || g.pz, zb_in = k > 0 || g.pz;
+    const int qe = (i + 1 < nx) ? q + 1 : q - (nx - 1);
+    const int qw = (i > 0) ? q - 1 : q + (nx - 1);
+    const int qn = (j + 1 < ny) ? q + sy : q - (ny - 1) * sy;
+    const int qs = (j > 0) ? q - sy : q + (ny - 1) * sy;
+    const int qt = (k + 1 < g.nz) ? q + sz : q - (g.nz - 1) * sz;
+    const int qb = (k > 0) ? q - sz : q + (g.nz - 1) * sz;
+    x[q] = relax_cell<T>(x[q], xe_in ? x[qe] : T(0), xw_in ? x[qw] : T(0), yn_in ? x[qn] : T(0),
+                         ys_in ? x[qs] : T(0), zt_in ? x[qt] : T(0), zb_in ? x[qb] : T(0),
+                         ldL<T>(Lx, q), xe_in ? ldL<T>(Lx, qe) : T(0), ldL<T>(Ly, q),
+                         yn_in ? ldL<T>(Ly, qn) : T(0), ldL<T>(Lz, q),
+                         zt_in ? ldL<T>(Lz, qt) : T(0), v.s[q], omega);
+  }
+  wave_sync();
+}
+
+// Sum over the wavefront, the same fixed order in every lane's result.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Residual of cell q of a tail level (dtype arithmetic); `act` is D != 0.
+template <typename T, typename TL>
+__device__ __forceinline__ T tail_cell_residual(const TailView<T, TL>& v, int q, float rnx,
+                                                float rny, bool& act) {
+  const Geom& g = v.g;
+  const int row = tail_div(q, g.nx, rnx);
+  const int i = q - row * g.nx;
+  const int k = tail_div(row, g.ny, rny);
+  const int j = row - k * g.ny;
+  T D;
+  const T ax = stencil_Ax<T, TL>(g, v.x, v.L, q, i, j, k, v.x[q], D);
+  act = D != T(0);
+  return act ? v.s[q] - ax : T(0);
+}
+
+// ||sigma - A x||_2 over the active cells: FP64 squares of the dtype
+// residuals summed per lane in cell order, then over the wavefront.
+template <typename T, typename TL>
+__device__ __forceinline__ double wave_resnorm(const TailView<T, TL>& v, int lane) {
+  const Geom& g = v.g;
+  const int ncell = (int)g.n;
+  const float rnx = 1.0f / (float)g.nx, rny = 1.0f / (float)g.ny;
+  double s2 = 0.0;
+  for (int q = lane; q < ncell; q += kWave) {
+    bool act;
+    const T r = tail_cell_residual<T, TL>(v, q, rnx, rny, act);
+    if (act) s2 += (double)r * (double)r;
+  }
+  return sqrt(wave_sum(s2));
+}
+
+// sigma -= its mean over the active cells (FP64 sum and mean, the
+// difference rounded once to the dtype).  With walls and periodic
+// directions only, every level is singular (constants are in the null
+// space) and a right-hand side is solvable only with zero mean; the
+// restricted residual has it in exact arithmetic, and this removes what
+// rounding left, which the smoother could not reduce and which would drift
+// the level's iterate along the null space.
+template <typename T, typename TL>
+__device__ __forceinline__ void wave_project(const TailView<T, TL>& v, int lane) {
+  const int ncell = (int)v.g.n;
+  double s = 0.0, c = 0.0;
+  for (int q = lane; q < ncell; q += kWave)
+    if (v.a[q]) {
+      s += (double)v.s[q];
+      c += 1.0;
+    }
+  s = wave_sum(s);
+  c = wave_sum(c);
+  const double mean = c > 0.0 ? s / c : 0.0;
+  for (int q = lane; q < ncell; q += kWave)
+    if (v.a[q]) v.s[q] = (T)((double)v.s[q] - mean);
+  wave_sync();
+}
+
+// Smoothing of the coarsest level: nu_coarse sweeps, or with coarse_rtol > 0
+// the right-hand side projected to zero mean, then sweeps until the residual
+// norm is at most coarse_rtol times its value on entry (at least one sweep,
+// at most coarse_max).  Run by the first
+// wavefront; returns the number of sweeps to every thread.
+template <typename T, typename TL>
+__device__ __forceinline__ int tail_coarsest(const TailView<T, TL>& v, int nu_coarse,
+                                             double coarse_rtol, int coarse_max, T omega,
+                                             int* count) {
+  const int t = threadIdx.x;
+  if (t < kWave) {
+    int n = 0;
+    if (!(coarse_rtol > 0.0)) {
+      for (; n < nu_coarse; ++n) {
+        wave_half_sweep<T, TL>(v, 0, omega, t);
+        wave_half_sweep<T, TL>(v, 1, omega, t);
+      }
+    } else {
+      wave_project<T, TL>(v, t);
+      const double lim = coarse_rtol * wave_resnorm<T, TL>(v, t);
+      while (n < coarse_max) {
+        wave_half_sweep<T, TL>(v, 0, omega, t);
+        wave_half_sweep<T, TL>(v, 1, omega, t);
+        ++n;
+        if (n < coarse_max && wave_resnorm<T, TL>(v, t) <= lim) break;
+      }
+    }
+    if (t == 0) *count = n;
+  }
+  __syncthreads();
+  return *count;
+}
+
 // Copy n elements between global memory and LDS in 16-byte pieces, several
 // in flight per thread (both ends 16-byte aligned), then the remaining bytes.
 template <typename T>
@@ -209,44 +379,67 @@ __device__ __forceinline__ void tail_copy(T* dst, const T* src, int n) {
   for (int b = (n16 << 4) + (int)threadIdx.x; b < nb; b += kTailThreads) d1[b] = s1[b];
 }
 
-template <typename T, typename TL>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T, TL> a, const double* omega_p,
-                                                       const int* done) {
-  if (done != nullptr && *done) return;
-  extern __shared__ __align__(16) char tail_lds[];
-  const T omega = (T)(*omega_p);
+// The whole tail of one problem (see the top of this file).  GLOBAL: the
+// tail is one level (the coarsest), used in place in global memory.
+template <typename T, typename TL, bool GLOBAL>
+__device__ __forceinline__ void tail_run(const TailArgs<T, TL>& a, char* tail_lds) {
+  __shared__ int count;
+  const T omega = (T)(*a.omega);
   const int last = a.nl - 1;
-  // stage every tail level in LDS (x and sigma of the first level come from
-  // the restriction that precedes this launch; deeper levels are produced here)
-  for (int l = 0; l < a.nl; ++l) {
-    const TailLevel<T, TL>& v = a.lv[l];
-    const TailView<T, TL> w = tail_view<T, TL>(tail_lds, v);
-    const int n = (int)v.g.n;
-    tail_copy<TL>(w.L, v.L, 3 * n);
-    tail_copy<uint8_t>(w.a, v.active, n);
-    if (l == 0) {
-      tail_copy<T>(w.x, v.x, n);
-      tail_copy<T>(w.s, v.sigma, n);
+  // stage the levels in LDS (x and sigma of the first level come from the
+  // restriction that precedes this launch; deeper levels are produced here)
+  if constexpr (!GLOBAL) {
+    for (int l = 0; l < a.nl; ++l) {
+      const TailLevel<T, TL>& v = a.lv[l];
+      const TailView<T, TL> w = tail_view<T, TL, false>(tail_lds, v);
+      const int n = (int)v.g.n;
+      tail_copy<TL>(w.L, v.L, 3 * n);
+      tail_copy<uint8_t>(w.a, v.active, n);
+      if (l == 0) {
+        tail_copy<T>(w.x, v.x, n);
+        tail_copy<T>(w.s, v.sigma, n);
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int l = 0; l < last; ++l) {
-    const TailView<T, TL> f = tail_view<T, TL>(tail_lds, a.lv[l]);
+    const TailView<T, TL> f = tail_view<T, TL, GLOBAL>(tail_lds, a.lv[l]);
     tail_sweeps<T, TL>(f, a.nu_pre, omega);
-    tail_restrict<T, TL>(f, a.lv[l], tail_view<T, TL>(tail_lds, a.lv[l + 1]));
+    tail_restrict<T, TL>(f, a.lv[l], tail_view<T, TL, GLOBAL>(tail_lds, a.lv[l + 1]));
   }
-  tail_sweeps<T, TL>(tail_view<T, TL>(tail_lds, a.lv[last]), a.nu_coarse, omega);
+  const int nc = tail_coarsest<T, TL>(tail_view<T, TL, GLOBAL>(tail_lds, a.lv[last]),
+                                      a.nu_coarse, a.coarse_rtol, a.coarse_max, omega, &count);
+  if (a.sweeps && threadIdx.x == 0) *a.sweeps = nc;
   for (int l = last - 1; l >= 0; --l) {
-    const TailView<T, TL> f = tail_view<T, TL>(tail_lds, a.lv[l]);
-    tail_prolong<T, TL>(f, a.lv[l], tail_view<T, TL>(tail_lds, a.lv[l + 1]));
+    const TailView<T, TL> f = tail_view<T, TL, GLOBAL>(tail_lds, a.lv[l]);
+    tail_prolong<T, TL>(f, a.lv[l], tail_view<T, TL, GLOBAL>(tail_lds, a.lv[l + 1]));
     tail_sweeps<T, TL>(f, a.nu_post, omega);
   }
-  for (int l = 0; l < a.nl; ++l) {
-    const TailLevel<T, TL>& v = a.lv[l];
-    const TailView<T, TL> w = tail_view<T, TL>(tail_lds, v);
-    tail_copy<T>(v.x, w.x, (int)v.g.n);
-    tail_copy<T>(v.sigma, w.s, (int)v.g.n);
+  if constexpr (!GLOBAL) {
+    for (int l = 0; l < a.nl; ++l) {
+      const TailLevel<T, TL>& v = a.lv[l];
+      const TailView<T, TL> w = tail_view<T, TL, false>(tail_lds, v);
+      tail_copy<T>(v.x, w.x, (int)v.g.n);
+      tail_copy<T>(v.sigma, w.s, (int)v.g.n);
+    }
   }
+}
+
+template <typename T, typename TL, bool GLOBAL>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T, TL> a) {
+  if (a.done != nullptr && *a.done) return;
+  extern __shared__ __align__(16) char tail_lds[];
+  tail_run<T, TL, GLOBAL>(a, tail_lds);
+}
+
+// One workgroup per problem of a batch, each with its own tail.
+template <typename T, typename TL, bool GLOBAL>
+__global__ __launch_bounds__(kTailThreads) void k_tail_batch(
+    const TailArgs<T, TL>* __restrict__ args) {
+  const TailArgs<T, TL>& a = args[blockIdx.x];
+  if (a.done != nullptr && *a.done) return;
+  extern __shared__ __align__(16) char tail_lds[];
+  tail_run<T, TL, GLOBAL>(a, tail_lds);
 }
 
 }  // namespace gmg

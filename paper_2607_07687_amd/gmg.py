@@ -35,7 +35,8 @@ class gmg_params(ctypes.Structure):
                 ("smoother", ctypes.c_int32), ("deferred_norm", ctypes.c_int32),
                 ("pair_sweeps", ctypes.c_int32), ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
-                ("theta_inc", ctypes.c_double)]
+                ("theta_inc", ctypes.c_double), ("coarse_rtol", ctypes.c_double),
+                ("coarse_max", ctypes.c_int32)]
 
 
 class gmg_solve_info(ctypes.Structure):
@@ -84,6 +85,7 @@ _SIGS = [
     ("gmg_setup", ctypes.c_int, [ctypes.POINTER(gmg_params), ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     ("gmg_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("gmg_update_faces", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("gmg_num_levels", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     ("gmg_level_shape", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32),
@@ -103,6 +105,7 @@ _SIGS = [
                                            ctypes.c_void_p, ctypes.c_void_p]),
     ("gmg_get_omega", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     ("gmg_set_omega", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    ("gmg_coarse_sweeps", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     ("gmg_vcycle", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_double)]),
     ("gmg_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -320,6 +323,15 @@ def gmg_setup(params, L, stream=None):
     return h
 
 
+def gmg_update_faces(h, L):
+    """New face coefficients L ([3][nz][ny][nx] tensor in params.dtype) for
+    the handle's hierarchy (same grid)."""
+    if _dtype_code(L) != h.params.dtype:
+        raise TypeError("L dtype does not match params.dtype")
+    Lp = _arr(L, "L", 3 * h.cells(0), _torch_dtype(h.params.dtype), h.device)
+    _check(load().gmg_update_faces(h.ptr, Lp))
+
+
 def gmg_num_levels(h):
     n = ctypes.c_int32()
     _check(load().gmg_num_levels(h.ptr, ctypes.byref(n)))
@@ -388,6 +400,12 @@ def gmg_get_omega(h):
     w = ctypes.c_double()
     _check(load().gmg_get_omega(h.ptr, ctypes.byref(w)))
     return w.value
+
+
+def gmg_coarse_sweeps(h):
+    n = ctypes.c_int32()
+    _check(load().gmg_coarse_sweeps(h.ptr, ctypes.byref(n)))
+    return n.value
 
 
 def gmg_set_omega(h, omega):

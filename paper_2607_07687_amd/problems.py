@@ -25,6 +25,9 @@ immersed bodies make the coefficients heterogeneous, Sec. 3.1):
   (512 x 192 x 192 box, sphere of diameter 32 at x = 128).
 * ``batch_problems``: 64 independent wall-bounded sphere problems of uneven
   sizes.
+* ``moving_body_problem``: one time step of a sequence of pressure problems
+  past an accelerating sphere or cylinder that moves through the box, the
+  time-correlated problems a flow solver hands its pressure solver.
 """
 from __future__ import annotations
 
@@ -313,4 +316,33 @@ def tgv_modes_sphere(n, seed, dmin=8.0, dmax=24.0):
     periodic = (False, False, False)
     L = sphere_faces(n, periodic, centre, radius)
     u = tgv_modes_velocity(n, rng)
+    return L, rhs_from_velocity(L, u, periodic), periodic
+
+
+def moving_body_problem(kind, n, step, dt=0.5, u0=1.0, accel=0.05, x0=None, wave=0.1):
+    """Pressure problem of time step `step` of a body moving through a
+    walled box (time-correlated problems: consecutive steps differ by a
+    fraction of a cell of body motion and a small change of velocity).
+
+    The body (kind 'sphere', diameter n_y / 4, or 'cylinder' along z, same
+    diameter) is centred at x = x0 + u0 t + accel t^2 / 2 (x0 default n_y),
+    mid-height, at t = step * dt.  The face velocity is the body's speed
+    U(t) = u0 + accel t along x plus a Taylor-Green wave of relative
+    amplitude `wave` that travels with the flow (phase U t along x), and
+    sigma is its flux divergence through L with the mean removed
+    (``rhs_from_velocity``), as for the impulsive start.  Returns
+    (L, sigma, periodic)."""
+    periodic = (False, False, False)
+    t = step * dt
+    U = u0 + accel * t
+    xc = (n[1] if x0 is None else x0) + u0 * t + 0.5 * accel * t * t
+    centre = (xc, n[1] / 2, n[2] / 2)
+    axis = None if kind == "sphere" else 2
+    if kind not in ("sphere", "cylinder"):
+        raise ValueError(kind)
+    L = body_faces(n, periodic, centre, n[1] / 8, axis)
+    u = np.zeros_like(L)
+    u[0] = U
+    if wave:
+        u += wave * U * tgv_velocity(n, period=n[1], phase=(-U * t, 0.0, 0.0))
     return L, rhs_from_velocity(L, u, periodic), periodic

@@ -1,9 +1,10 @@
 """Write tests/golden/sphere256_oracle.json: oracle results on the 256^3
 wall-bounded sphere workload (sphere of diameter 64 at the centre, cosine
 band of 2 cells, uniform-random face velocity, seed 1), FP32-rounded inputs,
-faces stored in FP32 on every level, V(2,2), nu_coarse = 4, omega = 1.
+faces stored in FP32 on every level, V(2,2) with the default coarsest-level
+rule (sweeps until the coarsest residual falls by 0.1, at most 64), omega = 1.
 
-Calls only the CPU oracle and the input generators.  Slow (about an hour):
+Calls only the CPU oracle and the input generators.  Takes a few minutes:
 
     python tests/golden/make_sphere256.py [--no-solve]
 

@@ -11,6 +11,8 @@ torch = pytest.importorskip("torch")
 # per-V-cycle tolerances: FP32 runs against the FP64 oracle fed the same
 # rounded inputs, and FP64 runs
 TOL = {"f32": 1e-5, "f64": 1e-11, "bf16": 1e-5}
+# unit roundoff of the iterate's precision
+EPS = {"f32": 2.0 ** -24, "f64": 2.0 ** -53, "bf16": 2.0 ** -24}
 
 
 def require_gpu():
@@ -43,16 +45,29 @@ def rel(a, b):
     return na / nb
 
 
-def assert_close(a, b, tol, what=""):
+def assert_close(a, b, tol, what="", scale=None, eps=0.0):
     """Agreement both norm-wise and element by element:
     ||a - b||_2 <= tol ||b||_2 and max |a - b| <= tol max |b|.  The second
-    bound keeps a few wrong cells from hiding inside a large field's norm."""
+    bound keeps a few wrong cells from hiding inside a large field's norm.
+    When a and b are increments of a field `scale` held in a precision of
+    unit roundoff `eps`, the rounding of that field, 8 eps ||scale|| (and
+    8 eps max |scale|), is allowed on top."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
-    e2 = rel(a, b)
+    d = a - b
+    nb = float(np.linalg.norm(b))
     mb = float(np.abs(b).max()) if b.size else 0.0
-    einf = float(np.abs(a - b).max()) / mb if mb > 0 else float(np.abs(a - b).max(initial=0.0))
-    assert e2 <= tol and einf <= tol, f"{what} rel2 {e2:.3e} relinf {einf:.3e} tol {tol:.1e}"
+    f2 = finf = 0.0
+    if scale is not None:
+        f2 = 8.0 * eps * float(np.linalg.norm(scale))
+        finf = 8.0 * eps * float(np.abs(scale).max())
+    e2n = float(np.linalg.norm(d))
+    einfn = float(np.abs(d).max(initial=0.0))
+    e2 = e2n / nb if nb > 0 else e2n
+    einf = einfn / mb if mb > 0 else einfn
+    ok = e2n <= tol * nb + f2 and einfn <= tol * mb + finf
+    assert ok, (f"{what} rel2 {e2:.3e} relinf {einf:.3e} tol {tol:.1e} "
+                f"(rounding allowance {f2 / max(nb, 1e-300):.1e} / {finf / max(mb, 1e-300):.1e})")
     return max(e2, einf)
 
 

@@ -114,10 +114,22 @@ def test_batch_argument_errors():
     prm = G.gmg_default_params((8, 8, 8), per, G.GMG_F64)  # F64 cycles: not allowed
     with pytest.raises(G.GMGError):
         G.gmg_batch_setup([prm], [dev(L, "f64")])
-    prm = _params(L, per, "f32")
+    # a single-level problem (6^3 walls cannot coarsen) smooths in the
+    # descent and the ascent: nu_coarse must be nu_pre + nu_post
+    L1, _, per1 = P.random_problem((6, 6, 6), (False, False, False), 2)
+    prm = _params(L1, per1, "f32")
     prm.nu_coarse = 3
     with pytest.raises(G.GMGError):
-        G.gmg_batch_setup([prm], [dev(L, "f64")])
+        G.gmg_batch_setup([prm], [dev(L1, "f64")])
+    # with two levels the tail smooths the coarsest level: any nu_coarse
+    prm = _params(L, per, "f32")
+    prm.nu_coarse = 3
+    G.gmg_batch_setup([prm], [dev(L, "f64")]).close()
+    # problems must share the coarsest-level rule
+    p1, p2 = _params(L, per, "f32"), _params(L, per, "f32")
+    p2.coarse_rtol = 0.2
+    with pytest.raises(G.GMGError):
+        G.gmg_batch_setup([p1, p2], [dev(L, "f64"), dev(L, "f64")])
 
 
 def test_batch_autotune_keeps_results_bitwise():

@@ -73,9 +73,9 @@ def _residual_bound(x, s, L, per):
 def test_solve_ir_each_step_matches_oracle(name, make, storage):
     # after m = 1, 2, 3 outer steps from zero: the library's FP64 residual of
     # its own iterate equals the oracle's residual of that same iterate
-    # (within the rounding of an FP64 residual evaluation), and the next
-    # step the library takes from it equals the oracle's one step from it
-    # (FP32 inner cycles against the oracle's FP64 ones: 1e-5)
+    # (within the rounding of an FP64 residual evaluation), and (m = 1, 2)
+    # the next step the library takes from it equals the oracle's one step
+    # from it (FP32 inner cycles against the oracle's FP64 ones: 1e-5)
     require_gpu()
     say(f"ir steps {name} {storage}")
     L, s, per = make()
@@ -100,7 +100,15 @@ def test_solve_ir_each_step_matches_oracle(name, make, storage):
         say(f"  m={m}: |r| {rn:.3e}, max err/bound {float(ratio.max()):.2f}")
         assert np.all(err <= bound)
         assert abs(rn - O.norm2(ro)) <= 1e-10 * O.norm2(ro) + float(np.sqrt((bound ** 2).sum()))
-        # one more step from this iterate on both sides
+        # one more step from this iterate on both sides, while its right-hand
+        # side r / beta is still the residual of the problem: after three
+        # steps these problems are near the FP64 evaluation floor, r is
+        # largely rounding noise, and the inner FP32 solve of a noise
+        # right-hand side meets its stopping and coarsest-level decisions at
+        # near-ties that FP32 and FP64 may take differently
+        if m == 3:
+            say(f"  step after m={m}: residual at the FP64 evaluation floor, not compared")
+            continue
         x1 = x.clone()
         G.gmg_solve_ir(h, x1, sd, rtol=0.0, max_outer=1, **kw)
         one = O.solve_ir(L, per, xm, s, rtol=0.0, max_outer=1, inner_storage=storage, **kw)

@@ -139,14 +139,18 @@ def build_reference(L, periodic, storage, anisotropic=True, max_levels=0):
 
 
 def coarsest_reference(r, x, b, omega, nuc, crtol, counts=None):
-    """crtol = 0: nuc sweeps.  crtol > 0: sweep until the residual norm on
-    the active cells is at most crtol times its value on entry, at least one
-    sweep and at most nuc (the cap)."""
+    """crtol = 0: nuc sweeps.  crtol > 0: remove the mean of b over the
+    active cells, then sweep until the residual norm on the active cells is
+    at most crtol times its value on entry, at least one sweep and at most
+    nuc (the cap)."""
     if crtol <= 0.0:
         return gauss_seidel(r["A"], r["colour"], x, b, omega, nuc)
+    act = r["active"]
+    b = b.copy()
+    b[act] -= sum(b[act]) / int(act.sum())
 
     def rnorm(v):
-        res = np.where(r["active"], b - r["A"] @ v, 0.0)
+        res = np.where(act, b - r["A"] @ v, 0.0)
         return math.sqrt(float(res @ res))
 
     r0 = rnorm(x)
@@ -303,3 +307,48 @@ def test_refinement_step_detects_plausible_mistakes():
     Ab = assemble(levels[0]["L"], per)
     rb = np.where(act, s.ravel() - Ab @ x0, 0.0)
     assert np.abs(rb - r).max() > 1e-6 * np.abs(r).max()
+
+
+def test_single_level_cycle_is_fixed_sweeps_whatever_the_rule():
+    # a grid that cannot coarsen has no coarse-grid correction: its cycle is
+    # nu_coarse plain sweeps, with or without the coarsest-level rule
+    per = (False, False, False)
+    L, s, _ = P.random_problem((7, 5, 6), per, seed=9, contrast=1.0, holes=0.05)
+    levels = O.build_hierarchy(L, per)
+    refs = build_reference(L, per, "f64")
+    assert len(levels) == len(refs) == 1
+    x0 = np.zeros(s.size)
+    want = gauss_seidel(refs[0]["A"], refs[0]["colour"], x0, s.ravel(), 0.9, 5)
+    for crtol in (0.0, 0.1, 0.5):
+        got = O.vcycle(levels, x0.reshape(s.shape), s, 0.9, 2, 2, 5, coarse_rtol=crtol)
+        assert np.abs(got.ravel() - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_coarse_rule_projects_out_the_mean():
+    # on a singular level a right-hand side with a nonzero mean (in the
+    # cycle: its rounding) cannot be solved; without the projection its
+    # residual norm stalls above the stopping factor and the rule runs to its
+    # cap, drifting x along the constants.  With it the rule stops early,
+    # and the result is that of the mean-free right-hand side
+    per = (False, False, False)
+    L, s, _ = P.random_problem((8, 8, 8), per, seed=13, contrast=1.0, holes=0.0)
+    levels = O.build_hierarchy(L, per, max_levels=1)
+    refs = build_reference(L, per, "f64", max_levels=1)
+    act = refs[0]["active"]
+    b = s.ravel().copy()
+    b[act] += 0.3 * math.sqrt(float(b[act] @ b[act]) / act.sum())  # a constant, 0.3 ||b||
+    c_ref = []
+    want = coarsest_reference(refs[0], np.zeros(b.size), b, 1.0, 64, 0.1, c_ref)
+    x, n = O.coarsest_sweeps(np.zeros_like(s), b.reshape(s.shape), levels[0]["L"], per, 1.0, 4,
+                             0.1, 64, levels[0]["active"])
+    assert n == c_ref[0] < 64
+    assert np.abs(x.ravel() - want).max() <= 1e-12 * np.abs(want).max()
+    bz = s.ravel().copy()
+    bz[act] -= bz[act].mean()
+    xz, nz = O.coarsest_sweeps(np.zeros_like(s), bz.reshape(s.shape), levels[0]["L"], per, 1.0,
+                               4, 0.1, 64, levels[0]["active"])
+    assert nz == n and np.abs(xz - x).max() <= 1e-12 * np.abs(x).max()
+    # without the projection the plain residual norm stays above 0.1 ||b||
+    xs = gauss_seidel(refs[0]["A"], refs[0]["colour"], np.zeros(b.size), b, 1.0, 64)
+    res = np.where(act, b - refs[0]["A"] @ xs, 0.0)
+    assert math.sqrt(float(res @ res)) > 0.1 * math.sqrt(float(b[act] @ b[act]))
