@@ -84,6 +84,7 @@ typedef struct gmg_params {
   int32_t nu_pre;        /* red-black sweeps before restriction (default 2)   */
   int32_t nu_post;       /* sweeps after the correction (default 2)           */
   int32_t nu_coarse;     /* sweeps on the coarsest level when coarse_rtol is 0,
+                            the group size of the coarse_rtol rule otherwise;
                             no direct solve (4)                                */
   int32_t rollback;      /* 1: a V-cycle that grows the residual is discarded
                             (default 1)                                        */
@@ -128,13 +129,17 @@ typedef struct gmg_params {
   double theta_dec;      /* factor applied on residual growth (0.5)           */
   double theta_inc;      /* factor applied on residual decay (1.2)            */
   double coarse_rtol;    /* smoothing of the coarsest level of a hierarchy of
-                            two or more levels (red-black smoother): sweeps
-                            until its residual norm (active cells, FP64 sum)
-                            is at most coarse_rtol times its value on entry,
-                            at least one and at most coarse_max.  Sec. 3.2:
-                            the coarsest grid is where the smoother removes
-                            the lowest wavenumbers.  Needs a coarsest level
-                            of at most 2^20 cells (else gmg_setup returns
+                            two or more levels (red-black smoother): its
+                            right-hand side loses its mean over the active
+                            cells (the level is singular; the mean holds only
+                            rounding), then sweeps in groups of nu_coarse,
+                            the residual norm (active cells, FP64 sum)
+                            checked after each group, until it is at most
+                            coarse_rtol times its value on entry or
+                            coarse_max sweeps are done.  Sec. 3.2: the
+                            coarsest grid is where the smoother removes the
+                            lowest wavenumbers.  Needs a coarsest level of at
+                            most 2^20 cells (else gmg_setup returns
                             GMG_ESHAPE).  0: exactly nu_coarse sweeps.  A
                             single-level grid always takes nu_coarse sweeps
                             per cycle.  Must be in [0, 1) (default 0.1)      */

@@ -268,9 +268,10 @@ def coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max,
     active cells ``act`` (with walls and periodic directions only the level
     is singular, constants being in the null space, and only a zero-mean
     right-hand side is solvable; the restricted residual has zero mean in
-    exact arithmetic), then sweeps until the residual norm over the active
-    cells is at most coarse_rtol times its value on entry, at least one
-    sweep and at most coarse_max.  No direct solve either way.  Returns
+    exact arithmetic), then sweeps in groups of g = max(1, nu_coarse), the
+    residual norm over the active cells checked after each group, until it
+    is at most coarse_rtol times its value on entry or coarse_max sweeps are
+    done (the last group cut to fit).  No direct solve either way.  Returns
     (x, sweeps)."""
     if coarse_rtol <= 0.0:
         for _ in range(nu_coarse):
@@ -282,11 +283,13 @@ def coarsest_sweeps(x, sigma, L, per, omega, nu_coarse, coarse_rtol, coarse_max,
     if act.any():
         sigma[act] -= sigma[act].mean()
     r0 = norm2(residual(x, sigma, L, per))
+    group = max(1, nu_coarse)
     n = 0
     while n < coarse_max:
-        x = rb_sweep(x, sigma, L, per, omega)
-        n += 1
-        if norm2(residual(x, sigma, L, per)) <= coarse_rtol * r0:
+        for _ in range(min(group, coarse_max - n)):
+            x = rb_sweep(x, sigma, L, per, omega)
+            n += 1
+        if n < coarse_max and norm2(residual(x, sigma, L, per)) <= coarse_rtol * r0:
             break
     return x, n
 

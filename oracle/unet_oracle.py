@@ -62,6 +62,16 @@ def conv3d_backward(x, w, dy):
     return dx, dw, db
 
 
+def bf16(a):
+    """Round to BF16 (round to nearest even on the FP32 bit pattern, after
+    rounding to FP32) and return the value in FP64: the storage rounding of
+    a BF16 activation or gradient whose value was accumulated in FP32."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def relu(x):
     return np.maximum(x, 0.0)
 
@@ -128,23 +138,27 @@ def init_params(seed, in_ch=4, chans=(16, 32, 64, 128)):
     return params
 
 
-def forward(params, x, chans=(16, 32, 64, 128)):
+def forward(params, x, chans=(16, 32, 64, 128), store_bf16=False):
     """U-Net forward for one sample x[C_in, D, H, W]; returns (y[1, D, H, W],
-    cache of every intermediate for backward)."""
+    cache of every intermediate for backward).  store_bf16: every stored
+    activation (each convolution + ReLU output and each pooling output) is
+    rounded to BF16, as a network that keeps its activations in BF16 stores
+    them; the head's output is not."""
     nl = len(chans)
+    rnd = bf16 if store_bf16 else (lambda v: v)
     cache = {"x": x}
     h = x
     for i in range(nl):
-        a = relu(conv3d(h, params[f"enc{i}a.w"], params[f"enc{i}a.b"]))
-        bb = relu(conv3d(a, params[f"enc{i}b.w"], params[f"enc{i}b.b"]))
+        a = rnd(relu(conv3d(h, params[f"enc{i}a.w"], params[f"enc{i}a.b"])))
+        bb = rnd(relu(conv3d(a, params[f"enc{i}b.w"], params[f"enc{i}b.b"])))
         cache[f"enc{i}in"], cache[f"enc{i}a"], cache[f"enc{i}b"] = h, a, bb
-        h = avgpool2(bb) if i < nl - 1 else bb
+        h = rnd(avgpool2(bb)) if i < nl - 1 else bb
     for i in range(nl - 2, -1, -1):
         u = upsample2(h)
-        c = relu(conv3d(u, params[f"up{i}.w"], params[f"up{i}.b"]))
+        c = rnd(relu(conv3d(u, params[f"up{i}.w"], params[f"up{i}.b"])))
         cat = np.concatenate([c, cache[f"enc{i}b"]], axis=0)
-        a = relu(conv3d(cat, params[f"dec{i}a.w"], params[f"dec{i}a.b"]))
-        bb = relu(conv3d(a, params[f"dec{i}b.w"], params[f"dec{i}b.b"]))
+        a = rnd(relu(conv3d(cat, params[f"dec{i}a.w"], params[f"dec{i}a.b"])))
+        bb = rnd(relu(conv3d(a, params[f"dec{i}b.w"], params[f"dec{i}b.b"])))
         cache[f"up{i}in"], cache[f"up{i}"], cache[f"cat{i}"] = u, c, cat
         cache[f"dec{i}a"], cache[f"dec{i}b"] = a, bb
         h = bb
@@ -153,35 +167,43 @@ def forward(params, x, chans=(16, 32, 64, 128)):
     return y, cache
 
 
-def backward(params, cache, dy, chans=(16, 32, 64, 128)):
-    """Gradients of every parameter (and of the input) given dL/dy."""
+def backward(params, cache, dy, chans=(16, 32, 64, 128), store_bf16=False):
+    """Gradients of every parameter (and of the input) given dL/dy.
+    store_bf16: every stored activation gradient (each convolution's input
+    gradient, each upsampling and pooling backward, and the encoder's sum of
+    pooled and skip gradients) is rounded to BF16; parameter gradients are
+    not."""
     nl = len(chans)
+    rnd = bf16 if store_bf16 else (lambda v: v)
     g = {}
     dh, g["head.w"], g["head.b"] = conv3d_backward(cache["headin"], params["head.w"], dy)
+    dh = rnd(dh)
     dskip = {}
     for i in range(nl - 1):
         d = relu_backward(cache[f"dec{i}b"], dh)
         d, g[f"dec{i}b.w"], g[f"dec{i}b.b"] = conv3d_backward(cache[f"dec{i}a"],
                                                               params[f"dec{i}b.w"], d)
-        d = relu_backward(cache[f"dec{i}a"], d)
+        d = relu_backward(cache[f"dec{i}a"], rnd(d))
         dcat, g[f"dec{i}a.w"], g[f"dec{i}a.b"] = conv3d_backward(cache[f"cat{i}"],
                                                                  params[f"dec{i}a.w"], d)
+        dcat = rnd(dcat)
         c = chans[i]
         dc, dskip[i] = dcat[:c], dcat[c:]
         d = relu_backward(cache[f"up{i}"], dc)
         du, g[f"up{i}.w"], g[f"up{i}.b"] = conv3d_backward(cache[f"up{i}in"],
                                                            params[f"up{i}.w"], d)
-        dh = upsample2_backward(du)
+        dh = rnd(upsample2_backward(rnd(du)))
     for i in range(nl - 1, -1, -1):
         # the bottom level feeds the decoder directly; the others feed the
         # pooling to the next level and the skip concatenation
-        d = dh if i == nl - 1 else avgpool2_backward(dh) + dskip[i]
+        d = dh if i == nl - 1 else rnd(avgpool2_backward(dh) + dskip[i])
         d = relu_backward(cache[f"enc{i}b"], d)
         d, g[f"enc{i}b.w"], g[f"enc{i}b.b"] = conv3d_backward(cache[f"enc{i}a"],
                                                               params[f"enc{i}b.w"], d)
-        d = relu_backward(cache[f"enc{i}a"], d)
+        d = relu_backward(cache[f"enc{i}a"], rnd(d))
         dh, g[f"enc{i}a.w"], g[f"enc{i}a.b"] = conv3d_backward(cache[f"enc{i}in"],
                                                                params[f"enc{i}a.w"], d)
+        dh = rnd(dh)
     return g, dh
 
 

@@ -12,8 +12,8 @@
 // in global memory by the same code.
 //
 // The coarsest level is smoothed either by nu_coarse sweeps or, with
-// coarse_rtol > 0, until its residual norm has fallen to coarse_rtol times its
-// value on entry (at least one sweep, at most coarse_max): the paper's
+// coarse_rtol > 0, in groups of nu_coarse sweeps until its residual norm has
+// fallen to coarse_rtol times its value on entry (at most coarse_max): the paper's
 // anisotropic coarsening (Sec. 3.2) reaches a coarsest grid on which the
 // smoother alone removes the lowest wavenumbers, and this rule lets it do
 // so.  The rule first removes the mean of the level's right-hand side over
@@ -210,21 +210,53 @@ __device__ __forceinline__ void tail_prolong(const TailView<T, TL>& f, const Tai
   __syncthreads();
 }
 
-// The coarsest level is smoothed by the workgroup's first wavefront alone:
-// its few cells do not fill more, and between two half-sweeps a wavefront
-// needs only its own memory operations completed (a fence, no barrier).
+// The coarsest level is smoothed by a group of threads: the workgroup's
+// first wavefront alone when the level has at most kWaveCells cells (its
+// cells do not fill more, and between two half-sweeps a wavefront needs only
+// its own memory operations completed: a fence, no barrier), else the whole
+// workgroup.  The group's stride STRIDE names it.
 constexpr int kWave = 64;
+constexpr int kWaveCells = 256;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
 }
 
-// Half-sweep of colour `colour` by one wavefront, in place (tail_half_sweep
-// with a wavefront's stride).
-template <typename T, typename TL>
-__device__ __forceinline__ void wave_half_sweep(const TailView<T, TL>& v, int colour, T omega,
-                                                int lane) {
+template <int STRIDE>
+__device__ __forceinline__ void grp_sync() {
+  if constexpr (STRIDE == kWave)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// Sum over the wavefront, the same fixed order in every lane's result.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over the group, the result in every thread (red: one LDS double).
+template <int STRIDE>
+__device__ __forceinline__ double grp_sum(double v, double* red) {
+  if constexpr (STRIDE == kWave) {
+    return wave_sum(v);
+  } else {
+    const double s = block_sum(v, threadIdx.x, STRIDE);
+    if (threadIdx.x == 0) *red = s;
+    __syncthreads();
+    const double out = *red;
+    __syncthreads();  // *red is reused by the next sum
+    return out;
+  }
+}
+
+// Half-sweep of colour `colour` by the group, in place: work items are
+// x-pairs of a row, each holding exactly one cell per colour.
+template <typename T, typename TL, int STRIDE>
+__device__ __forceinline__ void grp_half_sweep(const TailView<T, TL>& v, int colour, T omega) {
   const Geom& g = v.g;
   const int nx = g.nx, ny = g.ny;
   const int sy = nx, sz = nx * ny, n = sz * g.nz;
@@ -235,7 +267,7 @@ __device__ __forceinline__ void wave_half_sweep(const TailView<T, TL>& v, int co
   const TL* Ly = v.L + n;
   const TL* Lz = v.L + 2 * n;
   T* x = v.x;
-  for (int p = lane; p < np; p += kWave) {
+  for (int p = threadIdx.x; p < np; p += STRIDE) {
     const int row = tail_div(p, pr, rpr);
     const int m = p - row * pr;
     const int k = tail_div(row, ny, rny);
@@ -258,14 +290,7 @@ __device__ __forceinline__ void wave_half_sweep(const TailView<T, TL>& v, int co
                          yn_in ? ldL<T>(Ly, qn) : T(0), ldL<T>(Lz, q),
                          zt_in ? ldL<T>(Lz, qt) : T(0), v.s[q], omega);
   }
-  wave_sync();
-}
-
-// Sum over the wavefront, the same fixed order in every lane's result.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  grp_sync<STRIDE>();
 }
 
 // Residual of cell q of a tail level (dtype arithmetic); `act` is D != 0.
@@ -284,19 +309,19 @@ __device__ __forceinline__ T tail_cell_residual(const TailView<T, TL>& v, int q,
 }
 
 // ||sigma - A x||_2 over the active cells: FP64 squares of the dtype
-// residuals summed per lane in cell order, then over the wavefront.
-template <typename T, typename TL>
-__device__ __forceinline__ double wave_resnorm(const TailView<T, TL>& v, int lane) {
+// residuals summed per thread in cell order, then over the group.
+template <typename T, typename TL, int STRIDE>
+__device__ __forceinline__ double grp_resnorm(const TailView<T, TL>& v, double* red) {
   const Geom& g = v.g;
   const int ncell = (int)g.n;
   const float rnx = 1.0f / (float)g.nx, rny = 1.0f / (float)g.ny;
   double s2 = 0.0;
-  for (int q = lane; q < ncell; q += kWave) {
+  for (int q = threadIdx.x; q < ncell; q += STRIDE) {
     bool act;
     const T r = tail_cell_residual<T, TL>(v, q, rnx, rny, act);
     if (act) s2 += (double)r * (double)r;
   }
-  return sqrt(wave_sum(s2));
+  return sqrt(grp_sum<STRIDE>(s2, red));
 }
 
 // sigma -= its mean over the active cells (FP64 sum and mean, the
@@ -306,51 +331,71 @@ __device__ __forceinline__ double wave_resnorm(const TailView<T, TL>& v, int lan
 // restricted residual has it in exact arithmetic, and this removes what
 // rounding left, which the smoother could not reduce and which would drift
 // the level's iterate along the null space.
-template <typename T, typename TL>
-__device__ __forceinline__ void wave_project(const TailView<T, TL>& v, int lane) {
+template <typename T, typename TL, int STRIDE>
+__device__ __forceinline__ void grp_project(const TailView<T, TL>& v, double* red) {
   const int ncell = (int)v.g.n;
   double s = 0.0, c = 0.0;
-  for (int q = lane; q < ncell; q += kWave)
+  for (int q = threadIdx.x; q < ncell; q += STRIDE)
     if (v.a[q]) {
       s += (double)v.s[q];
       c += 1.0;
     }
-  s = wave_sum(s);
-  c = wave_sum(c);
+  s = grp_sum<STRIDE>(s, red);
+  c = grp_sum<STRIDE>(c, red);
   const double mean = c > 0.0 ? s / c : 0.0;
-  for (int q = lane; q < ncell; q += kWave)
+  for (int q = threadIdx.x; q < ncell; q += STRIDE)
     if (v.a[q]) v.s[q] = (T)((double)v.s[q] - mean);
-  wave_sync();
+  grp_sync<STRIDE>();
 }
 
-// Smoothing of the coarsest level: nu_coarse sweeps, or with coarse_rtol > 0
-// the right-hand side projected to zero mean, then sweeps until the residual
-// norm is at most coarse_rtol times its value on entry (at least one sweep,
-// at most coarse_max).  Run by the first
-// wavefront; returns the number of sweeps to every thread.
+// Smoothing of the coarsest level by one group: nu_coarse sweeps, or with
+// coarse_rtol > 0 the right-hand side projected to zero mean, then sweeps in
+// groups of max(1, nu_coarse), the residual norm checked after each, until
+// it is at most coarse_rtol times its value on entry or coarse_max sweeps
+// are done (the last group cut to fit).  Returns the number of sweeps.
+template <typename T, typename TL, int STRIDE>
+__device__ __forceinline__ int grp_coarsest(const TailView<T, TL>& v, int nu_coarse,
+                                            double coarse_rtol, int coarse_max, T omega,
+                                            double* red) {
+  int n = 0;
+  if (!(coarse_rtol > 0.0)) {
+    for (; n < nu_coarse; ++n) {
+      grp_half_sweep<T, TL, STRIDE>(v, 0, omega);
+      grp_half_sweep<T, TL, STRIDE>(v, 1, omega);
+    }
+    return n;
+  }
+  grp_project<T, TL, STRIDE>(v, red);
+  const double lim = coarse_rtol * grp_resnorm<T, TL, STRIDE>(v, red);
+  const int group = nu_coarse > 1 ? nu_coarse : 1;
+  while (n < coarse_max) {
+    const int k = min(group, coarse_max - n);
+    for (int s = 0; s < k; ++s) {
+      grp_half_sweep<T, TL, STRIDE>(v, 0, omega);
+      grp_half_sweep<T, TL, STRIDE>(v, 1, omega);
+    }
+    n += k;
+    if (n < coarse_max && grp_resnorm<T, TL, STRIDE>(v, red) <= lim) break;
+  }
+  return n;
+}
+
+// The coarsest level's smoothing (grp_coarsest) by the first wavefront or
+// the workgroup; returns the number of sweeps to every thread.
 template <typename T, typename TL>
 __device__ __forceinline__ int tail_coarsest(const TailView<T, TL>& v, int nu_coarse,
                                              double coarse_rtol, int coarse_max, T omega,
                                              int* count) {
-  const int t = threadIdx.x;
-  if (t < kWave) {
-    int n = 0;
-    if (!(coarse_rtol > 0.0)) {
-      for (; n < nu_coarse; ++n) {
-        wave_half_sweep<T, TL>(v, 0, omega, t);
-        wave_half_sweep<T, TL>(v, 1, omega, t);
-      }
-    } else {
-      wave_project<T, TL>(v, t);
-      const double lim = coarse_rtol * wave_resnorm<T, TL>(v, t);
-      while (n < coarse_max) {
-        wave_half_sweep<T, TL>(v, 0, omega, t);
-        wave_half_sweep<T, TL>(v, 1, omega, t);
-        ++n;
-        if (n < coarse_max && wave_resnorm<T, TL>(v, t) <= lim) break;
-      }
+  __shared__ double red;
+  if (v.g.n <= kWaveCells) {
+    if (threadIdx.x < kWave) {
+      const int n = grp_coarsest<T, TL, kWave>(v, nu_coarse, coarse_rtol, coarse_max, omega, &red);
+      if (threadIdx.x == 0) *count = n;
     }
-    if (t == 0) *count = n;
+  } else {
+    const int n =
+        grp_coarsest<T, TL, kTailThreads>(v, nu_coarse, coarse_rtol, coarse_max, omega, &red);
+    if (threadIdx.x == 0) *count = n;
   }
   __syncthreads();
   return *count;

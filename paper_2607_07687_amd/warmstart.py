@@ -143,24 +143,79 @@ def predict(net, sm, x_buf, out):
     return out
 
 
-def warm_solve(h, net, sm, x, x_buf, rtol=1e-6, max_outer=30):
+# a prediction whose residual exceeds this many times ||sigma|| is not used
+PRED_LIMIT = 10.0
+
+
+class HalfRes:
+    """Half-resolution inference: the network runs on the problem restricted
+    to the hierarchy's level 1 (sigma summed over 2x2x2 blocks, the level's
+    faces), and its prediction is prolongated back.  For a smooth pressure
+    the level-1 problem A_1 p_1 = R sigma has p_1 close to p at the coarse
+    cells (the level-1 faces are twice the mean of the fine faces they
+    cover, and R sums eight right-hand sides).  The network, trained on
+    faces in [0, 1], is fed the level-1 faces halved and R sigma / (8 s);
+    its output q then solves the problem with the halved faces, so
+    p_1 = 4 s q.  Every step runs in the libraries: the restriction and
+    level-1 faces from libgmg.so, scaling and packing in libunet.so, and
+    the piecewise-constant prolongation on the active cells from libgmg.so.
+    Needs a grid that coarsens by 2 in every direction to level 1."""
+
+    def __init__(self, h, sm):
+        import torch
+        n1, c = G.gmg_level_shape(h, 1)
+        if tuple(c) != (2, 2, 2):
+            raise ValueError("half-resolution inference needs 2x2x2 coarsening to level 1")
+        self.h, self.sm, self.n1 = h, sm, n1
+        nx, ny, nz = n1
+        dev = sm.sigma.device
+        self.zero = torch.zeros_like(sm.sigma)
+        self.x32 = torch.zeros_like(sm.sigma)
+        self.s1 = torch.zeros((nz, ny, nx), dtype=torch.float32, device=dev)
+        self.L1 = torch.zeros((3, nz, ny, nx), dtype=torch.float32, device=dev)
+        self.Lin = torch.zeros_like(self.L1)
+        self.x1 = torch.zeros_like(self.s1)
+        self.xb = torch.zeros((1, nz, ny, nx, NET.IN_CH), dtype=torch.int16, device=dev)
+        G.gmg_level_faces(h, 1, self.L1)
+        UN.unet_scale(self.L1, 0.5, self.Lin)
+
+    def predict(self, net, x64):
+        """x64 (FP64, level 0) <- P (4 s U(R sigma / (8 s), L_1 / 2))."""
+        nx, ny, nz = self.n1
+        s = self.sm.scale
+        G.gmg_restrict_residual(self.h, 0, self.zero, self.sm.sigma, self.s1)
+        UN.unet_pack_input(UN.shape(1, nz, ny, nx), self.s1, self.Lin, [8.0 * s], self.xb)
+        y = net.forward(self.xb, 1, nz, ny, nx)
+        UN.unet_scale(y, 4.0 * s, self.x1)
+        self.x32.zero_()
+        G.gmg_prolong_correct(self.h, 0, self.x1, self.x32)
+        UN.unet_scale_f64(self.x32, 1.0, x64)
+
+
+def warm_solve(h, net, sm, x, x_buf, rtol=1e-6, max_outer=30, half=None):
     """Solve with the learned warm start and plain GMG as the fallback.
 
     x0 = s * U(sigma / s, L) is written into x (FP64); its residual judges
-    it: if ||sigma - A x0|| > ||sigma|| (worse than the zero guess) x is
-    zeroed before the solve.  The refinement solve then runs from x; if it
-    misses rtol within max_outer steps from a prediction, x is zeroed and
-    the solve runs again from zero.  Returns (info of the solve whose x is
-    returned, fallback reason or None)."""
+    it.  A useful prediction can have a residual above ||sigma||: its error
+    has high-frequency content that the operator amplifies and the first
+    sweeps remove at once.  So x is zeroed before the solve only when the
+    prediction is clearly broken, ||sigma - A x0|| > PRED_LIMIT ||sigma|| or
+    not finite.  The refinement solve then runs from x; if it misses rtol
+    within max_outer steps from a prediction, x is zeroed and the solve runs
+    again from zero.  Returns (info of the solve whose x is returned,
+    fallback reason or None)."""
     nx, ny, nz = sm.n
-    pack([sm], x_buf)
-    y = net.forward(x_buf, 1, nz, ny, nx)
-    UN.unet_scale_f64(y, sm.scale, x)
+    if half is not None:
+        half.predict(net, x)
+    else:
+        pack([sm], x_buf)
+        y = net.forward(x_buf, 1, nz, ny, nx)
+        UN.unet_scale_f64(y, sm.scale, x)
     rn, sn = G.gmg_residual(h, x, sm.sigma64)
     reason = None
-    if not (rn <= sn):  # also catches a non-finite prediction
+    if not (rn <= PRED_LIMIT * sn):  # also catches a non-finite prediction
         x.zero_()
-        reason = "prediction worse than zero"
+        reason = "prediction residual far above the zero guess's"
     info = G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)
     if info["status"] != "GMG_OK" and reason is None:
         x.zero_()
@@ -169,12 +224,13 @@ def warm_solve(h, net, sm, x, x_buf, rtol=1e-6, max_outer=30):
     return info, reason
 
 
-def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
+def compare(net, samples, rtol=1e-6, reps=10, max_outer=30, half=False):
     """Wall time of plain GMG (x0 = 0) against U-Net inference + GMG from its
     prediction, on the same GPU; medians over reps.  Both solves are the FP64
     iterative refinement around FP32 V-cycles (each outer step one captured
     graph): the smooth low-mode right-hand sides of these problems put the
-    FP32 residual floor above 1e-6."""
+    FP32 residual floor above 1e-6.  half: the network runs on the problem
+    restricted to level 1 (HalfRes)."""
     import torch
     res = []
     for sm in samples:
@@ -182,16 +238,20 @@ def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
         prm = G.gmg_default_params(sm.n, sm.per, G.GMG_F64, cycle_dtype=G.GMG_F32)
         h = G.gmg_setup(prm, sm.L64)
         x = torch.zeros_like(sm.sigma64)
-        y32 = torch.zeros_like(sm.sigma)
-        xb = torch.zeros((1, nz, ny, nx, NET.IN_CH), dtype=torch.int16, device="cuda")
+        xb = None if half else torch.zeros((1, nz, ny, nx, NET.IN_CH), dtype=torch.int16,
+                                           device="cuda")
+        hr = HalfRes(h, sm) if half else None
 
         def warm():
+            if hr is not None:
+                hr.predict(net, x)
+                return
             pack([sm], xb)
             y = net.forward(xb, 1, nz, ny, nx)
             UN.unet_scale_f64(y, sm.scale, x)
 
         G.gmg_solve_ir(h, x, sm.sigma64, rtol, max_outer)  # warm-up (graph capture)
-        warm_solve(h, net, sm, x, xb, rtol, max_outer)
+        warm_solve(h, net, sm, x, xb, rtol, max_outer, hr)
         tp, tw, ti = [], [], []
         reasons = set()
         for _ in range(reps):
@@ -207,7 +267,7 @@ def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
             ti.append(time.perf_counter() - t0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            iw, why = warm_solve(h, net, sm, x, xb, rtol, max_outer)
+            iw, why = warm_solve(h, net, sm, x, xb, rtol, max_outer, hr)
             torch.cuda.synchronize()
             tw.append(time.perf_counter() - t0)
             if why:
@@ -222,7 +282,7 @@ def compare(net, samples, rtol=1e-6, reps=10, max_outer=30):
                         fallback=sorted(reasons)))
         h.close()
         r = res[-1]
-        print(f"eval {len(res)} {sm.n[0]}^3: plain {r['plain_ms']:.2f} ms ({r['plain_inner']} "
+        print(f"eval {len(res)} {sm.n[0]}^3{' (half-res inference)' if half else ''}: plain {r['plain_ms']:.2f} ms ({r['plain_inner']} "
               f"V-cycles, {r['plain_status']}), warm {r['warm_ms']:.2f} ms ({r['warm_inner']} "
               f"V-cycles, {r['warm_status']}; inference {r['infer_ms']:.2f} ms), "
               f"prediction r/s {rel0:.3e}", flush=True)
@@ -286,6 +346,9 @@ def main():
     ap.add_argument("--out", default="warmstart_out")
     ap.add_argument("--conv-throughput", action="store_true")
     ap.add_argument("--params", default="", help="trained weights (.npy): evaluate only")
+    ap.add_argument("--half-n", default="",
+                    help="evaluation grids (comma-separated) also run with half-resolution "
+                         "inference")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     G.load()
@@ -314,18 +377,23 @@ def main():
         np.save(os.path.join(args.out, "unet_params.npy"), net.get_flat())
         del train_set
     summary["eval"] = {}
+    half_n = [int(v) for v in args.half_n.split(",") if v]
     for en in [int(v) for v in args.eval_n.split(",")]:
         evals = make_samples((en,) * 3, range(20000, 20000 + args.eval_samples), args.workers,
                              with_target=False, keep64=True)
-        res = compare(net, evals)
+        for half in ([False, True] if en in half_n else [False]):
+            res = compare(net, evals, half=half)
+            med = lambda key: float(np.median([r[key] for r in res]))
+            key = f"{en}_half" if half else str(en)
+            summary["eval"][key] = dict(
+                per_sample=res, plain_ms_median=med("plain_ms"), warm_ms_median=med("warm_ms"),
+                infer_ms_median=med("infer_ms"), plain_vcycles_median=med("plain_inner"),
+                warm_vcycles_median=med("warm_inner"),
+                prediction_rel_residual_median=med("warm_rel_r0"),
+                fallbacks=sum(1 for r in res if r["fallback"]))
+            print(json.dumps({"eval": key, **{k: v for k, v in summary["eval"][key].items()
+                                              if k != "per_sample"}}), flush=True)
         del evals
-        med = lambda key: float(np.median([r[key] for r in res]))
-        summary["eval"][str(en)] = dict(
-            per_sample=res, plain_ms_median=med("plain_ms"), warm_ms_median=med("warm_ms"),
-            infer_ms_median=med("infer_ms"), plain_vcycles_median=med("plain_inner"),
-            warm_vcycles_median=med("warm_inner"), prediction_rel_residual_median=med("warm_rel_r0"))
-        print(json.dumps({"eval_n": en, **{k: v for k, v in summary["eval"][str(en)].items()
-                                           if k != "per_sample"}}), flush=True)
     with open(os.path.join(args.out, "summary.json"), "w") as f:
         json.dump(summary, f, indent=1)
 

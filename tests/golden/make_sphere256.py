@@ -2,7 +2,8 @@
 wall-bounded sphere workload (sphere of diameter 64 at the centre, cosine
 band of 2 cells, uniform-random face velocity, seed 1), FP32-rounded inputs,
 faces stored in FP32 on every level, V(2,2) with the default coarsest-level
-rule (sweeps until the coarsest residual falls by 0.1, at most 64), omega = 1.
+rule (groups of 4 sweeps until the coarsest residual falls by 0.1, at most
+64), omega = 1.
 
 Calls only the CPU oracle and the input generators.  Takes a few minutes:
 

@@ -1,13 +1,22 @@
 """GPU parity of the whole U-Net (forward output, every parameter gradient)
 against the FP64 oracle on a small grid, with the same BF16-rounded weights
-and inputs.  The GPU path rounds each activation and each backpropagated
-gradient to BF16 (unit roundoff u = 2^-9).  The output passes about ten
-roundings (bound 3e-2).  A weight gradient is a voxel sum of products of a
-forward activation and a backward gradient; the first encoder layer's
-gradient has passed about twenty backward roundings, so gradients are held
-to 0.1 norm-wise relative error and a cosine above 0.995 (20 u = 4e-2 of
-random-walk accumulation plus the correlated part the reductions keep);
-a wrong index or operand gives errors of order 1 and cosines far below."""
+and inputs, the oracle storing every activation and every activation
+gradient in BF16 at the points libunet.so does (store_bf16).
+
+What then separates the two is the order and precision of the sums inside
+each convolution: FP32 accumulation of K = 27 C_in products on the GPU, FP64
+in the oracle.  Before a BF16 store the two values differ by at most about
+K u32 of the sum's magnitude (u32 = 2^-24, K <= 27 * 64 = 1728 here: 1e-4),
+so they round to different BF16 neighbours only when they straddle a
+rounding boundary, for a fraction of at most 2 K u32 / u16 (u16 = 2^-8: 0.05)
+of the elements, each then off by one BF16 spacing (2 u16).  A stored tensor
+so differs by at most sqrt(0.05) * 2 u16 = 1.7e-3 norm-wise, and through the
+ten stores of the forward pass, or the twenty of the deepest gradient
+(random walk), by at most 6e-3 and 8e-3.  The bounds are 1e-2 for the output
+and the loss, and 2e-2 with a cosine above 0.9995 for every parameter
+gradient.  (Typical sums are far from the worst case, and the errors seen
+are some ten times smaller.)  A wrong index or operand gives errors of order
+one."""
 import numpy as np
 import pytest
 
@@ -64,18 +73,18 @@ def test_unet_forward_backward_matches_oracle():
     cnt = int(mask.sum())
     for i in range(n):
         xo = np.moveaxis(x64[i], -1, 0)[:4]
-        y, cache = UO.forward(P, xo, chans)
+        y, cache = UO.forward(P, xo, chans, store_bf16=True)
         outs.append(y[0])
         dlt = (y[0] - tgt[i]) * mask[i]
         ltot += float(np.sum(dlt * dlt))
-        g, _ = UO.backward(P, cache, (2.0 * dlt / cnt)[None], chans)
+        g, _ = UO.backward(P, cache, (2.0 * dlt / cnt)[None], chans, store_bf16=True)
         gsum = g if gsum is None else {k: gsum[k] + g[k] for k in g}
     want = np.stack(outs)
     got = out.cpu().numpy().astype(np.float64)
     e_out = np.linalg.norm(got - want) / np.linalg.norm(want)
     say(f"unet out rel err {e_out:.2e}, loss {loss:.4f} vs {ltot / cnt:.4f}")
-    assert e_out <= 3e-2
-    assert abs(loss - ltot / cnt) <= 3e-2 * ltot / cnt
+    assert e_out <= 1e-2
+    assert abs(loss - ltot / cnt) <= 1e-2 * ltot / cnt
     G = net.grad.cpu().numpy().astype(np.float64)
     bad = []
     for name, ci, co, taps in net.layers:
@@ -89,7 +98,7 @@ def test_unet_forward_backward_matches_oracle():
             e = np.linalg.norm(got_g - want_g) / max(np.linalg.norm(want_g), 1e-30)
             cos = float(np.sum(got_g * want_g) / (np.linalg.norm(got_g) * np.linalg.norm(want_g) + 1e-300))
             say(f"  {name}.{tag}: rel {e:.2e} cos {cos:.5f}")
-            bad.append((name, tag, e, cos)) if (e > 0.1 or cos < 0.995) else None
+            bad.append((name, tag, e, cos)) if (e > 2e-2 or cos < 0.9995) else None
     assert not bad, bad
 
 

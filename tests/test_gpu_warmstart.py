@@ -80,3 +80,38 @@ def test_untrained_prediction_falls_back_to_plain_gmg():
     info, why = W.warm_solve(h, net, sm, x, xb, rtol=1e-12, max_outer=1)
     assert info["status"] == "GMG_ENOCONV" and why is not None
     h.close()
+
+
+def test_half_resolution_inference_plumbing():
+    # the half-resolution path feeds the network the level-1 problem (R sigma
+    # against the oracle's restriction, the level-1 faces halved) and returns
+    # the piecewise-constant prolongation of 4 s times its output on the
+    # active cells, zero elsewhere
+    require_gpu()
+    from oracle import gmg_oracle as O
+    from paper_2607_07687_amd import unet as UN
+    from tests.test_gpu_unet_ops import from_dev_bf16
+    n = (32, 32, 32)
+    (sm,) = W.make_samples(n, [31700], workers=1, with_target=False, keep64=True)
+    prm = G.gmg_default_params(n, sm.per, G.GMG_F64, cycle_dtype=G.GMG_F32)
+    h = G.gmg_setup(prm, sm.L64)
+    net = NET.UNet((16, 32, 64))
+    net.init_he(2)
+    hr = W.HalfRes(h, sm)
+    x = torch.zeros_like(sm.sigma64)
+    hr.predict(net, x)
+    torch.cuda.synchronize()
+    levels = O.build_hierarchy(sm.L.cpu().numpy().astype(np.float64), sm.per, storage="f32")
+    s32 = sm.sigma.cpu().numpy().astype(np.float64)
+    want_s1 = O.restrict(np.where(levels[0]["active"], s32, 0.0), levels[0]["c"])
+    got_s1 = hr.s1.cpu().numpy().astype(np.float64)
+    assert np.abs(got_s1 - want_s1).max() <= 1e-5 * np.abs(want_s1).max()
+    assert np.array_equal(hr.Lin.cpu().numpy(), (levels[1]["L"] * 0.5).astype(np.float32))
+    packed = from_dev_bf16(hr.xb)[0]
+    assert np.allclose(packed[..., 0], got_s1 / (8 * sm.scale), rtol=2 ** -8, atol=0)
+    y = net.forward(hr.xb, 1, 16, 16, 16).cpu().numpy().astype(np.float64)[0]
+    xc = 4.0 * sm.scale * y
+    want = np.where(levels[0]["active"], O.prolong(xc, levels[0]["c"]), 0.0)
+    got = x.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    h.close()

@@ -138,11 +138,11 @@ def build_reference(L, periodic, storage, anisotropic=True, max_levels=0):
     return refs
 
 
-def coarsest_reference(r, x, b, omega, nuc, crtol, counts=None):
+def coarsest_reference(r, x, b, omega, nuc, crtol, counts=None, group=1):
     """crtol = 0: nuc sweeps.  crtol > 0: remove the mean of b over the
-    active cells, then sweep until the residual norm on the active cells is
-    at most crtol times its value on entry, at least one sweep and at most
-    nuc (the cap)."""
+    active cells, then sweep in groups of `group`, checking the residual
+    norm on the active cells after each group, until it is at most crtol
+    times its value on entry or nuc (the cap) sweeps are done."""
     if crtol <= 0.0:
         return gauss_seidel(r["A"], r["colour"], x, b, omega, nuc)
     act = r["active"]
@@ -154,23 +154,27 @@ def coarsest_reference(r, x, b, omega, nuc, crtol, counts=None):
         return math.sqrt(float(res @ res))
 
     r0 = rnorm(x)
-    for n in range(1, nuc + 1):
-        x = gauss_seidel(r["A"], r["colour"], x, b, omega, 1)
-        if rnorm(x) <= crtol * r0:
+    n = 0
+    while n < nuc:
+        k = min(group, nuc - n)
+        x = gauss_seidel(r["A"], r["colour"], x, b, omega, k)
+        n += k
+        if n < nuc and rnorm(x) <= crtol * r0:
             break
     if counts is not None:
         counts.append(n)
     return x
 
 
-def vcycle_reference(refs, x, b, omega, nu1, nu2, nuc, l=0, crtol=0.0, counts=None):
+def vcycle_reference(refs, x, b, omega, nu1, nu2, nuc, l=0, crtol=0.0, counts=None, group=1):
     r = refs[l]
     if r["c"] is None:
-        return coarsest_reference(r, x, b, omega, nuc, crtol, counts)
+        return coarsest_reference(r, x, b, omega, nuc, crtol, counts, group)
     x = gauss_seidel(r["A"], r["colour"], x, b, omega, nu1)
     res = np.where(r["active"], b - r["A"] @ x, 0.0)
     bc = r["P"].T @ res  # R = P^T
-    xc = vcycle_reference(refs, np.zeros(bc.size), bc, omega, nu1, nu2, nuc, l + 1, crtol, counts)
+    xc = vcycle_reference(refs, np.zeros(bc.size), bc, omega, nu1, nu2, nuc, l + 1, crtol, counts,
+                          group)
     x = x + np.where(r["active"], r["P"] @ xc, 0.0)
     return gauss_seidel(r["A"], r["colour"], x, b, omega, nu2)
 
@@ -197,17 +201,19 @@ def test_vcycle_equals_assembled_reconstruction(name, n, per, storage, aniso, ma
         assert np.array_equal(lv["active"].ravel(), r["active"])
     rng = np.random.default_rng(3)
     x0 = np.where(levels[0]["active"], rng.standard_normal(s.shape), 0.0)
-    for (nu1, nu2, nuc, omega, crtol) in ((1, 3, 5, 0.7, 0.0), (2, 2, 4, 1.0, 0.0),
-                                         (2, 2, 64, 1.0, 0.1), (1, 2, 40, 0.8, 0.01)):
+    for (nu1, nu2, nuc, omega, crtol, grp) in ((1, 3, 5, 0.7, 0.0, 1), (2, 2, 4, 1.0, 0.0, 1),
+                                              (2, 2, 64, 1.0, 0.1, 4), (1, 2, 40, 0.8, 0.01, 3),
+                                              (2, 1, 30, 0.9, 0.05, 1)):
         st, counts = [], []
-        got = O.vcycle(levels, x0, s, omega, nu1, nu2, nuc if crtol == 0 else 4,
+        got = O.vcycle(levels, x0, s, omega, nu1, nu2, nuc if crtol == 0 else grp,
                        coarse_rtol=crtol, coarse_max=nuc, stats=st)
         want = vcycle_reference(refs, x0.ravel(), s.ravel(), omega, nu1, nu2, nuc, crtol=crtol,
-                                counts=counts)
+                                counts=counts, group=grp)
         scale = np.abs(want).max()
         assert np.abs(got.ravel() - want).max() <= 1e-12 * scale, (nu1, nu2, nuc, omega, crtol)
         if crtol > 0:
             assert st == counts and 1 <= st[0] <= nuc
+            assert st[0] == nuc or st[0] % grp == 0
 
 
 def test_reconstruction_detects_plausible_mistakes():
@@ -227,8 +233,8 @@ def test_reconstruction_detects_plausible_mistakes():
     assert far(vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 4))  # coarsest count
     # the adaptive coarsest rule: its stopping factor decides the sweep count
     c1, c2 = [], []
-    a1 = vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 64, crtol=0.1, counts=c1)
-    a2 = vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 64, crtol=0.01, counts=c2)
+    a1 = vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 64, crtol=0.1, counts=c1, group=2)
+    a2 = vcycle_reference(refs, x0, s.ravel(), 0.7, 1, 3, 64, crtol=0.01, counts=c2, group=2)
     assert c1[0] < c2[0] and np.abs(a1 - a2).max() > 1e-6 * np.abs(a2).max()
     r0 = refs[0]
     # correction after the post-sweeps
@@ -338,7 +344,7 @@ def test_coarse_rule_projects_out_the_mean():
     b = s.ravel().copy()
     b[act] += 0.3 * math.sqrt(float(b[act] @ b[act]) / act.sum())  # a constant, 0.3 ||b||
     c_ref = []
-    want = coarsest_reference(refs[0], np.zeros(b.size), b, 1.0, 64, 0.1, c_ref)
+    want = coarsest_reference(refs[0], np.zeros(b.size), b, 1.0, 64, 0.1, c_ref, group=4)
     x, n = O.coarsest_sweeps(np.zeros_like(s), b.reshape(s.shape), levels[0]["L"], per, 1.0, 4,
                              0.1, 64, levels[0]["active"])
     assert n == c_ref[0] < 64

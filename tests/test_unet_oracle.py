@@ -109,3 +109,33 @@ def test_parameter_count():
     params = U.init_params(0)
     n = sum(v.size for v in params.values())
     assert 1.5e6 < n < 1.7e6
+
+
+def test_bf16_storage_rounding_is_round_to_nearest_even():
+    # BF16 keeps 8 significant bits: between 1 and 2 the spacing is 2^-7.
+    # Halfway cases go to the even neighbour; others to the nearest; values
+    # already in BF16 are kept; FP64 inputs are rounded to FP32 first
+    u = 2.0 ** -7
+    x = np.array([1.0, 1.0 + u / 2, 1.0 + 3 * u / 2, 1.0 + 0.49 * u, 1.0 + 0.51 * u, -1.5,
+                  3.0 * 2.0 ** -130, 65504.0])
+    want = np.array([1.0, 1.0, 1.0 + 2 * u, 1.0, 1.0 + u, -1.5, 3.0 * 2.0 ** -130, 65536.0])
+    assert np.array_equal(U.bf16(x), want)
+    # idempotent, and within half a BF16 spacing (unit roundoff 2^-8) of the input
+    r = np.random.default_rng(0).standard_normal(1000)
+    b = U.bf16(r)
+    assert np.array_equal(U.bf16(b), b)
+    assert np.all(np.abs(b - r) <= 2.0 ** -8 * np.abs(r))
+
+
+def test_bf16_storage_changes_the_forward_only_by_its_rounding():
+    # with BF16 storage each stored activation is within 2^-8 of the value it
+    # rounds; over the network the output then moves by a few 2^-8 relative
+    chans = (8, 16)
+    P = U.init_params(4, 4, chans)
+    x = np.random.default_rng(1).standard_normal((4, 8, 8, 8))
+    y, _ = U.forward(P, x, chans)
+    yb, cb = U.forward(P, x, chans, store_bf16=True)
+    for k in ("enc0a", "enc0b", "enc1a", "enc1b", "up0", "dec0a", "dec0b"):
+        assert np.array_equal(U.bf16(cb[k]), cb[k]), k
+    e = np.linalg.norm(yb - y) / np.linalg.norm(y)
+    assert 0 < e < 10 * 2.0 ** -8
