@@ -380,6 +380,149 @@ __device__ __forceinline__ int grp_coarsest(const TailView<T, TL>& v, int nu_coa
   return n;
 }
 
+// Register-resident variant for the first wavefront on a level of at most
+// 2 x 64 x-pairs: each lane owns up to two x-pairs, i.e. two cells of each
+// colour, and keeps their indices, neighbour indices, faces and sigma in
+// registers for the whole coarsest smoothing; a half-sweep then reads only
+// the neighbours' x from LDS.  Every update is relax_cell on the operands
+// grp_half_sweep passes it, so the iterates are bitwise the same.
+constexpr int kRegPairs = 2 * kWave;
+
+template <typename T>
+struct RegCell {
+  int q;       // cell index, -1: none
+  int nb[6];   // x+1, x-1, y+1, y-1, z+1, z-1 (wrapped where periodic)
+  int in;      // bit d: neighbour d is in the grid (or wrapped)
+  T f[6];      // faces: low x, high x, low y, high y, low z, high z (0 beyond a wall)
+  T sg;
+};
+
+template <typename T, typename TL>
+__device__ __forceinline__ RegCell<T> reg_cell(const TailView<T, TL>& v, int p, int colour) {
+  const Geom& g = v.g;
+  const int nx = g.nx, ny = g.ny;
+  const int sy = nx, sz = nx * ny, n = sz * g.nz;
+  const int pr = (nx + 1) >> 1;
+  RegCell<T> c;
+  c.q = -1;
+  if (p >= pr * ny * g.nz) return c;
+  const int row = tail_div(p, pr, 1.0f / (float)pr);
+  const int m = p - row * pr;
+  const int k = tail_div(row, ny, 1.0f / (float)ny);
+  const int j = row - k * ny;
+  const int i = 2 * m + ((j + k + colour) & 1);
+  if (i >= nx) return c;
+  const int q = row * nx + i;
+  c.q = q;
+  const bool ok[6] = {i + 1 < nx || (bool)g.px, i > 0 || (bool)g.px,
+                      j + 1 < ny || (bool)g.py, j > 0 || (bool)g.py,
+                      k + 1 < g.nz || (bool)g.pz, k > 0 || (bool)g.pz};
+  c.nb[0] = (i + 1 < nx) ? q + 1 : q - (nx - 1);
+  c.nb[1] = (i > 0) ? q - 1 : q + (nx - 1);
+  c.nb[2] = (j + 1 < ny) ? q + sy : q - (ny - 1) * sy;
+  c.nb[3] = (j > 0) ? q - sy : q + (ny - 1) * sy;
+  c.nb[4] = (k + 1 < g.nz) ? q + sz : q - (g.nz - 1) * sz;
+  c.nb[5] = (k > 0) ? q - sz : q + (g.nz - 1) * sz;
+  c.in = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) c.in |= ok[d] ? (1 << d) : 0;
+  c.f[0] = ldL<T>(v.L, q);
+  c.f[1] = ok[0] ? ldL<T>(v.L, c.nb[0]) : T(0);
+  c.f[2] = ldL<T>(v.L + n, q);
+  c.f[3] = ok[2] ? ldL<T>(v.L + n, c.nb[2]) : T(0);
+  c.f[4] = ldL<T>(v.L + 2 * n, q);
+  c.f[5] = ok[4] ? ldL<T>(v.L + 2 * n, c.nb[4]) : T(0);
+  c.sg = T(0);
+  return c;
+}
+
+// The six neighbour values of a cell (0 outside a wall) into nv.
+template <typename T>
+__device__ __forceinline__ void reg_nbrs(const T* x, const RegCell<T>& c, T (&nv)[6]) {
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nv[d] = ((c.in >> d) & 1) ? x[c.nb[d]] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void reg_relax(T* x, const RegCell<T>& c, T omega) {
+  if (c.q < 0) return;
+  T nv[6];
+  reg_nbrs<T>(x, c, nv);
+  x[c.q] = relax_cell<T>(x[c.q], nv[0], nv[1], nv[2], nv[3], nv[4], nv[5], c.f[0], c.f[1],
+                         c.f[2], c.f[3], c.f[4], c.f[5], c.sg, omega);
+}
+
+// Squared residual sigma - A x of an owned active cell (0 otherwise).
+template <typename T>
+__device__ __forceinline__ double reg_res2(const T* x, const RegCell<T>& c) {
+  if (c.q < 0) return 0.0;
+  T nv[6];
+  reg_nbrs<T>(x, c, nv);
+  const T xc = x[c.q];
+  T ax = T(0), d = T(0);
+  ax += c.f[1] * (nv[0] - xc);
+  ax += c.f[0] * (nv[1] - xc);
+  d += c.f[0] + c.f[1];
+  ax += c.f[3] * (nv[2] - xc);
+  ax += c.f[2] * (nv[3] - xc);
+  d += c.f[2] + c.f[3];
+  ax += c.f[5] * (nv[4] - xc);
+  ax += c.f[4] * (nv[5] - xc);
+  d += c.f[4] + c.f[5];
+  if (-d == T(0)) return 0.0;
+  const T r = c.sg - ax;
+  return (double)r * (double)r;
+}
+
+template <typename T, typename TL>
+__device__ __forceinline__ int reg_coarsest(const TailView<T, TL>& v, int nu_coarse,
+                                            double coarse_rtol, int coarse_max, T omega,
+                                            double* red) {
+  const int lane = threadIdx.x;
+  RegCell<T> c[2][2];  // [colour][x-pair slot]
+#pragma unroll
+  for (int col = 0; col < 2; ++col)
+#pragma unroll
+    for (int it = 0; it < 2; ++it) c[col][it] = reg_cell<T, TL>(v, lane + kWave * it, col);
+  const bool rule = coarse_rtol > 0.0;
+  if (rule) grp_project<T, TL, kWave>(v, red);
+#pragma unroll
+  for (int col = 0; col < 2; ++col)
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      if (c[col][it].q >= 0) c[col][it].sg = v.s[c[col][it].q];
+  auto sweep = [&]() {
+#pragma unroll
+    for (int col = 0; col < 2; ++col) {
+      reg_relax<T>(v.x, c[col][0], omega);
+      reg_relax<T>(v.x, c[col][1], omega);
+      wave_sync();
+    }
+  };
+  auto norm = [&]() {
+    double a = 0.0;
+#pragma unroll
+    for (int col = 0; col < 2; ++col)
+#pragma unroll
+      for (int it = 0; it < 2; ++it) a += reg_res2<T>(v.x, c[col][it]);
+    return sqrt(wave_sum(a));
+  };
+  int n = 0;
+  if (!rule) {
+    for (; n < nu_coarse; ++n) sweep();
+    return n;
+  }
+  const double lim = coarse_rtol * norm();
+  const int group = nu_coarse > 1 ? nu_coarse : 1;
+  while (n < coarse_max) {
+    const int k = min(group, coarse_max - n);
+    for (int s2 = 0; s2 < k; ++s2) sweep();
+    n += k;
+    if (n < coarse_max && norm() <= lim) break;
+  }
+  return n;
+}
+
 // The coarsest level's smoothing (grp_coarsest) by the first wavefront or
 // the workgroup; returns the number of sweeps to every thread.
 template <typename T, typename TL>
@@ -387,7 +530,13 @@ __device__ __forceinline__ int tail_coarsest(const TailView<T, TL>& v, int nu_co
                                              double coarse_rtol, int coarse_max, T omega,
                                              int* count) {
   __shared__ double red;
-  if (v.g.n <= kWaveCells) {
+  const int pairs = ((v.g.nx + 1) >> 1) * v.g.ny * v.g.nz;
+  if (pairs <= kRegPairs) {
+    if (threadIdx.x < kWave) {
+      const int n = reg_coarsest<T, TL>(v, nu_coarse, coarse_rtol, coarse_max, omega, &red);
+      if (threadIdx.x == 0) *count = n;
+    }
+  } else if (v.g.n <= kWaveCells) {
     if (threadIdx.x < kWave) {
       const int n = grp_coarsest<T, TL, kWave>(v, nu_coarse, coarse_rtol, coarse_max, omega, &red);
       if (threadIdx.x == 0) *count = n;
