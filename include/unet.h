@@ -67,10 +67,23 @@ unet_status unet_conv_dgrad(unet_shape s, unet_act dy, const void* w, int32_t ta
 
 /* Weight and bias gradients: dw[o][t][c] = sum_v dy[v][o] x[v + t - 1][c],
  * db[o] = sum_v dy[v][o] (FP32 outputs, overwritten).  Deterministic split-K
- * over voxel chunks: ws is caller workspace of unet_wgrad_workspace() bytes. */
+ * over voxel chunks (FP32 partial rows summed in a fixed order): ws is caller
+ * workspace of unet_wgrad_workspace() bytes (0 for invalid arguments).
+ * Inputs: x.c = 8 or a multiple of 8, dy.c a multiple of 16, at most 128. */
 size_t unet_wgrad_workspace(unet_shape s, int32_t cin, int32_t cout, int32_t taps);
 unet_status unet_conv_wgrad(unet_shape s, unet_act x, unet_act dy, int32_t taps, float* dw,
                             float* db, void* ws, void* stream);
+
+/* Which weight-gradient kernel unet_conv_wgrad runs for these sizes (host
+ * only, no GPU call): info[0] = 1 for the row-tiled kernel (3x3x3 taps, w a
+ * multiple of 32 or w = 16, h a multiple of 4, 8 or a multiple of 16 input
+ * channels) else 0 for the voxel-chunk kernel; info[1..3] = input channels,
+ * output channels and w extent of one row-kernel workgroup (0 otherwise);
+ * info[4] = number of voxel chunks (partial rows); info[5] = d planes per
+ * chunk (row kernel).  info: 6 int32 written by the call.  UNET_EINVAL for a
+ * bad shape, channel count or taps. */
+unet_status unet_wgrad_kernel(unet_shape s, int32_t cin, int32_t cout, int32_t taps,
+                              int32_t* info);
 
 /* dy_pre = dy * (y > 0) (ReLU backward, in place on dy allowed). */
 unet_status unet_relu_bwd(unet_shape s, unet_act y, unet_act dy, unet_act out, void* stream);

@@ -62,6 +62,38 @@ def conv3d_backward(x, w, dy):
     return dx, dw, db
 
 
+def conv3d_points(x, w, b, pts):
+    """conv3d at selected voxels, from the definition: for each (d, h, w)
+    in pts, y[o] = b[o] + sum over c and taps t of w[o, c, t] x[c, v + t -
+    (k - 1) / 2] (zero outside the grid).  Returns y [len(pts), C_out]."""
+    k = w.shape[2]
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (p, p), (p, p), (p, p)))
+    out = np.zeros((len(pts), w.shape[0]))
+    for i, (d, h, ww) in enumerate(pts):
+        patch = xp[:, d:d + k, h:h + k, ww:ww + k]
+        out[i] = b + np.tensordot(w, patch, axes=([1, 2, 3, 4], [0, 1, 2, 3]))
+    return out
+
+
+def conv3d_wgrad_pairs(x, dy, pairs, k=3):
+    """Selected weight-gradient entries of conv3d, from the definition:
+    for each (o, c) in pairs, g[o, c][a, b, e] = sum over voxels v of
+    dy[o, v] x[c, v + (a, b, e) - (k - 1) / 2] (zero outside the grid), one
+    dot product per tap.  Returns (g [len(pairs), k, k, k], db[C_out] = sum
+    over voxels of dy[o])."""
+    p = k // 2
+    C, D, H, W = x.shape
+    xp = np.pad(x, ((0, 0), (p, p), (p, p), (p, p)))
+    out = np.zeros((len(pairs), k, k, k))
+    for i, (o, c) in enumerate(pairs):
+        for a in range(k):
+            for b in range(k):
+                for e in range(k):
+                    out[i, a, b, e] = np.sum(dy[o] * xp[c, a:a + D, b:b + H, e:e + W])
+    return out, dy.sum(axis=(1, 2, 3))
+
+
 def bf16(a):
     """Round to BF16 (round to nearest even on the FP32 bit pattern, after
     rounding to FP32) and return the value in FP64: the storage rounding of

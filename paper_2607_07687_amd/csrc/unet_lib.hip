@@ -113,12 +113,14 @@ __global__ void k_mfma_selfcheck(const uint16_t* A, const uint16_t* B, float* ou
 }
 
 // ---------------------------------------------------------------------------
-// Implicit-GEMM convolution forward: each wave computes 64 voxels (4 blocks
-// of 16) x NB*16 output channels; K steps of 32 = 4 lanes-groups x 8
-// consecutive input channels of one tap.
+// Implicit-GEMM convolution forward: each wave computes 16 MB voxels (MB
+// blocks of 16) x NB*16 output channels, the workgroup's output channels
+// starting at 16 NB blockIdx.y; K steps of 32 = 4 lane groups x 8
+// consecutive input channels of one tap.  Every output's K order is the same
+// for every (MB, NB), so the split does not change a bit of the result.
 // ---------------------------------------------------------------------------
 
-template <int NB>
+template <int MB, int NB>
 __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* __restrict__ x,
                                                   int xld, int xoff, int cin,
                                                   const uint16_t* __restrict__ w,
@@ -127,17 +129,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* 
                                                   float* __restrict__ yf, int relu) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long nvox = (long long)s.n * s.d * s.h * s.w;
-  const long long vbase = (long long)blockIdx.x * 256 + wave * 64;
+  const long long vbase = ((long long)blockIdx.x * 4 + wave) * (16 * MB);
+  const int co0 = blockIdx.y * (16 * NB);  // this workgroup's output channels
   const int K = taps * cin;
   const int ksteps = (K + 31) / 32;
   // Each of the lane's four voxels: its index (the host keeps voxel counts
   // below 2^31) and a mask of the taps that land inside the grid (bit t for
   // tap t in (kd, kh, kw) order; zero padding elsewhere).  A tap's neighbour
   // is then the voxel index plus an offset that is the same for every voxel.
-  int vi[4];
-  uint32_t vm[4];
+  int vi[MB];
+  uint32_t vm[MB];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
+  for (int mb = 0; mb < MB; ++mb) {
     const long long v = vbase + mb * 16 + (lane & 15);
     const bool ok = v < nvox;
     const Vox a = vox_of(ok ? v : 0, s);
@@ -163,48 +166,48 @@ __global__ __launch_bounds__(256) void k_conv_fwd(unet_shape s, const uint16_t* 
   // at a clamped k when the value is padding), and padding is zeroed after
   // the load, so that no branch sits between the loads of a step and the
   // next step's loads can be in flight while this step's MFMAs run.
-  auto load = [&](int ks, bf16x8 (&a)[4], bf16x8 (&b)[NB]) {
+  auto load = [&](int ks, bf16x8 (&a)[MB], bf16x8 (&b)[NB]) {
     const int k = ks * 32 + kl;
     const bool kin = k < K;
     const int kk = kin ? k : K - 8;
     const int t = (int)(((uint32_t)kk * rcin) >> 22), ci = kk - t * cin;
     const int off = (taps == 1) ? 0 : (t / 9 - 1) * hw + ((t / 3) % 3 - 1) * s.w + (t % 3 - 1);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
+    for (int mb = 0; mb < MB; ++mb) {
       const bool use = kin && ((vm[mb] >> t) & 1u);
       const bf16x8 v = ld8(x + (long long)(use ? vi[mb] + off : vi[mb]) * xld + xoff + ci);
       a[mb] = use ? v : zero8();
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const bf16x8 v = ld8(w + (long long)(nb * 16 + (lane & 15)) * K + kk);
+      const bf16x8 v = ld8(w + (long long)(co0 + nb * 16 + (lane & 15)) * K + kk);
       b[nb] = kin ? v : zero8();
     }
   };
-  f32x4 acc[4][NB];
+  f32x4 acc[MB][NB];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 a0[4], b0[NB], a1[4], b1[NB];
+  bf16x8 a0[MB], b0[NB], a1[MB], b1[NB];
   load(0, a0, b0);
   for (int ks = 0; ks < ksteps; ++ks) {
     load(ks + 1 < ksteps ? ks + 1 : ks, a1, b1);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
         acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[mb], b0[nb], acc[mb][nb], 0, 0, 0);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) a0[mb] = a1[mb];
+    for (int mb = 0; mb < MB; ++mb) a0[mb] = a1[mb];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) b0[nb] = b1[nb];
   }
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int co = nb * 16 + (lane & 15);
+      const int co = co0 + nb * 16 + (lane & 15);
       const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -244,6 +247,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
   constexpr int kSW = kTW + 2, kSH = kTH + 2, kSlots = 3 * kSH * kSW;
   __shared__ __align__(16) uint16_t tile[kSlots * CIN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int co0 = blockIdx.y * (16 * NB);  // this workgroup's output channels
   const int tw = s.w / kTW, th = s.h / kTH;
   int b = blockIdx.x;
   const int w0 = (b % tw) * kTW;
@@ -299,7 +303,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const bf16x8 v = ld8(w + (long long)(nb * 16 + (lane & 15)) * K + kk);
+      const bf16x8 v = ld8(w + (long long)(co0 + nb * 16 + (lane & 15)) * K + kk);
       bb[nb] = kin ? v : zero8();
     }
 #pragma unroll
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
   for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int co = nb * 16 + (lane & 15);
+      const int co = co0 + nb * 16 + (lane & 15);
       const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(unet_shape s, const uint16_t
                                                     int xld, int xoff, int cin,
                                                     const uint16_t* __restrict__ dy, int dld,
                                                     int doff, int taps, long long vchunk,
-                                                    float* __restrict__ ws) {
+                                                    long long rs, float* __restrict__ ws) {
   constexpr int COUT = OB * 16;
   __shared__ uint16_t sdy[COUT][40];  // [o][v], padded rows
   __shared__ uint16_t sx[64][40];     // [k][v]
@@ -413,8 +417,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(unet_shape s, const uint16_t
     }
     __syncthreads();
   }
-  // partial dW of this chunk: ws[chunk][o][k]
-  float* out = ws + (long long)blockIdx.y * COUT * K;
+  // partial dW of this chunk: ws[chunk * rs + o K + k]
+  float* out = ws + (long long)blockIdx.y * rs;
 #pragma unroll
   for (int ob = 0; ob < OB; ++ob)
 #pragma unroll
@@ -425,27 +429,300 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(unet_shape s, const uint16_t
     }
 }
 
-// Per-chunk channel sums of dy (bias gradient partials): wsb[chunk][o].
+// Per-chunk channel sums of dy (bias gradient partials): wsb[chunk * rs + o].
 __global__ __launch_bounds__(256) void k_bias_partial(unet_shape s, const uint16_t* __restrict__ dy,
                                                       int dld, int doff, int cout, long long vchunk,
-                                                      float* __restrict__ wsb) {
+                                                      long long rs, float* __restrict__ wsb) {
   const long long nvox = (long long)s.n * s.d * s.h * s.w;
   const long long v0 = (long long)blockIdx.x * vchunk, v1 = min(nvox, v0 + vchunk);
   for (int o = threadIdx.x; o < cout; o += blockDim.x) {
     float acc = 0.f;
     for (long long v = v0; v < v1; ++v) acc += bf2f(dy[v * dld + doff + o]);
-    wsb[(long long)blockIdx.x * cout + o] = acc;
+    wsb[(long long)blockIdx.x * rs + o] = acc;
   }
 }
 
-// out[i] = sum over chunks of ws[chunk][i] in chunk order.
-__global__ void k_sum_chunks(const float* __restrict__ ws, long long n, int nchunks,
-                             float* __restrict__ out) {
+// out[i] = sum over c of ws[c * n + i] (i < n), in two levels when there are
+// more than 64 chunks: workgroup (64 outputs, group g) sums chunks
+// [64 g, 64 g + 64), each wave 16 of them in order, the four wave sums added
+// in wave order, into tmp[g * n + i]; k_sum_split then adds the groups in
+// order.  The order depends only on the chunk count: deterministic.
+__global__ __launch_bounds__(256) void k_sum_groups(const float* __restrict__ ws, long long n,
+                                                    int nchunks, float* __restrict__ tmp) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long i = (long long)blockIdx.x * 64 + lane;
+  const int c0 = blockIdx.y * 64 + wave * 16, c1 = min(nchunks, c0 + 16);
+  float acc = 0.f;
+  if (i < n)
+    for (int c = c0; c < c1; ++c) acc += ws[(long long)c * n + i];
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && i < n)
+    tmp[(long long)blockIdx.y * n + i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// Sum of the nchunks rows of ws (row length n) in row order; entries below nw
+// go to dw, the rest to db.
+__global__ void k_sum_split(const float* __restrict__ ws, long long n, int nchunks, long long nw,
+                            float* __restrict__ dw, float* __restrict__ db) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc = 0.f;
   for (int c = 0; c < nchunks; ++c) acc += ws[(long long)c * n + i];
-  out[i] = acc;
+  if (i < nw)
+    dw[i] = acc;
+  else
+    db[i - nw] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient, row-tiled form.  Workgroup = one voxel chunk (sample n, a
+// range of d planes, a block of 4 h rows, a w segment of WS voxels) x one
+// channel part (OT outputs x CT inputs).  The workgroup walks its planes in
+// order.  Each input plane's rows h0-1 .. h0+4 (w0-1 .. w0+WS, zeros outside
+// the grid) are staged channel-major in a 3-slot LDS ring, so that the 8
+// voxels a lane feeds to the MFMA are contiguous and the three w taps of one
+// (d, h) tap row come from one 16-byte and one 4-byte LDS read, shifted by 0,
+// 1 or 2 elements in registers.  The plane's dy rows are staged the same way.
+// A unit is 32 voxels (a row of 32, or two rows of 16).  Wave q owns one
+// 16 x 16 (output, input) channel block and all 27 taps for units
+// q / P, q / P + 4 / P, ... of every plane, plus the bias sums (an MFMA
+// against ones) when its input block is the part's first and the part starts
+// at input channel 0.  Waves that share a channel block add their sums in
+// wave order at the end.  Output: the chunk's row of ws, ws[chunk * rs + ...]
+// with dW at o * 27 cin + t cin + c and the bias sums at cout * 27 cin + o.
+// The next plane's loads are issued before the current plane's MFMAs.
+// ---------------------------------------------------------------------------
+
+struct WgradRowsArgs {
+  unet_shape s;
+  const uint16_t* x;
+  int xld, xoff, cin;
+  const uint16_t* dy;
+  int dld, doff, cout;
+  int nws, nhb, nds, dper, ncp;  // w segments, 4-row blocks, d ranges, planes per range, input parts
+  long long rs;                  // ws row stride (floats)
+  float* ws;
+};
+
+__device__ __forceinline__ uint32_t pack_lo(uint32_t a, uint32_t b) {
+  return (a & 0xFFFFu) | (b << 16);
+}
+__device__ __forceinline__ uint32_t pack_hi(uint32_t a, uint32_t b) {
+  return (a >> 16) | (b & 0xFFFF0000u);
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const uint4 v = make_uint4(a, b, c, d);
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+// Four voxels x 8 channels (one 16-byte load per voxel) written channel-major:
+// row e of dst (pitch elements apart) receives the 4 voxels' channel e.
+__device__ __forceinline__ void store_quad_t(uint16_t* dst, int pitch, const uint4 (&r)[4]) {
+  const uint32_t v0[4] = {r[0].x, r[0].y, r[0].z, r[0].w};
+  const uint32_t v1[4] = {r[1].x, r[1].y, r[1].z, r[1].w};
+  const uint32_t v2[4] = {r[2].x, r[2].y, r[2].z, r[2].w};
+  const uint32_t v3[4] = {r[3].x, r[3].y, r[3].z, r[3].w};
+#pragma unroll
+  for (int e2 = 0; e2 < 4; ++e2) {
+    *reinterpret_cast<uint2*>(dst + (2 * e2) * pitch) =
+        make_uint2(pack_lo(v0[e2], v1[e2]), pack_lo(v2[e2], v3[e2]));
+    *reinterpret_cast<uint2*>(dst + (2 * e2 + 1) * pitch) =
+        make_uint2(pack_hi(v0[e2], v1[e2]), pack_hi(v2[e2], v3[e2]));
+  }
+}
+
+template <int CT, int OT, int WS>
+__global__ __launch_bounds__(256, 2) void k_wgrad_rows(WgradRowsArgs a) {
+  constexpr int CTP = CT < 16 ? 16 : CT;       // staged input channels (8 padded to 16)
+  constexpr int NCB = CTP / 16;                // 16-channel input blocks
+  constexpr int P = (OT / 16) * NCB;           // channel blocks per workgroup
+  constexpr int RPW = 4 / P;                   // waves per channel block
+  constexpr int RU = 32 / WS;                  // rows per 32-voxel unit
+  constexpr int U = 4 / RU;                    // units per plane
+  constexpr int XQ = (WS + 5) / 4;             // 4-voxel groups per staged row (WS + 2)
+  constexpr int XP = WS == 32 ? 40 : 24;       // staged row pitch (elements)
+  constexpr int XO = 8 * XP + 8;               // 8-channel group stride
+  constexpr int XR = 2 * NCB * XO;             // one staged row, all channels
+  constexpr int XPL = 6 * XR;                  // one plane slot (6 rows)
+  constexpr int DP = 40, DO = 8 * DP + 8, DU = (OT / 8) * DO;
+  constexpr int NX = 6 * XQ * (CT / 8);        // x staging items per plane
+  constexpr int ND = 4 * (WS / 4) * (OT / 8);  // dy staging items per plane
+  constexpr int SM = 3 * XPL + U * DU;         // LDS elements (ring, then dy rows)
+  // the final sums pass TG taps of every wave at a time through LDS
+  constexpr int TG = 4 * 9 * 4 * 64 * 4 <= SM * 2 ? 9 : (4 * 3 * 4 * 64 * 4 <= SM * 2 ? 3 : 1);
+  static_assert(P >= 1 && P <= 4 && 4 % P == 0, "channel blocks per workgroup");
+  static_assert(NX <= 256 && ND <= 256, "one staging item per thread");
+  static_assert(4 * TG * 4 * 64 * 4 <= SM * 2, "final sums fit in LDS");
+  __shared__ __align__(16) uint16_t smem[SM];
+  uint16_t* const xs = smem;
+  uint16_t* const ds = smem + 3 * XPL;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int D = a.s.d, H = a.s.h, W = a.s.w;
+  // chunks grouped per XCD: dispatch order sends block b to XCD b % 8
+  const int nchunk = gridDim.x;
+  int chunk = blockIdx.x;
+  if ((nchunk & 7) == 0) chunk = (blockIdx.x & 7) * (nchunk >> 3) + (blockIdx.x >> 3);
+  int t = chunk;
+  const int wsg = t % a.nws;
+  t /= a.nws;
+  const int hb = t % a.nhb;
+  t /= a.nhb;
+  const int dsi = t % a.nds;
+  const int n = t / a.nds;
+  const int c0 = (blockIdx.y % a.ncp) * CT, o0 = (blockIdx.y / a.ncp) * OT;
+  const int w0 = wsg * WS, h0 = hb * 4;
+  const int d0 = dsi * a.dper, d1 = min(D, d0 + a.dper);
+  const long long plane = (long long)H * W;
+  const long long nbase = (long long)n * D * plane;
+
+  // staging items: x (staged row, 8-channel group, 4-voxel group), dy (row, group, 4 voxels)
+  const bool xitem = tid < NX;
+  const int xq = tid % XQ, xoc = (tid / XQ) % (CT / 8), xrow = tid / (XQ * (CT / 8));
+  const int xh = h0 - 1 + xrow;
+  const bool xrow_ok = xitem && xh >= 0 && xh < H;
+  const bool ditem = tid < ND;
+  const int dq = tid % (WS / 4), doc = (tid / (WS / 4)) % (OT / 8), drow = tid / ((WS / 4) * (OT / 8));
+  uint4 rx[4], rd[4];
+  auto load_x = [&](int p) {
+    const bool ok = xrow_ok && p >= 0 && p < D;
+    const long long vrow = nbase + (long long)p * plane + (long long)xh * W;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int w = w0 - 1 + 4 * xq + j;
+      rx[j] = make_uint4(0, 0, 0, 0);
+      if (ok && w >= 0 && w < W && 4 * xq + j < WS + 2)
+        rx[j] = *reinterpret_cast<const uint4*>(a.x + (vrow + w) * a.xld + a.xoff + c0 + 8 * xoc);
+    }
+  };
+  auto store_x = [&](int slot) {
+    if (xitem) store_quad_t(xs + slot * XPL + xrow * XR + xoc * XO + 4 * xq, XP, rx);
+  };
+  auto load_dy = [&](int p) {
+    const long long v = nbase + (long long)p * plane + (long long)(h0 + drow) * W + w0 + 4 * dq;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      rd[j] = make_uint4(0, 0, 0, 0);
+      if (ditem) rd[j] = *reinterpret_cast<const uint4*>(a.dy + (v + j) * a.dld + a.doff + o0 + 8 * doc);
+    }
+  };
+  auto store_dy = [&]() {
+    if (ditem) store_quad_t(ds + (drow / RU) * DU + doc * DO + (drow % RU) * WS + 4 * dq, DP, rd);
+  };
+
+  if (CT == 8) {  // padded input channels 8..15 stay zero
+    for (int i = tid; i < 3 * 6 * (XO / 8); i += 256) {
+      const int sr = i / (XO / 8), off = i % (XO / 8);
+      *reinterpret_cast<uint4*>(xs + sr * XR + XO + 8 * off) = make_uint4(0, 0, 0, 0);
+    }
+  }
+  load_x(d0 - 1);
+  store_x(0);
+  load_x(d0);
+  store_x(1);
+  load_x(d0 + 1);
+  store_x(2);
+  load_dy(d0);
+  store_dy();
+  __syncthreads();
+  if (d0 + 1 < d1) {
+    load_x(d0 + 2);
+    load_dy(d0 + 1);
+  }
+
+  const int cblk = wave % P, rsub = wave / P;
+  const int ob = cblk / NCB, cb = cblk % NCB;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int oo = ob * 16 + l16;
+  const int aoff = (oo >> 3) * DO + (oo & 7) * DP + 8 * g;
+  const int ci = cb * 16 + l16;
+  const int boff = (ci >> 3) * XO + (ci & 7) * XP + (RU == 2 ? 8 * (g & 1) : 8 * g);
+  const int grow = RU == 2 ? (g >> 1) : 0;
+  const bool do_bias = cb == 0 && c0 == 0;
+  const bf16x8 ones = as_bf16x8(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u);
+  f32x4 acc[27], bacc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 27; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int d = d0; d < d1; ++d) {
+    for (int u = rsub; u < U; u += RPW) {
+      const bf16x8 av = ld8(ds + u * DU + aoff);
+      if (do_bias) bacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, bacc, 0, 0, 0);
+      const int lr = u * RU + grow;  // row of the 4-row block
+#pragma unroll
+      for (int kd = 0; kd < 3; ++kd) {
+        const uint16_t* xb = xs + ((d + kd - d0) % 3) * XPL + boff + lr * XR;
+#pragma unroll
+        for (int kh = 0; kh < 3; ++kh) {
+          const uint16_t* pb = xb + kh * XR;
+          const uint4 q = *reinterpret_cast<const uint4*>(pb);
+          const uint32_t q4 = *reinterpret_cast<const uint32_t*>(pb + 8);
+          const int tp = 9 * kd + 3 * kh;
+          acc[tp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(q.x, q.y, q.z, q.w),
+                                                            acc[tp], 0, 0, 0);
+          acc[tp + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              av,
+              as_bf16x8(__builtin_amdgcn_alignbit(q.y, q.x, 16), __builtin_amdgcn_alignbit(q.z, q.y, 16),
+                        __builtin_amdgcn_alignbit(q.w, q.z, 16), __builtin_amdgcn_alignbit(q4, q.w, 16)),
+              acc[tp + 1], 0, 0, 0);
+          acc[tp + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(q.y, q.z, q.w, q4),
+                                                                acc[tp + 2], 0, 0, 0);
+        }
+      }
+    }
+    if (d + 1 < d1) {
+      __syncthreads();
+      store_x((d + 3 - d0) % 3);  // plane d + 2 replaces plane d - 1
+      store_dy();                 // plane d + 1
+      __syncthreads();
+      if (d + 2 < d1) {
+        load_x(d + 3);
+        load_dy(d + 2);
+      }
+    }
+  }
+
+  // Final sums: each wave parks TG taps of its tiles in LDS; the threads add
+  // the RPW waves of each channel block in wave order and store the chunk's
+  // row (16 consecutive input channels per lane group).
+  float* const red = reinterpret_cast<float*>(smem);
+  const int K = 27 * a.cin;
+  float* const row = a.ws + (long long)chunk * a.rs;
+#pragma unroll
+  for (int grp = 0; grp < 27 / TG; ++grp) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TG; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[((wave * TG + i) * 4 + e) * 64 + lane] = acc[TG * grp + i][e];
+    __syncthreads();
+    for (int idx = tid; idx < P * TG * 4 * 64; idx += 256) {
+      const int ln = idx & 63, e = (idx >> 6) & 3, i = (idx >> 8) % TG, cbk = (idx >> 8) / TG;
+      float v = 0.f;
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) v += red[(((cbk + P * rr) * TG + i) * 4 + e) * 64 + ln];
+      const int c = (cbk % NCB) * 16 + (ln & 15);
+      const int o = o0 + (cbk / NCB) * 16 + 4 * (ln >> 4) + e;
+      if (c < CT) row[(long long)o * K + (TG * grp + i) * a.cin + c0 + c] = v;
+    }
+  }
+  if (c0 == 0) {  // bias sums: blocks whose input block is the first
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[(wave * 4 + e) * 64 + lane] = bacc[e];
+    __syncthreads();
+    if (tid < (OT / 16) * 16) {
+      const int obk = tid >> 4, e = tid & 3, gg = (tid >> 2) & 3;
+      float v = 0.f;
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr) v += red[((obk * NCB + P * rr) * 4 + e) * 64 + 16 * gg];
+      row[(long long)a.cout * K + o0 + obk * 16 + 4 * gg + e] = v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +837,191 @@ __global__ __launch_bounds__(256) void k_head_wgrad_partial(long long nvox, int 
     for (long long v = v0; v < v1; ++v)
       acc += dy[v] * (ch < c ? bf2f(x[v * xld + xoff + ch]) : 1.f);
     wsp[(long long)blockIdx.x * (c + 1) + ch] = acc;
+  }
+}
+
+// ---- 8-channel forms (16-byte accesses) for channel counts that are
+// multiples of 8: one thread per (voxel, 8-channel group); the arithmetic and
+// its order per element are those of the one-channel kernels above.
+__device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ void st16(uint16_t* p, const uint4& v) { *reinterpret_cast<uint4*>(p) = v; }
+__device__ __forceinline__ void unpack8(const uint4& r, float (&f)[8]) {
+  const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    f[2 * e] = __uint_as_float(u[e] << 16);
+    f[2 * e + 1] = __uint_as_float(u[e] & 0xFFFF0000u);
+  }
+}
+__device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
+  uint32_t u[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) u[e] = (uint32_t)f2bf(f[2 * e]) | ((uint32_t)f2bf(f[2 * e + 1]) << 16);
+  return make_uint4(u[0], u[1], u[2], u[3]);
+}
+
+__global__ void k_relu_bwd8(long long nvox, int g8, const uint16_t* __restrict__ y, int yld,
+                            int yoff, const uint16_t* __restrict__ dy, int dld, int doff,
+                            uint16_t* __restrict__ out, int old, int ooff) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * g8) return;
+  const long long v = i / g8;
+  const int c = (int)(i - v * g8) * 8;
+  float fy[8];
+  unpack8(ld16(y + v * yld + yoff + c), fy);
+  const uint4 d = ld16(dy + v * dld + doff + c);
+  const uint32_t du[4] = {d.x, d.y, d.z, d.w};
+  uint32_t o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    o[e] = (fy[2 * e] > 0.f ? (du[e] & 0xFFFFu) : 0u) | (fy[2 * e + 1] > 0.f ? (du[e] & 0xFFFF0000u) : 0u);
+  st16(out + v * old + ooff + c, make_uint4(o[0], o[1], o[2], o[3]));
+}
+
+__global__ void k_pool_fwd8(unet_shape f, int g8, const uint16_t* __restrict__ x, int xld, int xoff,
+                            uint16_t* __restrict__ y, int yld, int yoff) {
+  unet_shape cs{f.n, f.d / 2, f.h / 2, f.w / 2};
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ncv = (long long)cs.n * cs.d * cs.h * cs.w;
+  if (i >= ncv * g8) return;
+  const long long V = i / g8;
+  const int c = (int)(i - V * g8) * 8;
+  const Vox a = vox_of(V, cs);
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 8; ++q) {
+    const Vox b{a.n, 2 * a.d + (q >> 2), 2 * a.h + ((q >> 1) & 1), 2 * a.w + (q & 1)};
+    float fx[8];
+    unpack8(ld16(x + vox_index(b, f) * xld + xoff + c), fx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] += fx[e];
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) acc[e] *= 0.125f;
+  st16(y + V * yld + yoff + c, pack8(acc));
+}
+
+__global__ void k_pool_bwd8(unet_shape f, int g8, const uint16_t* __restrict__ dy, int dld,
+                            int doff, uint16_t* __restrict__ dx, int xld, int xoff, int accumulate) {
+  unet_shape cs{f.n, f.d / 2, f.h / 2, f.w / 2};
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nfv = (long long)f.n * f.d * f.h * f.w;
+  if (i >= nfv * g8) return;
+  const long long v = i / g8;
+  const int c = (int)(i - v * g8) * 8;
+  const Vox a = vox_of(v, f);
+  const Vox b{a.n, a.d / 2, a.h / 2, a.w / 2};
+  float g[8];
+  unpack8(ld16(dy + vox_index(b, cs) * dld + doff + c), g);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) g[e] *= 0.125f;
+  if (accumulate) {
+    float o[8];
+    unpack8(ld16(dx + v * xld + xoff + c), o);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g[e] += o[e];
+  }
+  st16(dx + v * xld + xoff + c, pack8(g));
+}
+
+__global__ void k_up_fwd8(unet_shape cs, int g8, const uint16_t* __restrict__ x, int xld, int xoff,
+                          uint16_t* __restrict__ y, int yld, int yoff) {
+  const unet_shape f{cs.n, 2 * cs.d, 2 * cs.h, 2 * cs.w};
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nfv = (long long)f.n * f.d * f.h * f.w;
+  if (i >= nfv * g8) return;
+  const long long v = i / g8;
+  const int c = (int)(i - v * g8) * 8;
+  const Vox a = vox_of(v, f);
+  const Vox b{a.n, a.d / 2, a.h / 2, a.w / 2};
+  st16(y + v * yld + yoff + c, ld16(x + vox_index(b, cs) * xld + xoff + c));
+}
+
+__global__ void k_up_bwd8(unet_shape cs, int g8, const uint16_t* __restrict__ dy, int dld, int doff,
+                          uint16_t* __restrict__ dx, int xld, int xoff) {
+  const unet_shape f{cs.n, 2 * cs.d, 2 * cs.h, 2 * cs.w};
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ncv = (long long)cs.n * cs.d * cs.h * cs.w;
+  if (i >= ncv * g8) return;
+  const long long V = i / g8;
+  const int c = (int)(i - V * g8) * 8;
+  const Vox a = vox_of(V, cs);
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 8; ++q) {
+    const Vox b{a.n, 2 * a.d + (q >> 2), 2 * a.h + ((q >> 1) & 1), 2 * a.w + (q & 1)};
+    float g[8];
+    unpack8(ld16(dy + vox_index(b, f) * dld + doff + c), g);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] += g[e];
+  }
+  st16(dx + V * xld + xoff + c, pack8(acc));
+}
+
+__global__ void k_head_fwd8(long long nvox, int g8, const uint16_t* __restrict__ x, int xld,
+                            int xoff, const float* __restrict__ w, const float* __restrict__ b,
+                            float* __restrict__ y) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  float acc = 0.f;
+  for (int g = 0; g < g8; ++g) {
+    float fx[8];
+    unpack8(ld16(x + v * xld + xoff + 8 * g), fx);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += w[8 * g + e] * fx[e];
+  }
+  y[v] = acc + b[0];
+}
+
+__global__ void k_head_dgrad8(long long nvox, int g8, const float* __restrict__ w,
+                              const float* __restrict__ dy, uint16_t* __restrict__ dx, int xld,
+                              int xoff) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * g8) return;
+  const long long v = i / g8;
+  const int c = (int)(i - v * g8) * 8;
+  const float d = dy[v];
+  float o[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) o[e] = w[c + e] * d;
+  st16(dx + v * xld + xoff + c, pack8(o));
+}
+
+// Head weight-gradient partials, 8-channel form: workgroup = voxel chunk,
+// thread (j, g) sums voxels v0 + j, v0 + j + J, ... for channels 8g..8g+7
+// (g = 0 also the bias column); the J voxel lanes are then added by a fixed
+// pairwise tree in LDS.  wsp[chunk][c + 1] as k_head_wgrad_partial.
+__global__ __launch_bounds__(256) void k_head_wgrad8(long long nvox, int g8,
+                                                     const uint16_t* __restrict__ x, int xld,
+                                                     int xoff, const float* __restrict__ dy,
+                                                     long long vchunk, float* __restrict__ wsp) {
+  __shared__ float red[256][9];
+  const int tid = threadIdx.x, J = 256 / g8;
+  const int g = tid % g8, j = tid / g8;
+  const long long v0 = (long long)blockIdx.x * vchunk, v1 = min(nvox, v0 + vchunk);
+  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (j < J) {
+    for (long long v = v0 + j; v < v1; v += J) {
+      const float d = dy[v];
+      float fx[8];
+      unpack8(ld16(x + v * xld + xoff + 8 * g), fx);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc[e] += d * fx[e];
+      acc[8] += d;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) red[tid][e] = acc[e];
+  __syncthreads();
+  for (int st = 1; st < J; st *= 2) {
+    if (j < J && j % (2 * st) == 0 && j + st < J)
+#pragma unroll
+      for (int e = 0; e < 9; ++e) red[tid][e] += red[tid + st * g8][e];
+    __syncthreads();
+  }
+  if (j == 0) {
+    const int c = g8 * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wsp[(long long)blockIdx.x * (c + 1) + 8 * g + e] = red[g][e];
+    if (g == 0) wsp[(long long)blockIdx.x * (c + 1) + c] = red[0][8];
   }
 }
 
@@ -701,6 +1163,91 @@ long long wgrad_chunk(long long nvox) {
   return c;
 }
 
+
+// Groups of 64 chunk rows summed first when there are more than 64 rows.
+long long sum_groups(long long nchunk) { return nchunk > 64 ? (nchunk + 63) / 64 : 0; }
+
+// Fixed-order sum of nchunk partial rows ws[c * rs + i] (i < rs): entries
+// below nw go to dw, the rest to db.  Groups of 64 rows first (into the
+// sum_groups(nchunk) rows after the partials) when there are more.
+void enq_sum_rows(float* ws, long long nchunk, long long rs, long long nw, float* dw, float* db,
+                  hipStream_t st) {
+  const float* rows = ws;
+  long long nrows = nchunk;
+  const long long ng = sum_groups(nchunk);
+  if (ng > 0) {
+    float* tmp = ws + nchunk * rs;
+    hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((rs + 63) / 64), (unsigned)ng), dim3(256), 0,
+                       st, ws, rs, (int)nchunk, tmp);
+    rows = tmp;
+    nrows = ng;
+  }
+  hipLaunchKernelGGL(k_sum_split, dim3((unsigned)((rs + 255) / 256)), dim3(256), 0, st, rows, rs,
+                     (int)nrows, nw, dw, db);
+}
+
+// Launch plan of the weight gradient.  Row kernel when the grid tiles into
+// 4-row blocks of 32-voxel rows (w a multiple of 32) or row pairs (w = 16),
+// with 8 or a multiple of 16 input channels and 3x3x3 taps; otherwise the
+// voxel-chunk kernel.  Channel parts start at 32 x 32 and are halved while the
+// grid would have fewer than 512 workgroups; d ranges of at least 4 planes
+// then bring it to about 1024, while the partial rows stay within 8 Mi floats.
+struct WgradPlan {
+  bool rows;
+  int ct, ot, ws, nws, nhb, nds, dper, ncp, nop;
+  long long nchunk, ngroup, rs, vchunk;
+};
+
+WgradPlan wgrad_plan(unet_shape s, int cin, int cout, int taps) {
+  WgradPlan p{};
+  const long long nv = (long long)s.n * s.d * s.h * s.w;
+  p.rs = (long long)cout * taps * cin + cout;
+  const int ws = s.w % 32 == 0 ? 32 : (s.w == 16 ? 16 : 0);
+  p.rows = taps == 27 && ws > 0 && s.h % 4 == 0 && (cin == 8 || cin % 16 == 0) && cout % 16 == 0;
+  if (p.rows) {
+    auto blocks = [](int ot, int ct) { return (ot / 16) * (std::max(ct, 16) / 16); };
+    const int pmin = ws == 16 ? 2 : 1;  // a 4-row block of w = 16 holds only 2 units
+    int ot = cout % 32 == 0 ? 32 : 16;
+    int ct = cin == 8 ? 8 : (cin % 32 == 0 ? 32 : 16);
+    const long long cols = (long long)s.n * (s.w / ws) * (s.h / 4);
+    const int maxnds = std::max(1, s.d / 4);
+    for (;;) {
+      const long long base = cols * (cin / ct) * (cout / ot);
+      if (base * maxnds >= 512) break;
+      if (ot == 32 && ot >= ct && blocks(16, ct) >= pmin)
+        ot = 16;
+      else if (ct == 32 && blocks(ot, 16) >= pmin)
+        ct = 16;
+      else
+        break;
+    }
+    p.rows = blocks(ot, ct) >= pmin;
+    if (p.rows) {
+      p.ct = ct;
+      p.ot = ot;
+      p.ws = ws;
+      p.nws = s.w / ws;
+      p.nhb = s.h / 4;
+      p.ncp = cin / ct;
+      p.nop = cout / ot;
+      const long long base = cols * p.ncp * p.nop;
+      const long long want = (1024 + base - 1) / base;
+      int nds = (int)std::min<long long>(maxnds, std::max<long long>(1, want));
+      // partial rows beyond 8 Mi floats cost more to sum than the split gains
+      while (nds > 1 && cols * nds * p.rs > (8LL << 20)) nds = (nds + 1) / 2;
+      p.dper = (s.d + nds - 1) / nds;
+      p.nds = (s.d + p.dper - 1) / p.dper;
+      p.nchunk = cols * p.nds;
+    }
+  }
+  if (!p.rows) {
+    p.vchunk = wgrad_chunk(nv);
+    p.nchunk = (nv + p.vchunk - 1) / p.vchunk;
+  }
+  p.ngroup = sum_groups(p.nchunk);
+  return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -725,17 +1272,27 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
       (!out_f32 && !y.p))
     return ufail(UNET_EINVAL, "bad output view (c multiple of 16, <= 128)");
   const long long nv = nvox_of(s);
-  const dim3 grid(nblk(nv, 256));
   hipStream_t st = (hipStream_t)stream;
   const uint16_t* xp = (const uint16_t*)x.p;
   const uint16_t* wp = (const uint16_t*)w;
   uint16_t* yp = (uint16_t*)y.p;
+  const int ob = y.c / 16;  // 16-channel output blocks
+  if (ob != 1 && ob != 2 && ob != 4 && ob != 8)
+    return ufail(UNET_EINVAL, "output channels must be 16, 32, 64 or 128");
   // LDS-tiled form for grids with w a multiple of 64 and h of 4, or w = 32
-  // and h a multiple of 8; 8 to 64 input channels and 16 to 64 output channels
+  // and h a multiple of 8; 8 to 64 input channels and 16 to 64 output
+  // channels.  Small grids split the output channels over workgroups until
+  // every CU has as many workgroups as its LDS holds (measured on 32^3 grids:
+  // 32 -> 64 channels 188 -> 302 TFLOP/s, 64 -> 64 220 -> 308).
   const bool t64 = s.w % 64 == 0 && s.h % 4 == 0, t32 = s.w == 32 && s.h % 8 == 0;
   if (taps == 27 && (t64 || t32) && (x.c == 8 || x.c == 16 || x.c == 32 || x.c == 64) &&
-      (y.c == 16 || y.c == 32 || y.c == 64)) {
-    const dim3 tg((unsigned)(nv / 256));
+      ob <= 4) {
+    const long long tiles = nv / 256;
+    const long long lds = 3LL * (256 / (t64 ? 64 : 32) + 2) * ((t64 ? 64 : 32) + 2) * x.c * 2;
+    const long long target = 256 * std::min<long long>(4, (160 * 1024) / lds);
+    int nb = ob;
+    while (nb > 1 && tiles * (ob / nb) < target) nb /= 2;
+    const dim3 tg((unsigned)tiles, (unsigned)(ob / nb));
     auto go = [&](auto cinc, auto nbc) {
       constexpr int CIN = decltype(cinc)::value, NB = decltype(nbc)::value;
       if (t64)
@@ -746,9 +1303,9 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
                            x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
     };
     auto by_out = [&](auto cinc) {
-      if (y.c == 16)
+      if (nb == 1)
         go(cinc, std::integral_constant<int, 1>{});
-      else if (y.c == 32)
+      else if (nb == 2)
         go(cinc, std::integral_constant<int, 2>{});
       else
         go(cinc, std::integral_constant<int, 4>{});
@@ -764,26 +1321,35 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
     UHIP(hipGetLastError());
     return UNET_OK;
   }
-  switch (y.c / 16) {
-    case 1:
-      hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp, bias,
-                         taps, yp, y.ld, y.off, out_f32, relu);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_conv_fwd<2>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp, bias,
-                         taps, yp, y.ld, y.off, out_f32, relu);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp, bias,
-                         taps, yp, y.ld, y.off, out_f32, relu);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_conv_fwd<8>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp, bias,
-                         taps, yp, y.ld, y.off, out_f32, relu);
-      break;
-    default:
-      return ufail(UNET_EINVAL, "output channels must be 16, 32, 64 or 128");
+  // Gathered form: the widest output-channel block per wave that still gives
+  // every CU a workgroup, with 64 voxels per wave, else 16 (measured: 16^3
+  // grids 18-21 -> 54-88 TFLOP/s, 32^3 with 128 channels 105-126 -> 170-180).
+  int mb = 4, nb = ob;
+  auto wgs = [&](int m, int b) { return ((nv + 64 * m - 1) / (64 * m)) * (ob / b); };
+  while (nb > 1 && wgs(4, nb) < 256) nb /= 2;
+  if (wgs(4, nb) < 256) {
+    mb = 1;
+    nb = ob;
+    while (nb > 1 && wgs(1, nb) < 256) nb /= 2;
   }
+  const dim3 grid((unsigned)((nv + 64 * mb - 1) / (64 * mb)), (unsigned)(ob / nb));
+  auto launch = [&](auto mbc, auto nbc) {
+    constexpr int MB = decltype(mbc)::value, NB = decltype(nbc)::value;
+    hipLaunchKernelGGL((k_conv_fwd<MB, NB>), grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp,
+                       bias, taps, yp, y.ld, y.off, out_f32, relu);
+  };
+  auto by_nb = [&](auto mbc) {
+    switch (nb) {
+      case 1: launch(mbc, std::integral_constant<int, 1>{}); break;
+      case 2: launch(mbc, std::integral_constant<int, 2>{}); break;
+      case 4: launch(mbc, std::integral_constant<int, 4>{}); break;
+      default: launch(mbc, std::integral_constant<int, 8>{}); break;
+    }
+  };
+  if (mb == 4)
+    by_nb(std::integral_constant<int, 4>{});
+  else
+    by_nb(std::integral_constant<int, 1>{});
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -801,10 +1367,24 @@ unet_status unet_conv_dgrad(unet_shape s, unet_act dy, const void* w, int32_t ta
 }
 
 size_t unet_wgrad_workspace(unet_shape s, int32_t cin, int32_t cout, int32_t taps) {
-  const long long nv = nvox_of(s);
-  const long long ch = wgrad_chunk(nv);
-  const long long nc = (nv + ch - 1) / ch;
-  return (size_t)(nc * ((long long)cout * cin * taps + cout)) * sizeof(float);
+  if (!shape_ok(s) || cin <= 0 || cout <= 0 || (taps != 27 && taps != 1)) return 0;
+  const WgradPlan p = wgrad_plan(s, cin, cout, taps);
+  return (size_t)((p.nchunk + p.ngroup) * p.rs) * sizeof(float);
+}
+
+unet_status unet_wgrad_kernel(unet_shape s, int32_t cin, int32_t cout, int32_t taps,
+                              int32_t* info) {
+  if (!info || !shape_ok(s) || cin <= 0 || cin % 8 || cout <= 0 || cout % 16 || cout > 128 ||
+      (taps != 27 && taps != 1))
+    return ufail(UNET_EINVAL, "bad wgrad_kernel args");
+  const WgradPlan p = wgrad_plan(s, cin, cout, taps);
+  info[0] = p.rows ? 1 : 0;
+  info[1] = p.ct;
+  info[2] = p.ot;
+  info[3] = p.ws;
+  info[4] = (int32_t)p.nchunk;
+  info[5] = p.dper;
+  return UNET_OK;
 }
 
 unet_status unet_conv_wgrad(unet_shape s, unet_act x, unet_act dy, int32_t taps, float* dw,
@@ -813,39 +1393,63 @@ unet_status unet_conv_wgrad(unet_shape s, unet_act x, unet_act dy, int32_t taps,
     return ufail(UNET_EINVAL, "bad wgrad args");
   if (!act_ok(x, 8) || !act_ok(dy, 16) || dy.c > 128) return ufail(UNET_EINVAL, "bad wgrad views");
   hipStream_t st = (hipStream_t)stream;
-  const long long nv = nvox_of(s);
-  const long long ch = wgrad_chunk(nv);
-  const int nc = (int)((nv + ch - 1) / ch);
+  const WgradPlan p = wgrad_plan(s, x.c, dy.c, taps);
   const int K = taps * x.c;
-  float* wsw = (float*)ws;
-  float* wsb = wsw + (long long)nc * dy.c * K;
-  const dim3 grid((K + 63) / 64, nc);
+  const long long nw = (long long)dy.c * K;
+  float* wsp = (float*)ws;
   const uint16_t* xp = (const uint16_t*)x.p;
   const uint16_t* dp = (const uint16_t*)dy.p;
-  switch (dy.c / 16) {
-    case 1:
-      hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
-                         dy.ld, dy.off, taps, ch, wsw);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_conv_wgrad<2>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
-                         dy.ld, dy.off, taps, ch, wsw);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_conv_wgrad<4>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
-                         dy.ld, dy.off, taps, ch, wsw);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_conv_wgrad<8>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
-                         dy.ld, dy.off, taps, ch, wsw);
-      break;
-    default:
-      return ufail(UNET_EINVAL, "output channels must be 16, 32, 64 or 128");
+  if (p.rows) {
+    WgradRowsArgs a{s, xp, x.ld, x.off, x.c, dp, dy.ld, dy.off, dy.c,
+                    p.nws, p.nhb, p.nds, p.dper, p.ncp, p.rs, wsp};
+    const dim3 grid((unsigned)p.nchunk, (unsigned)(p.ncp * p.nop));
+    const int key = p.ct * 10000 + p.ot * 100 + p.ws;
+    switch (key) {
+#define WGROWS(CT, OT, WS)                                                             \
+  case CT * 10000 + OT * 100 + WS:                                                     \
+    hipLaunchKernelGGL((k_wgrad_rows<CT, OT, WS>), grid, dim3(256), 0, st, a);         \
+    break;
+      WGROWS(8, 16, 32)
+      WGROWS(8, 32, 32)
+      WGROWS(16, 16, 32)
+      WGROWS(16, 32, 32)
+      WGROWS(32, 16, 32)
+      WGROWS(32, 32, 32)
+      WGROWS(8, 32, 16)
+      WGROWS(16, 32, 16)
+      WGROWS(32, 16, 16)
+      WGROWS(32, 32, 16)
+#undef WGROWS
+      default:
+        return ufail(UNET_EINVAL, "wgrad: no row kernel for this channel tiling");
+    }
+  } else {
+    const dim3 grid((K + 63) / 64, (unsigned)p.nchunk);
+    switch (dy.c / 16) {
+      case 1:
+        hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
+                           dy.ld, dy.off, taps, p.vchunk, p.rs, wsp);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_conv_wgrad<2>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
+                           dy.ld, dy.off, taps, p.vchunk, p.rs, wsp);
+        break;
+      case 4:
+        hipLaunchKernelGGL(k_conv_wgrad<4>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
+                           dy.ld, dy.off, taps, p.vchunk, p.rs, wsp);
+        break;
+      case 8:
+        hipLaunchKernelGGL(k_conv_wgrad<8>, grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, dp,
+                           dy.ld, dy.off, taps, p.vchunk, p.rs, wsp);
+        break;
+      default:
+        return ufail(UNET_EINVAL, "output channels must be 16, 32, 64 or 128");
+    }
+    hipLaunchKernelGGL(k_bias_partial, dim3((unsigned)p.nchunk), dim3(128), 0, st, s, dp, dy.ld,
+                       dy.off, dy.c, p.vchunk, p.rs, wsp + nw);
   }
-  hipLaunchKernelGGL(k_bias_partial, dim3(nc), dim3(128), 0, st, s, dp, dy.ld, dy.off, dy.c, ch, wsb);
-  const long long nw = (long long)dy.c * K;
-  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(nw)), dim3(256), 0, st, wsw, nw, nc, dw);
-  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(dy.c)), dim3(256), 0, st, wsb, (long long)dy.c, nc, db);
+  UHIP(hipGetLastError());
+  enq_sum_rows(wsp, p.nchunk, p.rs, nw, dw, db, st);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -855,9 +1459,14 @@ unet_status unet_relu_bwd(unet_shape s, unet_act y, unet_act dy, unet_act out, v
       y.c != out.c)
     return ufail(UNET_EINVAL, "bad relu_bwd views");
   const long long n = nvox_of(s) * y.c;
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, nvox_of(s), y.c,
-                     (const uint16_t*)y.p, y.ld, y.off, (const uint16_t*)dy.p, dy.ld, dy.off,
-                     (uint16_t*)out.p, out.ld, out.off);
+  if (y.c % 8 == 0)
+    hipLaunchKernelGGL(k_relu_bwd8, dim3(nblk(n / 8)), dim3(256), 0, (hipStream_t)stream,
+                       nvox_of(s), y.c / 8, (const uint16_t*)y.p, y.ld, y.off,
+                       (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)out.p, out.ld, out.off);
+  else
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, nvox_of(s),
+                       y.c, (const uint16_t*)y.p, y.ld, y.off, (const uint16_t*)dy.p, dy.ld,
+                       dy.off, (uint16_t*)out.p, out.ld, out.off);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -866,8 +1475,12 @@ unet_status unet_pool_fwd(unet_shape f, unet_act x, unet_act y, void* stream) {
   if (!shape_ok(f) || f.d % 2 || f.h % 2 || f.w % 2 || !act_ok(x, 1) || !act_ok(y, 1) || x.c != y.c)
     return ufail(UNET_EINVAL, "bad pool args");
   const long long n = nvox_of(f) / 8 * x.c;
-  hipLaunchKernelGGL(k_pool_fwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, f, x.c,
-                     (const uint16_t*)x.p, x.ld, x.off, (uint16_t*)y.p, y.ld, y.off);
+  if (x.c % 8 == 0)
+    hipLaunchKernelGGL(k_pool_fwd8, dim3(nblk(n / 8)), dim3(256), 0, (hipStream_t)stream, f,
+                       x.c / 8, (const uint16_t*)x.p, x.ld, x.off, (uint16_t*)y.p, y.ld, y.off);
+  else
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, f, x.c,
+                       (const uint16_t*)x.p, x.ld, x.off, (uint16_t*)y.p, y.ld, y.off);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -877,9 +1490,14 @@ unet_status unet_pool_bwd(unet_shape f, unet_act dy, unet_act dx, int32_t accumu
       dx.c != dy.c)
     return ufail(UNET_EINVAL, "bad pool_bwd args");
   const long long n = nvox_of(f) * dx.c;
-  hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, f, dx.c,
-                     (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)dx.p, dx.ld, dx.off,
-                     accumulate);
+  if (dx.c % 8 == 0)
+    hipLaunchKernelGGL(k_pool_bwd8, dim3(nblk(n / 8)), dim3(256), 0, (hipStream_t)stream, f,
+                       dx.c / 8, (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)dx.p, dx.ld,
+                       dx.off, accumulate);
+  else
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, f, dx.c,
+                       (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)dx.p, dx.ld, dx.off,
+                       accumulate);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -888,8 +1506,12 @@ unet_status unet_up_fwd(unet_shape cs, unet_act x, unet_act y, void* stream) {
   if (!shape_ok(cs) || !act_ok(x, 1) || !act_ok(y, 1) || x.c != y.c)
     return ufail(UNET_EINVAL, "bad up args");
   const long long n = nvox_of(cs) * 8 * x.c;
-  hipLaunchKernelGGL(k_up_fwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, cs, x.c,
-                     (const uint16_t*)x.p, x.ld, x.off, (uint16_t*)y.p, y.ld, y.off);
+  if (x.c % 8 == 0)
+    hipLaunchKernelGGL(k_up_fwd8, dim3(nblk(n / 8)), dim3(256), 0, (hipStream_t)stream, cs,
+                       x.c / 8, (const uint16_t*)x.p, x.ld, x.off, (uint16_t*)y.p, y.ld, y.off);
+  else
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, cs, x.c,
+                       (const uint16_t*)x.p, x.ld, x.off, (uint16_t*)y.p, y.ld, y.off);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -898,8 +1520,13 @@ unet_status unet_up_bwd(unet_shape cs, unet_act dy, unet_act dx, void* stream) {
   if (!shape_ok(cs) || !act_ok(dy, 1) || !act_ok(dx, 1) || dx.c != dy.c)
     return ufail(UNET_EINVAL, "bad up_bwd args");
   const long long n = nvox_of(cs) * dx.c;
-  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, cs, dx.c,
-                     (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)dx.p, dx.ld, dx.off);
+  if (dx.c % 8 == 0)
+    hipLaunchKernelGGL(k_up_bwd8, dim3(nblk(n / 8)), dim3(256), 0, (hipStream_t)stream, cs,
+                       dx.c / 8, (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)dx.p, dx.ld,
+                       dx.off);
+  else
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, cs, dx.c,
+                       (const uint16_t*)dy.p, dy.ld, dy.off, (uint16_t*)dx.p, dx.ld, dx.off);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
@@ -908,16 +1535,22 @@ unet_status unet_head_fwd(unet_shape s, unet_act x, const float* w, const float*
                           void* stream) {
   if (!shape_ok(s) || !act_ok(x, 1) || !w || !b || !y) return ufail(UNET_EINVAL, "bad head args");
   const long long nv = nvox_of(s);
-  hipLaunchKernelGGL(k_head_fwd, dim3(nblk(nv)), dim3(256), 0, (hipStream_t)stream, nv, x.c,
-                     (const uint16_t*)x.p, x.ld, x.off, w, b, y);
+  if (x.c % 8 == 0)
+    hipLaunchKernelGGL(k_head_fwd8, dim3(nblk(nv)), dim3(256), 0, (hipStream_t)stream, nv,
+                       x.c / 8, (const uint16_t*)x.p, x.ld, x.off, w, b, y);
+  else
+    hipLaunchKernelGGL(k_head_fwd, dim3(nblk(nv)), dim3(256), 0, (hipStream_t)stream, nv, x.c,
+                       (const uint16_t*)x.p, x.ld, x.off, w, b, y);
   UHIP(hipGetLastError());
   return UNET_OK;
 }
 
 size_t unet_head_workspace(unet_shape s, int32_t cin) {
+  if (!shape_ok(s) || cin <= 0) return 0;
   const long long nv = nvox_of(s);
   const long long ch = wgrad_chunk(nv);
-  return (size_t)((nv + ch - 1) / ch) * (cin + 1) * sizeof(float);
+  const long long nc = (nv + ch - 1) / ch;
+  return (size_t)(nc + sum_groups(nc)) * (cin + 1) * sizeof(float);
 }
 
 unet_status unet_head_bwd(unet_shape s, unet_act x, const float* w, const float* dy, unet_act dx,
@@ -926,20 +1559,27 @@ unet_status unet_head_bwd(unet_shape s, unet_act x, const float* w, const float*
     return ufail(UNET_EINVAL, "bad head_bwd args");
   hipStream_t st = (hipStream_t)stream;
   const long long nv = nvox_of(s);
+  const bool v8 = x.c % 8 == 0 && x.c <= 256;
   if (dx.p) {
     if (!act_ok(dx, 1) || dx.c != x.c) return ufail(UNET_EINVAL, "bad head dx view");
-    hipLaunchKernelGGL(k_head_dgrad, dim3(nblk(nv * x.c)), dim3(256), 0, st, nv, x.c, w, dy,
-                       (uint16_t*)dx.p, dx.ld, dx.off);
+    if (v8)
+      hipLaunchKernelGGL(k_head_dgrad8, dim3(nblk(nv * x.c / 8)), dim3(256), 0, st, nv, x.c / 8,
+                         w, dy, (uint16_t*)dx.p, dx.ld, dx.off);
+    else
+      hipLaunchKernelGGL(k_head_dgrad, dim3(nblk(nv * x.c)), dim3(256), 0, st, nv, x.c, w, dy,
+                         (uint16_t*)dx.p, dx.ld, dx.off);
   }
   const long long ch = wgrad_chunk(nv);
   const int nc = (int)((nv + ch - 1) / ch);
   float* wsp = (float*)ws;
-  hipLaunchKernelGGL(k_head_wgrad_partial, dim3(nc), dim3(64), 0, st, nv, x.c,
-                     (const uint16_t*)x.p, x.ld, x.off, dy, ch, wsp);
+  if (v8)
+    hipLaunchKernelGGL(k_head_wgrad8, dim3(nc), dim3(256), 0, st, nv, x.c / 8,
+                       (const uint16_t*)x.p, x.ld, x.off, dy, ch, wsp);
+  else
+    hipLaunchKernelGGL(k_head_wgrad_partial, dim3(nc), dim3(64), 0, st, nv, x.c,
+                       (const uint16_t*)x.p, x.ld, x.off, dy, ch, wsp);
   // wsp[chunk][c + 1] -> dw[c] (the last column is the bias gradient)
-  hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(x.c)), dim3(256), 0, st, wsp, (long long)(x.c + 1),
-                     nc, dw);
-  hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, wsp + x.c, (long long)(x.c + 1), nc, db);
+  enq_sum_rows(wsp, nc, x.c + 1, x.c, dw, db, st);
   UHIP(hipGetLastError());
   return UNET_OK;
 }

@@ -40,6 +40,7 @@ _SIGS = [
     ("unet_conv_dgrad", ctypes.c_int, [unet_shape, unet_act, _V, _I, unet_act, _V, _V]),
     ("unet_wgrad_workspace", ctypes.c_size_t, [unet_shape, _I, _I, _I]),
     ("unet_conv_wgrad", ctypes.c_int, [unet_shape, unet_act, unet_act, _I, _V, _V, _V, _V]),
+    ("unet_wgrad_kernel", ctypes.c_int, [unet_shape, _I, _I, _I, _V]),
     ("unet_relu_bwd", ctypes.c_int, [unet_shape, unet_act, unet_act, unet_act, _V]),
     ("unet_pool_fwd", ctypes.c_int, [unet_shape, unet_act, unet_act, _V]),
     ("unet_pool_bwd", ctypes.c_int, [unet_shape, unet_act, unet_act, _I, _V]),
@@ -125,6 +126,16 @@ def unet_wgrad_workspace(s, cin, cout, taps):
 
 def unet_conv_wgrad(s, x, dy, taps, dw, db, ws):
     _check(load().unet_conv_wgrad(s, x, dy, taps, _p(dw), _p(db), _p(ws), _stream()))
+
+
+def unet_wgrad_kernel(s, cin, cout, taps):
+    """Kernel choice of unet_conv_wgrad (host only): dict with rows (row-tiled
+    kernel or voxel chunks), ct / ot / ws (channels and w extent of a row
+    workgroup), chunks (partial rows) and dper (d planes per chunk)."""
+    info = (ctypes.c_int32 * 6)()
+    _check(load().unet_wgrad_kernel(s, cin, cout, taps, ctypes.cast(info, ctypes.c_void_p)))
+    return {"rows": bool(info[0]), "ct": info[1], "ot": info[2], "ws": info[3],
+            "chunks": info[4], "dper": info[5]}
 
 
 def unet_relu_bwd(s, y, dy, out):

@@ -332,6 +332,37 @@ def conv_throughput(n=128, reps=5):
     return out
 
 
+def train_throughput(n=128, batch=2, steps=20, warmup=3):
+    """Measured time of one training step (forward, backward, Adam) at batch
+    x n^3 on synthetic data: random BF16 inputs, random targets, every cell
+    active.  HIP-event timing of `steps` steps after `warmup`."""
+    import torch
+    net = NET.UNet()
+    net.init_he(0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = (torch.randn((batch, n, n, n, NET.IN_CH), device="cuda", generator=g)
+         .to(torch.bfloat16).view(torch.int16).contiguous())
+    tgt = torch.randn((batch, n, n, n), device="cuda", generator=g).contiguous()
+    msk = torch.ones((batch, n, n, n), dtype=torch.uint8, device="cuda")
+
+    def step():
+        net.forward(x, batch, n, n, n)
+        net.backward(x, tgt, msk, want_loss=False)
+        net.adam(1e-4)
+
+    for _ in range(warmup):
+        step()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    res = {"n": n, "batch": batch, "steps": steps, "ms_per_step": ev0.elapsed_time(ev1) / steps}
+    print(res, flush=True)
+    return res
+
+
 def main():
     import torch
     ap = argparse.ArgumentParser()
@@ -345,6 +376,8 @@ def main():
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--out", default="warmstart_out")
     ap.add_argument("--conv-throughput", action="store_true")
+    ap.add_argument("--train-throughput", action="store_true",
+                    help="time training steps on synthetic data at --n and --batch")
     ap.add_argument("--params", default="", help="trained weights (.npy): evaluate only")
     ap.add_argument("--half-n", default="",
                     help="evaluation grids (comma-separated) also run with half-resolution "
@@ -357,6 +390,11 @@ def main():
     if args.conv_throughput:
         res = conv_throughput(args.n)
         with open(os.path.join(args.out, "conv_throughput.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        return
+    if args.train_throughput:
+        res = train_throughput(args.n, args.batch)
+        with open(os.path.join(args.out, "train_throughput.json"), "w") as f:
             json.dump(res, f, indent=1)
         return
     net = NET.UNet()

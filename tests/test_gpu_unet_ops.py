@@ -142,52 +142,180 @@ def test_conv_dgrad_and_wgrad(n, cin, cout, dhw):
     assert rel(db.cpu().numpy().astype(np.float64), dbs) <= 1e-5
 
 
-def test_pool_upsample_relu_bwd():
+# Forward cases on larger grids, compared at sampled voxels (every output
+# channel).  LDS-tiled: 4 output blocks per workgroup, 2 (whole and split
+# over 2 workgroups), 1 of 4 on 32 x 8 tiles.  Gathered, 64 voxels per wave:
+# 8 output blocks, 4 of 8, 2 of 4, 1; 16 voxels per wave: 2 of 8.  (Small
+# grids, as in CONV_CASES, take 16 voxels and one output block per wave.)
+CONV_LARGE_CASES = [(1, 32, 64, (32, 64, 64)), (1, 32, 32, (32, 64, 64)),
+                    (1, 16, 64, (16, 64, 128)), (1, 32, 64, (32, 32, 32)),
+                    (1, 24, 128, (16, 64, 64)), (1, 64, 128, (32, 32, 32)),
+                    (1, 128, 64, (32, 32, 32)), (1, 24, 16, (16, 64, 64)),
+                    (1, 128, 128, (16, 16, 16))]
+
+
+@pytest.mark.parametrize("n,cin,cout,dhw", CONV_LARGE_CASES)
+def test_conv_forward_large(n, cin, cout, dhw):
     require_gpu()
-    rng = np.random.default_rng(3)
-    n, c, dhw = 2, 16, (4, 6, 8)
-    x = rng.standard_normal((n, c) + dhw)
+    say(f"conv fwd large {n} {cin}->{cout} {dhw}")
+    rng = np.random.default_rng(200 + cin + cout)
+    x = rng.standard_normal((n, cin) + dhw).astype(np.float32)
+    w = rng.standard_normal((cout, cin, 3, 3, 3)) / np.sqrt(27 * cin)
+    b = rng.standard_normal(cout) * 0.1
     xd, x64 = to_dev_bf16(cl(x))
+    wd, w64 = to_dev_bf16(w_gpu(w))
+    bd = torch.from_numpy(b.astype(np.float32)).cuda()
+    w64o = w64.reshape(cout, 27, cin).transpose(0, 2, 1).reshape(cout, cin, 3, 3, 3)
+    d, h, ww = dhw
+    pts = [(0, 0, 0), (d - 1, h - 1, ww - 1), (0, h - 1, 0), (d - 1, 0, ww - 1)]
+    pts += [tuple(int(rng.integers(0, m)) for m in dhw) for _ in range(60)]
+    want = UO.conv3d_points(cf(x64)[0], w64o, b.astype(np.float32).astype(np.float64), pts)
+    s = UN.shape(n, *dhw)
+    yf = torch.full((n,) + dhw + (cout,), np.nan, dtype=torch.float32, device="cuda")
+    UN.unet_conv_fwd(s, UN.act(xd, cin, 0, cin), wd, bd, 27, UN.act(None, cout, 0, cout), yf, 0)
+    y = yf.cpu().numpy()
+    assert np.all(np.isfinite(y))
+    got = np.stack([y[0][p] for p in pts]).astype(np.float64)
+    assert rel(got, want) <= 1e-5
+
+
+# Weight-gradient cases of the row-tiled kernel, one or more per channel tiling
+# (input channels, output channels, w extent of a workgroup): 4-row blocks of
+# w = 32k or w = 16 grids, several d ranges per sample, XCD-grouped chunk
+# order (chunk count a multiple of 8) and two-level partial sums (more than 64
+# chunks).  Entries are compared on sampled (o, c) pairs (all 27 taps) and the
+# whole bias gradient.
+WGRAD_ROW_CASES = [
+    (1, 8, 16, (16, 8, 64)), (1, 8, 32, (128, 64, 32)), (1, 16, 16, (12, 8, 96)),
+    (1, 16, 32, (128, 64, 32)), (1, 32, 16, (128, 64, 32)), (1, 64, 64, (64, 32, 32)),
+    (1, 8, 32, (8, 8, 16)), (2, 16, 32, (4, 8, 16)), (1, 32, 16, (6, 4, 16)),
+    (1, 128, 128, (32, 16, 16))]
+
+
+@pytest.mark.parametrize("n,cin,cout,dhw", WGRAD_ROW_CASES)
+def test_conv_wgrad_rows(n, cin, cout, dhw):
+    require_gpu()
+    plan = UN.unet_wgrad_kernel(UN.shape(n, *dhw), cin, cout, 27)
+    say(f"conv wgrad rows {n} {cin}->{cout} {dhw} {plan}")
+    assert plan["rows"]
+    rng = np.random.default_rng(100 + cin + cout)
+    x = rng.standard_normal((n, cin) + dhw)
+    dy = rng.standard_normal((n, cout) + dhw)
+    # x as a channel slice [8, 8 + cin) of a wider row, dy plain
+    xw = np.zeros((n,) + dhw + (cin + 16,))
+    xw[..., 8:8 + cin] = cl(x)
+    xd, xw64 = to_dev_bf16(xw)
+    x64 = cf(xw64[..., 8:8 + cin])
+    dyd, dy64 = to_dev_bf16(cl(dy))
+    dy64 = cf(dy64)
+    pairs = sorted({(int(o), int(c)) for o, c in zip(rng.integers(0, cout, 24),
+                                                    rng.integers(0, cin, 24))}
+                   | {(0, 0), (cout - 1, cin - 1)})
+    want = 0.0
+    want_b = 0.0
+    for i in range(n):
+        g, b = UO.conv3d_wgrad_pairs(x64[i], dy64[i], pairs)
+        want = want + g
+        want_b = want_b + b
+    s = UN.shape(n, *dhw)
+    ws = torch.empty(UN.unet_wgrad_workspace(s, cin, cout, 27) // 4 + 1, dtype=torch.float32,
+                     device="cuda")
+    dw = torch.full((cout * 27 * cin,), np.nan, dtype=torch.float32, device="cuda")
+    db = torch.full((cout,), np.nan, dtype=torch.float32, device="cuda")
+    UN.unet_conv_wgrad(s, UN.act(xd, cin + 16, 8, cin), UN.act(dyd, cout, 0, cout), 27, dw, db, ws)
+    got = dw.cpu().numpy().astype(np.float64).reshape(cout, 3, 3, 3, cin)
+    assert np.all(np.isfinite(got))
+    got_p = np.stack([got[o, :, :, :, c] for o, c in pairs])
+    assert rel(got_p, want) <= 1e-5
+    assert rel(db.cpu().numpy().astype(np.float64), want_b) <= 1e-5
+    # a second call gives bitwise the same result (fixed summation order)
+    dw2 = torch.empty_like(dw)
+    db2 = torch.empty_like(db)
+    UN.unet_conv_wgrad(s, UN.act(xd, cin + 16, 8, cin), UN.act(dyd, cout, 0, cout), 27, dw2, db2,
+                       ws)
+    assert torch.equal(dw, dw2) and torch.equal(db, db2)
+
+
+def put(a_cl, ld):
+    """channels-last FP64 array -> (device BF16 rows of ld channels holding a
+    in the first C, FP64 of the rounded values)."""
+    c = a_cl.shape[-1]
+    full = np.zeros(a_cl.shape[:-1] + (ld,))
+    full[..., :c] = a_cl
+    d, r = to_dev_bf16(full)
+    return d, r[..., :c]
+
+
+def zeros_ld(shape, ld):
+    return torch.zeros(tuple(shape) + (ld,), dtype=torch.int16, device="cuda")
+
+
+def got_c(t, c):
+    """device BF16 rows -> FP64 [n][C][...] of the first c channels; the
+    channels beyond c must be untouched (zero)."""
+    a = from_dev_bf16(t)
+    assert np.all(a[..., c:] == 0.0)
+    return cf(a[..., :c])
+
+
+# (channels, row length): 8-channel vector kernels, and one-channel kernels
+# for a count that is not a multiple of 8
+@pytest.mark.parametrize("c,ld", [(16, 16), (16, 24), (4, 8), (12, 16)])
+def test_pool_upsample_relu_bwd(c, ld):
+    require_gpu()
+    say(f"pool/upsample/relu c={c} ld={ld}")
+    rng = np.random.default_rng(3)
+    n, dhw = 2, (4, 6, 8)
+    x = rng.standard_normal((n, c) + dhw)
+    xd, x64 = put(cl(x), ld)
+    x64 = cf(x64)
     fine = UN.shape(n, *dhw)
     coarse = UN.shape(n, 2, 3, 4)
-    yp = torch.zeros((n, 2, 3, 4, c), dtype=torch.int16, device="cuda")
-    UN.unet_pool_fwd(fine, UN.act(xd, c, 0, c), UN.act(yp, c, 0, c))
-    want = np.stack([UO.avgpool2(cf(x64)[i]) for i in range(n)])
-    got = cf(from_dev_bf16(yp))
+    yp = zeros_ld((n, 2, 3, 4), ld)
+    UN.unet_pool_fwd(fine, UN.act(xd, ld, 0, c), UN.act(yp, ld, 0, c))
+    want = np.stack([UO.avgpool2(x64[i]) for i in range(n)])
+    got = got_c(yp, c)
     assert np.all(np.abs(got - want) <= 2.0 ** -8 * np.abs(want) + 1e-7)
     # upsample of the pooled values, and the adjoint sums
-    yu = torch.zeros((n,) + dhw + (c,), dtype=torch.int16, device="cuda")
-    UN.unet_up_fwd(coarse, UN.act(yp, c, 0, c), UN.act(yu, c, 0, c))
-    assert np.array_equal(cf(from_dev_bf16(yu)), np.stack([UO.upsample2(g) for g in got]))
-    dyd, dy64 = to_dev_bf16(cl(rng.standard_normal((n, c) + dhw)))
-    du = torch.zeros((n, 2, 3, 4, c), dtype=torch.int16, device="cuda")
-    UN.unet_up_bwd(coarse, UN.act(dyd, c, 0, c), UN.act(du, c, 0, c))
-    want = np.stack([UO.upsample2_backward(cf(dy64)[i]) for i in range(n)])
-    assert np.all(np.abs(cf(from_dev_bf16(du)) - want) <= 2.0 ** -8 * np.abs(want) + 1e-6)
-    dp = torch.zeros((n,) + dhw + (c,), dtype=torch.int16, device="cuda")
-    UN.unet_pool_bwd(fine, UN.act(du, c, 0, c), UN.act(dp, c, 0, c), 0)
-    want = np.stack([UO.avgpool2_backward(cf(from_dev_bf16(du))[i]) for i in range(n)])
-    assert np.array_equal(cf(from_dev_bf16(dp)), want)
+    yu = zeros_ld((n,) + dhw, ld)
+    UN.unet_up_fwd(coarse, UN.act(yp, ld, 0, c), UN.act(yu, ld, 0, c))
+    assert np.array_equal(got_c(yu, c), np.stack([UO.upsample2(g) for g in got]))
+    dyd, dy64 = put(cl(rng.standard_normal((n, c) + dhw)), ld)
+    dy64 = cf(dy64)
+    du = zeros_ld((n, 2, 3, 4), ld)
+    UN.unet_up_bwd(coarse, UN.act(dyd, ld, 0, c), UN.act(du, ld, 0, c))
+    want = np.stack([UO.upsample2_backward(dy64[i]) for i in range(n)])
+    gu = got_c(du, c)
+    assert np.all(np.abs(gu - want) <= 2.0 ** -8 * np.abs(want) + 1e-6)
+    dp = zeros_ld((n,) + dhw, ld)
+    UN.unet_pool_bwd(fine, UN.act(du, ld, 0, c), UN.act(dp, ld, 0, c), 0)
+    want = np.stack([UO.avgpool2_backward(gu[i]) for i in range(n)])
+    assert np.array_equal(got_c(dp, c), want)
+    # accumulate = 1 adds the pooled gradient to what dx holds (BF16 sum)
+    UN.unet_pool_bwd(fine, UN.act(du, ld, 0, c), UN.act(dp, ld, 0, c), 1)
+    assert np.all(np.abs(got_c(dp, c) - 2 * want) <= 2.0 ** -8 * np.abs(2 * want))
     # ReLU backward keeps dy where y > 0
-    ro = torch.zeros_like(xd)
-    UN.unet_relu_bwd(fine, UN.act(xd, c, 0, c), UN.act(dyd, c, 0, c), UN.act(ro, c, 0, c))
-    want = np.stack([UO.relu_backward(cf(x64)[i], cf(dy64)[i]) for i in range(n)])
-    assert np.array_equal(cf(from_dev_bf16(ro)), want)
+    ro = zeros_ld((n,) + dhw, ld)
+    UN.unet_relu_bwd(fine, UN.act(xd, ld, 0, c), UN.act(dyd, ld, 0, c), UN.act(ro, ld, 0, c))
+    want = np.stack([UO.relu_backward(x64[i], dy64[i]) for i in range(n)])
+    assert np.array_equal(got_c(ro, c), want)
 
 
-def test_head_mse_adam():
+@pytest.mark.parametrize("c,ld", [(16, 16), (12, 16)])
+def test_head_mse_adam(c, ld):
     require_gpu()
+    say(f"head/mse/adam c={c} ld={ld}")
     rng = np.random.default_rng(4)
-    n, c, dhw = 2, 16, (3, 4, 5)
+    n, dhw = 2, (3, 4, 5)
     x = rng.standard_normal((n, c) + dhw)
-    xd, x64 = to_dev_bf16(cl(x))
+    xd, x64 = put(cl(x), ld)
     w = rng.standard_normal(c).astype(np.float32)
     b = np.float32(0.3)
     s = UN.shape(n, *dhw)
     wd = torch.from_numpy(w).cuda()
     bd = torch.tensor([b], dtype=torch.float32, device="cuda")
     y = torch.zeros((n,) + dhw, dtype=torch.float32, device="cuda")
-    UN.unet_head_fwd(s, UN.act(xd, c, 0, c), wd, bd, y)
+    UN.unet_head_fwd(s, UN.act(xd, ld, 0, c), wd, bd, y)
     w5 = w.astype(np.float64).reshape(1, c, 1, 1, 1)
     want = np.stack([UO.conv3d(cf(x64)[i], w5, np.array([float(b)]))[0] for i in range(n)])
     assert rel(y.cpu().numpy().astype(np.float64), want) <= 1e-6
@@ -205,7 +333,7 @@ def test_head_mse_adam():
     dw = torch.zeros(c, dtype=torch.float32, device="cuda")
     db = torch.zeros(1, dtype=torch.float32, device="cuda")
     dx = torch.zeros_like(xd)
-    UN.unet_head_bwd(s, UN.act(xd, c, 0, c), wd, dpred, UN.act(dx, c, 0, c), dw, db, ws)
+    UN.unet_head_bwd(s, UN.act(xd, ld, 0, c), wd, dpred, UN.act(dx, ld, 0, c), dw, db, ws)
     dp64 = dpred.cpu().numpy().astype(np.float64)
     gx, gw, gb = 0.0, 0.0, 0.0
     dxs = []
@@ -216,7 +344,7 @@ def test_head_mse_adam():
     assert rel(dw.cpu().numpy().astype(np.float64), gw.reshape(c)) <= 1e-5
     assert abs(float(db.item()) - float(gb[0])) <= 1e-5 * abs(float(gb[0])) + 1e-7
     want = np.stack(dxs)
-    assert np.all(np.abs(cf(from_dev_bf16(dx)) - want) <= 2.0 ** -8 * np.abs(want) + 1e-7)
+    assert np.all(np.abs(got_c(dx, c) - want) <= 2.0 ** -8 * np.abs(want) + 1e-7)
     # Adam: two steps against the oracle's
     p0 = rng.standard_normal(1000)
     g1, g2 = rng.standard_normal(1000), rng.standard_normal(1000)
@@ -232,6 +360,30 @@ def test_head_mse_adam():
         UO.adam_step(po, {"p": g.astype(np.float32).astype(np.float64)}, st, 1e-3)
     assert rel(master.cpu().numpy().astype(np.float64) - p0, po["p"] - p0) <= 1e-4
     assert np.array_equal(out16.cpu().numpy().view(np.uint16), bf16_round(master.cpu().numpy()))
+
+
+def test_head_backward_many_chunks():
+    # 131072 voxels: 128 voxel chunks, summed in two levels
+    require_gpu()
+    rng = np.random.default_rng(5)
+    n, c, dhw = 2, 16, (16, 64, 64)
+    x = rng.standard_normal((n, c) + dhw)
+    xd, x64 = to_dev_bf16(cl(x))
+    w = rng.standard_normal(c).astype(np.float32)
+    dy = rng.standard_normal((n,) + dhw).astype(np.float32)
+    s = UN.shape(n, *dhw)
+    ws = torch.empty(UN.unet_head_workspace(s, c) // 4 + 1, dtype=torch.float32, device="cuda")
+    dw = torch.zeros(c, dtype=torch.float32, device="cuda")
+    db = torch.zeros(1, dtype=torch.float32, device="cuda")
+    UN.unet_head_bwd(s, UN.act(xd, c, 0, c), torch.from_numpy(w).cuda(),
+                     torch.from_numpy(dy).cuda(), UN.act(None, c, 0, c), dw, db, ws)
+    w5 = w.astype(np.float64).reshape(1, c, 1, 1, 1)
+    gw, gb = 0.0, 0.0
+    for i in range(n):
+        _, dw_i, db_i = UO.conv3d_backward(cf(x64)[i], w5, dy[i].astype(np.float64)[None])
+        gw, gb = gw + dw_i, gb + db_i
+    assert rel(dw.cpu().numpy().astype(np.float64), gw.reshape(c)) <= 1e-5
+    assert abs(float(db.item()) - float(gb[0])) <= 1e-5 * np.abs(dy).sum()
 
 
 def test_scale_to_fp32_and_fp64():

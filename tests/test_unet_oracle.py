@@ -1,5 +1,6 @@
-"""Pins of the U-Net oracle: convolution against torch's CPU float64 conv3d
-(a library routine) and the closed form of a delta input, pooling /
+"""Pins of the U-Net oracle: convolution and selected weight-gradient entries
+against torch's CPU float64 conv3d and its autograd (library routines) and
+the closed form of a delta input, pooling /
 upsampling adjointness, exact gradients of every layer and of a whole small
 U-Net against central finite differences, and the closed form of the first
 Adam step."""
@@ -20,6 +21,19 @@ def test_conv3d_matches_torch_cpu_float64():
         want = torch.nn.functional.conv3d(torch.from_numpy(x)[None], torch.from_numpy(w),
                                           torch.from_numpy(b), padding=k // 2)[0].numpy()
         assert np.allclose(U.conv3d(x, w, b), want, rtol=0, atol=1e-12)
+
+
+def test_conv3d_points_match_torch_cpu_float64():
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((4, 5, 6, 7))
+    w = rng.standard_normal((3, 4, 3, 3, 3))
+    b = rng.standard_normal(3)
+    want = torch.nn.functional.conv3d(torch.from_numpy(x)[None], torch.from_numpy(w),
+                                      torch.from_numpy(b), padding=1)[0].numpy()
+    pts = [(0, 0, 0), (4, 5, 6), (2, 3, 0), (1, 0, 6), (3, 2, 4)]
+    got = U.conv3d_points(x, w, b, pts)
+    for i, (d, h, ww) in enumerate(pts):
+        assert np.allclose(got[i], want[:, d, h, ww], rtol=0, atol=1e-12)
 
 
 def test_conv3d_of_delta_is_flipped_kernel():
@@ -67,6 +81,25 @@ def test_conv_backward_finite_differences():
     _fd_check(loss, x, dx, [(0, 0, 0, 0), (2, 1, 3, 2), (1, 2, 1, 1)])
     _fd_check(loss, w, dw, [(0, 0, 0, 0, 0), (1, 2, 2, 1, 0), (0, 1, 1, 1, 1)])
     _fd_check(loss, b, db, [(0,), (1,)])
+
+
+def test_wgrad_pairs_match_torch_weight_gradient():
+    # the selected-entry weight gradient against torch's CPU float64 autograd
+    # of conv3d (a library routine), on a grid with walls on every side
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((5, 4, 6, 7))
+    dy = rng.standard_normal((3, 4, 6, 7))
+    xt = torch.from_numpy(x)[None]
+    wt = torch.zeros((3, 5, 3, 3, 3), dtype=torch.float64, requires_grad=True)
+    bt = torch.zeros(3, dtype=torch.float64, requires_grad=True)
+    y = torch.nn.functional.conv3d(xt, wt, bt, padding=1)
+    (y * torch.from_numpy(dy)[None]).sum().backward()
+    want = wt.grad.numpy()
+    pairs = [(0, 0), (2, 4), (1, 3), (2, 0)]
+    got, db = U.conv3d_wgrad_pairs(x, dy, pairs)
+    for i, (o, c) in enumerate(pairs):
+        assert np.allclose(got[i], want[o, c], rtol=0, atol=1e-12)
+    assert np.allclose(db, bt.grad.numpy(), rtol=0, atol=1e-12)
 
 
 def test_unet_backward_finite_differences():
