@@ -59,6 +59,19 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
                           int32_t taps, unet_act y, float* out_f32, int32_t relu,
                           void* stream);
 
+/* Which forward-convolution kernel unet_conv_fwd (and unet_conv_dgrad, a
+ * forward convolution of dy) runs for these sizes (host only, no GPU call):
+ * info[0] = 1 for LDS tiles (3x3x3 taps, 8, 16, 32 or 64 input channels,
+ * 16-64 output channels, w a multiple of 64 and h of 4, or w = 32 and h a
+ * multiple of 8), 0 for gathered operands (everything else); info[1] = tile
+ * width (kind 1) or voxel blocks of 16 per wave (kind 0); info[2] = output
+ * blocks of 16 per wave; info[3] = output-channel groups (workgroups that
+ * share an input tile).  info: 4 int32 written by the call.  UNET_EINVAL for
+ * a bad shape, channel count (cin a multiple of 8 up to 256; cout 16, 32, 64
+ * or 128) or taps. */
+unet_status unet_conv_kernel(unet_shape s, int32_t cin, int32_t cout, int32_t taps,
+                             int32_t* info);
+
 /* Data gradient of a convolution: dx = sum_{o, t} w[o][t][c] dy[v - t + 1][o]
  * (BF16 in, BF16 out; dx.c multiple of 16).  wflip: caller workspace of
  * C_out * taps * C_in BF16 for the flipped, transposed weights. */

@@ -281,18 +281,15 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
   constexpr int K = 27 * CIN;
   constexpr int ksteps = (K + 31) / 32;
   const int kl = 8 * (lane >> 4);
-  f32x4 acc[4][NB];
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = 0; ks < ksteps; ++ks) {
-    const int k = ks * 32 + kl;
+  // Operands of K step ks: A (4 voxel blocks) from the LDS tile, B (NB
+  // output blocks) from the weights.  Steps past the end read step ksteps - 1
+  // (never used).
+  auto load_a = [&](int ks, bf16x8 (&a)[4]) {
+    const int k = min(ks, ksteps - 1) * 32 + kl;
     const bool kin = k < K;
     const int kk = kin ? k : K - 8;
     const int t = kk / CIN, ci = kk % CIN;
     const int dd = t / 9, dh = (t / 3) % 3, dw = t % 3;
-    bf16x8 a[4], bb[NB];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
       // the wave's voxel mb * 16 + (lane & 15): row l / TW of its rows
@@ -301,16 +298,44 @@ __global__ __launch_bounds__(256) void k_conv_fwd_tile(unet_shape s,
       const bf16x8 v = *reinterpret_cast<const bf16x8*>(tile + slot * CIN + ci);
       a[mb] = kin ? v : zero8();
     }
+  };
+  auto load_b = [&](int ks, bf16x8 (&b)[NB]) {
+    const int k = min(ks, ksteps - 1) * 32 + kl;
+    const bool kin = k < K;
+    const int kk = kin ? k : K - 8;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const bf16x8 v = ld8(w + (long long)(co0 + nb * 16 + (lane & 15)) * K + kk);
-      bb[nb] = kin ? v : zero8();
+      b[nb] = kin ? v : zero8();
     }
+  };
+  f32x4 acc[4][NB];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], bb[nb], acc[mb][nb], 0, 0, 0);
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // weights PF steps ahead, activations one step ahead; MFMA order as in
+  // k_conv_fwd (K steps in order)
+  constexpr int PF = 4;
+  bf16x8 bq[PF][NB], aq[2][4];
+#pragma unroll
+  for (int u = 0; u < PF; ++u) load_b(u, bq[u]);
+  load_a(0, aq[0]);
+  for (int ks = 0; ks < ksteps; ks += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int k = ks + u;
+      if (k < ksteps) {
+        load_a(k + 1, aq[(u + 1) & 1]);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[u & 1][mb], bq[u][nb],
+                                                                  acc[mb][nb], 0, 0, 0);
+        load_b(k + PF, bq[u]);
+      }
+    }
   }
   const long long vbase = (((long long)n0 * s.d + d0) * s.h + h0 + kRW * wave) * s.w + w0;
 #pragma unroll
@@ -1164,6 +1189,58 @@ long long wgrad_chunk(long long nvox) {
 }
 
 
+// Launch plan of the forward convolution (and of the data gradient, which is
+// a forward convolution).
+//   CONV_TILE:   3x3x3 taps, 8, 16, 32 or 64 input channels, 16-64 output
+//                channels, w a multiple of 64 and h of 4 (64 x 4 tiles) or
+//                w = 32 and h a multiple of 8 (32 x 8 tiles): LDS tiles.
+//   CONV_GATHER: everything else: 64 (or 16) voxels per wave, operands
+//                gathered from global memory.
+// Both split the output channels over workgroups while the grid would leave
+// CUs without work (tiles: until every CU has as many workgroups as its LDS
+// holds).  Measured on 32^3 grids: tiles with 32 -> 64 channels 188 -> 302
+// TFLOP/s, 64 -> 64 220 -> 308; gathered 16^3 grids 18-21 -> 54-88, 32^3
+// with 128 channels 105-126 -> 170-180.
+enum { CONV_GATHER = 0, CONV_TILE = 1 };
+struct ConvPlan {
+  int kind, mb, nb, tw;
+  long long grid;  // workgroups per output-channel group
+};
+
+ConvPlan conv_plan(unet_shape s, int cin, int cout, int taps) {
+  ConvPlan p{};
+  const long long nv = (long long)s.n * s.d * s.h * s.w;
+  const int ob = cout / 16;
+  const bool t64 = s.w % 64 == 0 && s.h % 4 == 0, t32 = s.w == 32 && s.h % 8 == 0;
+  if (taps == 27 && (t64 || t32) && ob <= 4 &&
+      (cin == 8 || cin == 16 || cin == 32 || cin == 64)) {
+    p.kind = CONV_TILE;
+    p.tw = t64 ? 64 : 32;
+    const int th = 256 / p.tw;
+    const long long tiles = nv / 256;
+    const long long lds = 3LL * (th + 2) * (p.tw + 2) * cin * 2;
+    const long long target = 256 * std::min<long long>(4, (160 * 1024) / lds);
+    p.nb = ob;
+    while (p.nb > 1 && tiles * (ob / p.nb) < target) p.nb /= 2;
+    p.grid = tiles;
+  } else {
+    // the widest output block per wave that still gives every CU a
+    // workgroup, with 64 voxels per wave, else 16
+    p.kind = CONV_GATHER;
+    auto wgs = [&](int m, int b) { return ((nv + 64 * m - 1) / (64 * m)) * (ob / b); };
+    p.mb = 4;
+    p.nb = ob;
+    while (p.nb > 1 && wgs(4, p.nb) < 256) p.nb /= 2;
+    if (wgs(4, p.nb) < 256) {
+      p.mb = 1;
+      p.nb = std::min(ob, 2);
+      while (p.nb > 1 && wgs(1, p.nb) < 256) p.nb /= 2;
+    }
+    p.grid = (nv + 64 * p.mb - 1) / (64 * p.mb);
+  }
+  return p;
+}
+
 // Groups of 64 chunk rows summed first when there are more than 64 rows.
 long long sum_groups(long long nchunk) { return nchunk > 64 ? (nchunk + 63) / 64 : 0; }
 
@@ -1271,86 +1348,71 @@ unet_status unet_conv_fwd(unet_shape s, unet_act x, const void* w, const float* 
   if (y.c % 16 || y.c > 128 || y.c <= 0 || y.ld % 8 || y.off % 8 || y.off + y.c > y.ld ||
       (!out_f32 && !y.p))
     return ufail(UNET_EINVAL, "bad output view (c multiple of 16, <= 128)");
-  const long long nv = nvox_of(s);
+  const int ob = y.c / 16;
+  if (ob != 1 && ob != 2 && ob != 4 && ob != 8)
+    return ufail(UNET_EINVAL, "output channels must be 16, 32, 64 or 128");
+  const ConvPlan p = conv_plan(s, x.c, y.c, taps);
   hipStream_t st = (hipStream_t)stream;
   const uint16_t* xp = (const uint16_t*)x.p;
   const uint16_t* wp = (const uint16_t*)w;
   uint16_t* yp = (uint16_t*)y.p;
-  const int ob = y.c / 16;  // 16-channel output blocks
-  if (ob != 1 && ob != 2 && ob != 4 && ob != 8)
-    return ufail(UNET_EINVAL, "output channels must be 16, 32, 64 or 128");
-  // LDS-tiled form for grids with w a multiple of 64 and h of 4, or w = 32
-  // and h a multiple of 8; 8 to 64 input channels and 16 to 64 output
-  // channels.  Small grids split the output channels over workgroups until
-  // every CU has as many workgroups as its LDS holds (measured on 32^3 grids:
-  // 32 -> 64 channels 188 -> 302 TFLOP/s, 64 -> 64 220 -> 308).
-  const bool t64 = s.w % 64 == 0 && s.h % 4 == 0, t32 = s.w == 32 && s.h % 8 == 0;
-  if (taps == 27 && (t64 || t32) && (x.c == 8 || x.c == 16 || x.c == 32 || x.c == 64) &&
-      ob <= 4) {
-    const long long tiles = nv / 256;
-    const long long lds = 3LL * (256 / (t64 ? 64 : 32) + 2) * ((t64 ? 64 : 32) + 2) * x.c * 2;
-    const long long target = 256 * std::min<long long>(4, (160 * 1024) / lds);
-    int nb = ob;
-    while (nb > 1 && tiles * (ob / nb) < target) nb /= 2;
-    const dim3 tg((unsigned)tiles, (unsigned)(ob / nb));
-    auto go = [&](auto cinc, auto nbc) {
-      constexpr int CIN = decltype(cinc)::value, NB = decltype(nbc)::value;
-      if (t64)
-        hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB, 64>), tg, dim3(256), 0, st, s, xp, x.ld,
-                           x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
-      else
-        hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB, 32>), tg, dim3(256), 0, st, s, xp, x.ld,
-                           x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
-    };
-    auto by_out = [&](auto cinc) {
-      if (nb == 1)
-        go(cinc, std::integral_constant<int, 1>{});
-      else if (nb == 2)
-        go(cinc, std::integral_constant<int, 2>{});
-      else
-        go(cinc, std::integral_constant<int, 4>{});
-    };
-    if (x.c == 8)
-      by_out(std::integral_constant<int, 8>{});
-    else if (x.c == 16)
-      by_out(std::integral_constant<int, 16>{});
-    else if (x.c == 32)
-      by_out(std::integral_constant<int, 32>{});
-    else
-      by_out(std::integral_constant<int, 64>{});
-    UHIP(hipGetLastError());
-    return UNET_OK;
-  }
-  // Gathered form: the widest output-channel block per wave that still gives
-  // every CU a workgroup, with 64 voxels per wave, else 16 (measured: 16^3
-  // grids 18-21 -> 54-88 TFLOP/s, 32^3 with 128 channels 105-126 -> 170-180).
-  int mb = 4, nb = ob;
-  auto wgs = [&](int m, int b) { return ((nv + 64 * m - 1) / (64 * m)) * (ob / b); };
-  while (nb > 1 && wgs(4, nb) < 256) nb /= 2;
-  if (wgs(4, nb) < 256) {
-    mb = 1;
-    nb = ob;
-    while (nb > 1 && wgs(1, nb) < 256) nb /= 2;
-  }
-  const dim3 grid((unsigned)((nv + 64 * mb - 1) / (64 * mb)), (unsigned)(ob / nb));
-  auto launch = [&](auto mbc, auto nbc) {
-    constexpr int MB = decltype(mbc)::value, NB = decltype(nbc)::value;
-    hipLaunchKernelGGL((k_conv_fwd<MB, NB>), grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c, wp,
-                       bias, taps, yp, y.ld, y.off, out_f32, relu);
-  };
-  auto by_nb = [&](auto mbc) {
-    switch (nb) {
-      case 1: launch(mbc, std::integral_constant<int, 1>{}); break;
-      case 2: launch(mbc, std::integral_constant<int, 2>{}); break;
-      case 4: launch(mbc, std::integral_constant<int, 4>{}); break;
-      default: launch(mbc, std::integral_constant<int, 8>{}); break;
+  const dim3 grid((unsigned)p.grid, (unsigned)(ob / p.nb));
+  auto nbs = [&](auto fn) {  // NB as a compile-time constant
+    switch (p.nb) {
+      case 1: fn(std::integral_constant<int, 1>{}); break;
+      case 2: fn(std::integral_constant<int, 2>{}); break;
+      case 4: fn(std::integral_constant<int, 4>{}); break;
+      default: fn(std::integral_constant<int, 8>{}); break;
     }
   };
-  if (mb == 4)
-    by_nb(std::integral_constant<int, 4>{});
-  else
-    by_nb(std::integral_constant<int, 1>{});
+  if (p.kind == CONV_TILE) {
+    auto go = [&](auto cinc) {
+      constexpr int CIN = decltype(cinc)::value;
+      nbs([&](auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        if constexpr (NB <= 4) {
+          if (p.tw == 64)
+            hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB, 64>), grid, dim3(256), 0, st, s, xp,
+                               x.ld, x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
+          else
+            hipLaunchKernelGGL((k_conv_fwd_tile<CIN, NB, 32>), grid, dim3(256), 0, st, s, xp,
+                               x.ld, x.off, wp, bias, yp, y.ld, y.off, out_f32, relu);
+        }
+      });
+    };
+    if (x.c == 8)
+      go(std::integral_constant<int, 8>{});
+    else if (x.c == 16)
+      go(std::integral_constant<int, 16>{});
+    else if (x.c == 32)
+      go(std::integral_constant<int, 32>{});
+    else
+      go(std::integral_constant<int, 64>{});
+  } else {
+    nbs([&](auto nbc) {
+      constexpr int NB = decltype(nbc)::value;
+      if (p.mb == 4)
+        hipLaunchKernelGGL((k_conv_fwd<4, NB>), grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c,
+                           wp, bias, taps, yp, y.ld, y.off, out_f32, relu);
+      else if constexpr (NB <= 2)
+        hipLaunchKernelGGL((k_conv_fwd<1, NB>), grid, dim3(256), 0, st, s, xp, x.ld, x.off, x.c,
+                           wp, bias, taps, yp, y.ld, y.off, out_f32, relu);
+    });
+  }
   UHIP(hipGetLastError());
+  return UNET_OK;
+}
+
+unet_status unet_conv_kernel(unet_shape s, int32_t cin, int32_t cout, int32_t taps,
+                             int32_t* info) {
+  if (!info || !shape_ok(s) || cin <= 0 || cin % 8 || cin > 256 || (taps != 27 && taps != 1) ||
+      (cout != 16 && cout != 32 && cout != 64 && cout != 128))
+    return ufail(UNET_EINVAL, "bad conv_kernel args");
+  const ConvPlan p = conv_plan(s, cin, cout, taps);
+  info[0] = p.kind;
+  info[1] = p.kind == CONV_GATHER ? p.mb : p.tw;
+  info[2] = p.nb;
+  info[3] = cout / 16 / p.nb;
   return UNET_OK;
 }
 

@@ -41,6 +41,7 @@ _SIGS = [
     ("unet_wgrad_workspace", ctypes.c_size_t, [unet_shape, _I, _I, _I]),
     ("unet_conv_wgrad", ctypes.c_int, [unet_shape, unet_act, unet_act, _I, _V, _V, _V, _V]),
     ("unet_wgrad_kernel", ctypes.c_int, [unet_shape, _I, _I, _I, _V]),
+    ("unet_conv_kernel", ctypes.c_int, [unet_shape, _I, _I, _I, _V]),
     ("unet_relu_bwd", ctypes.c_int, [unet_shape, unet_act, unet_act, unet_act, _V]),
     ("unet_pool_fwd", ctypes.c_int, [unet_shape, unet_act, unet_act, _V]),
     ("unet_pool_bwd", ctypes.c_int, [unet_shape, unet_act, unet_act, _I, _V]),
@@ -126,6 +127,21 @@ def unet_wgrad_workspace(s, cin, cout, taps):
 
 def unet_conv_wgrad(s, x, dy, taps, dw, db, ws):
     _check(load().unet_conv_wgrad(s, x, dy, taps, _p(dw), _p(db), _p(ws), _stream()))
+
+
+CONV_KINDS = {0: "gather", 1: "tile"}
+
+
+def unet_conv_kernel(s, cin, cout, taps):
+    """Kernel choice of unet_conv_fwd (host only): dict with kind ("tile" or
+    "gather"), tw (tile width) or mb (voxel blocks of 16 per wave), nb (output
+    blocks per wave) and groups (output-channel groups)."""
+    info = (ctypes.c_int32 * 4)()
+    _check(load().unet_conv_kernel(s, cin, cout, taps, ctypes.cast(info, ctypes.c_void_p)))
+    kind = CONV_KINDS[info[0]]
+    out = {"kind": kind, "nb": info[2], "groups": info[3]}
+    out["mb" if kind == "gather" else "tw"] = info[1]
+    return out
 
 
 def unet_wgrad_kernel(s, cin, cout, taps):

@@ -77,7 +77,8 @@ CONV_CASES = [(2, 8, 16, (5, 6, 7)), (1, 16, 32, (4, 4, 9)), (2, 32, 64, (3, 5, 
               (1, 32, 16, (3, 4, 64)), (2, 8, 16, (2, 4, 64)), (1, 8, 32, (3, 8, 64)),
               (1, 64, 64, (2, 4, 64)), (1, 32, 64, (3, 4, 64)), (1, 64, 16, (2, 8, 64)),
               # w = 32, h a multiple of 8: 32 x 8 tiles
-              (2, 32, 64, (2, 8, 32)), (1, 64, 64, (3, 16, 32)), (1, 16, 32, (2, 8, 32))]
+              (2, 32, 64, (2, 8, 32)), (1, 64, 64, (3, 16, 32)), (1, 16, 32, (2, 8, 32)),
+              (2, 8, 16, (3, 8, 32))]
 
 
 @pytest.mark.parametrize("n,cin,cout,dhw", CONV_CASES)
@@ -143,15 +144,18 @@ def test_conv_dgrad_and_wgrad(n, cin, cout, dhw):
 
 
 # Forward cases on larger grids, compared at sampled voxels (every output
-# channel).  LDS-tiled: 4 output blocks per workgroup, 2 (whole and split
-# over 2 workgroups), 1 of 4 on 32 x 8 tiles.  Gathered, 64 voxels per wave:
-# 8 output blocks, 4 of 8, 2 of 4, 1; 16 voxels per wave: 2 of 8.  (Small
-# grids, as in CONV_CASES, take 16 voxels and one output block per wave.)
-CONV_LARGE_CASES = [(1, 32, 64, (32, 64, 64)), (1, 32, 32, (32, 64, 64)),
-                    (1, 16, 64, (16, 64, 128)), (1, 32, 64, (32, 32, 32)),
-                    (1, 24, 128, (16, 64, 64)), (1, 64, 128, (32, 32, 32)),
-                    (1, 128, 64, (32, 32, 32)), (1, 24, 16, (16, 64, 64)),
-                    (1, 128, 128, (16, 16, 16))]
+# channel), chosen so that with CONV_CASES every kernel instance the launch
+# plan can pick runs at least once (tests/test_unet_plan.py checks this on
+# the host).  LDS tiles with 2 and 4 output blocks per wave for 8, 16, 32 and
+# 64 input channels on 64 x 4 and 32 x 8 tiles (grids with enough tiles that
+# the output channels are not split); gathered operands with 64 voxels per
+# wave and 8, 4 (of 8), 2 (of 4) and 1 output blocks, or 16 voxels and 2 (of
+# 8).  Small grids, as in CONV_CASES, take one output block per wave.
+CONV_LARGE_CASES = ([(1, cin, 16 * nb, (64, 64, 64) if tw == 64 else (128, 64, 32))
+                     for cin in (8, 16, 32, 64) for nb in (2, 4) for tw in (64, 32)]
+                    + [(1, 24, 128, (16, 64, 64)), (1, 64, 128, (32, 32, 32)),
+                       (1, 128, 64, (32, 32, 32)), (1, 24, 16, (16, 64, 64)),
+                       (1, 128, 128, (16, 16, 16))])
 
 
 @pytest.mark.parametrize("n,cin,cout,dhw", CONV_LARGE_CASES)
