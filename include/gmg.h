@@ -144,6 +144,14 @@ typedef struct gmg_params {
                             single-level grid always takes nu_coarse sweeps
                             per cycle.  Must be in [0, 1) (default 0.1)      */
   int32_t coarse_max;    /* sweep cap of that rule, 1 .. 4096 (default 64)    */
+  double ir_target;      /* refinement (gmg_solve_ir, gmg_batch_solve_ir): the
+                            inner tolerance of an outer step that starts from
+                            residual r is max(inner_rtol, ir_target * rtol *
+                            ||sigma|| / ||r||), so the step's inner solve
+                            stops once the outer tolerance is within reach
+                            instead of always reducing its own residual by
+                            inner_rtol.  0: inner_rtol alone.  In [0, 1]
+                            (default 0.5)                                      */
 } gmg_params;
 
 #define GMG_MAX_HISTORY 512
@@ -349,8 +357,9 @@ typedef struct gmg_ir_info {
  *   r = sigma - A x (FP64); stop if ||r|| <= rtol ||sigma|| or m == max_outer;
  *   beta = ||r|| / sqrt(#active cells); b = fp32(r / beta);
  *   e = adaptive FP32 GMG solve of A e = b from e = 0 (omega reset to omega0,
- *       same rule as gmg_solve) until ||b - A e|| <= inner_rtol ||b|| or
- *       max_inner cycles;
+ *       same rule as gmg_solve) until ||b - A e|| <= t ||b|| or max_inner
+ *       cycles, t = max(inner_rtol, ir_target rtol ||sigma|| / ||r||)
+ *       (t = inner_rtol with ir_target 0);
  *   x += beta * e (FP64).
  * x (in: initial guess, out: solution) and sigma are device FP64 arrays of the
  * level-0 shape.  All decisions are taken on the device; the host polls one

@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256) void k_b_ir_check(const BOuter<TL>* __restrict
     ir->done = 1;
   } else {
     ir->beta = rn / sqrt((double)max(ir->n_active, 1));
+    ir->inner_rtol = ir_inner_tolerance(ir, rn);
   }
 }
 
@@ -246,14 +247,15 @@ __global__ __launch_bounds__(BT) void k_b_scale_cast(const BOuter<TL>* __restric
   if (tid == 0) o.partB[t.slot] = s;
 }
 
+// Inner solve of the step, to the step's inner tolerance (ir_inner_tolerance).
 template <typename TL>
 __global__ __launch_bounds__(256) void k_b_solve_init(const BOuter<TL>* __restrict__ ov,
-                                                      double inner_rtol, int max_inner,
-                                                      double omega0) {
+                                                      int max_inner, double omega0) {
   const BOuter<TL>& o = ov[blockIdx.x];
   if (o.ir->done) return;
   const double ss = reduce_partials(o.partB, o.npart);
   if (threadIdx.x == 0) {
+    const double inner_rtol = o.ir->inner_rtol;
     SolveState* st = o.st;
     st->snorm = sqrt(ss);
     st->rho = st->rho0 = st->last = sqrt(ss);  // e = 0: the residual is b
@@ -296,7 +298,8 @@ __global__ __launch_bounds__(BT) void k_b_ir_update(const BOuter<TL>* __restrict
 
 template <typename TL>
 __global__ __launch_bounds__(256) void k_b_ir_init(const BOuter<TL>* __restrict__ ov, double rtol,
-                                                   int max_outer) {
+                                                   int max_outer, double inner_base,
+                                                   double target) {
   const BOuter<TL>& o = ov[blockIdx.x];
   // partials A hold ||sigma||^2 pieces, partials B the active-cell counts
   const double ss = reduce_partials(o.partA, o.npart);
@@ -310,6 +313,8 @@ __global__ __launch_bounds__(256) void k_b_ir_init(const BOuter<TL>* __restrict_
     ir->outer = 0;
     ir->inner_total = 0;
     ir->max_outer = max_outer;
+    ir->inner_base = ir->inner_rtol = inner_base;
+    ir->target = target;
     ir->done = isfinite(ir->snorm) ? 0 : 1;
     ir->status = isfinite(ir->snorm) ? 5 : kStNonFinite;
     o.st->done = 1;
@@ -627,15 +632,15 @@ gmg_status batch_enqueue_solve(gmg_batch* b, hipStream_t s, bool head, double rt
   const dim3 rblk(BX, BY, 1);
   if (head) {
     hipLaunchKernelGGL(k_b_norm_count<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
-    hipLaunchKernelGGL(k_b_ir_init<TL>, dim3(b->n), dim3(256), 0, s, ov, rtol, max_outer);
+    hipLaunchKernelGGL(k_b_ir_init<TL>, dim3(b->n), dim3(256), 0, s, ov, rtol, max_outer,
+                       inner_rtol, p.ir_target);
     hipLaunchKernelGGL(k_b_resid64<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
     hipLaunchKernelGGL(k_b_ir_check<TL>, dim3(b->n), dim3(256), 0, s, ov);
   }
   const OmegaRule rule = b->h[0]->rule;
   for (int m = 0; m < steps; ++m) {
     hipLaunchKernelGGL(k_b_scale_cast<TL>, dim3(b->res_cnt), rblk, 0, s, ov, b->res_tiles);
-    hipLaunchKernelGGL(k_b_solve_init<TL>, dim3(b->n), dim3(256), 0, s, ov, inner_rtol, max_inner,
-                       p.omega0);
+    hipLaunchKernelGGL(k_b_solve_init<TL>, dim3(b->n), dim3(256), 0, s, ov, max_inner, p.omega0);
     for (int c = 0; c < max_inner; ++c) {
       int role[kMaxLevels];
       // consecutive sweeps of a smoothing step run as two-sweep passes where
@@ -743,9 +748,11 @@ gmg_status gmg_batch_setup(const gmg_params* params, const void* const* L, int32
         q.nu_coarse != p0.nu_coarse || q.rollback != p0.rollback || q.omega0 != p0.omega0 ||
         q.omega_min != p0.omega_min || q.omega_max != p0.omega_max ||
         q.theta_dec != p0.theta_dec || q.theta_inc != p0.theta_inc ||
-        q.coarse_rtol != p0.coarse_rtol || q.coarse_max != p0.coarse_max)
+        q.coarse_rtol != p0.coarse_rtol || q.coarse_max != p0.coarse_max ||
+        q.ir_target != p0.ir_target)
       return fail(GMG_EINVAL,
-                  "batch problems must share storage, sweeps, the coarse rule and the omega rule");
+                  "batch problems must share storage, sweeps, the coarse rule, the omega rule "
+                  "and ir_target");
   }
   gmg_batch* b = new (std::nothrow) gmg_batch();
   if (!b) return fail(GMG_ENOMEM, "host allocation failed");

@@ -50,9 +50,23 @@ struct IRState {
   int inner_total;
   int n_active;
   int pad0, pad1;
+  double inner_base;  // inner tolerance asked for by the caller
+  double target;      // ir_target of the parameters (0: inner_base alone)
+  double inner_rtol;  // inner tolerance of the next outer step
   double hist[GMG_MAX_HISTORY];
   int inner[GMG_MAX_HISTORY];
 };
+
+// Inner tolerance of the outer step that starts from residual norm rn: the
+// caller's inner tolerance, raised to target * rtol * ||sigma|| / rn when that
+// is larger, so that the inner solve stops once the correction brings the
+// outer residual within reach of the outer tolerance instead of always
+// reducing its own residual by the full inner factor.
+__device__ inline double ir_inner_tolerance(const IRState* ir, double rn) {
+  if (ir->target > 0.0 && rn > 0.0)
+    return fmax(ir->inner_base, ir->target * ir->rtol * ir->snorm / rn);
+  return ir->inner_base;
+}
 
 // Status of a solve (or refinement) state that met a non-finite norm: NaN or
 // Inf in sigma, in the initial guess or in the faces, or an overflow.  The

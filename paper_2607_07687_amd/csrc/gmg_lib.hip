@@ -351,13 +351,16 @@ __device__ double reduce_partials(const double* p, long long n) {
   return block_sum(s, tid, blockDim.x);
 }
 
-// Start of a solve: ||sigma|| (partials a) and ||r(x0)|| (partials b).
+// Start of a solve: ||sigma|| (partials a) and ||r(x0)|| (partials b).  The
+// tolerance is rtol, or *rtol_p when given (a refinement step's inner
+// tolerance, set on the device).
 __global__ __launch_bounds__(256) void k_solve_init(const double* pa, long long na,
                                                     const double* pb, long long nb,
                                                     SolveState* st, double rtol,
                                                     int max_cycles, double omega0,
-                                                    const int* skip) {
+                                                    const int* skip, const double* rtol_p) {
   if (skip != nullptr && *skip) return;
+  if (rtol_p != nullptr) rtol = *rtol_p;
   const double ss = reduce_partials(pa, na);
   __syncthreads();
   const double rr = reduce_partials(pb, nb);
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(BT) void k_count_mask(Geom g, const uint8_t* __rest
 // Start of a refinement solve: ||sigma|| and the active-cell count.
 __global__ __launch_bounds__(256) void k_ir_init(const double* ps, const double* pc, long long n,
                                                  IRState* ir, SolveState* inner, double rtol,
-                                                 int max_outer) {
+                                                 int max_outer, double inner_base, double target) {
   const double ss = reduce_partials(ps, n);
   __syncthreads();
   const double cnt = reduce_partials(pc, n);
@@ -524,6 +527,8 @@ __global__ __launch_bounds__(256) void k_ir_init(const double* ps, const double*
     ir->outer = 0;
     ir->inner_total = 0;
     ir->max_outer = max_outer;
+    ir->inner_base = ir->inner_rtol = inner_base;
+    ir->target = target;
     ir->done = isfinite(ir->snorm) ? 0 : 1;
     ir->status = isfinite(ir->snorm) ? 5 : kStNonFinite;
     inner->done = 1;
@@ -549,6 +554,7 @@ __global__ __launch_bounds__(256) void k_ir_check(const double* p, long long n, 
     ir->done = 1;
   } else {
     ir->beta = rn / sqrt((double)max(ir->n_active, 1));
+    ir->inner_rtol = ir_inner_tolerance(ir, rn);
   }
 }
 
@@ -1266,6 +1272,8 @@ static gmg_status validate(const gmg_params* p) {
     return fail(GMG_EINVAL, "coarse_rtol must be in [0, 1)");
   if (p->coarse_rtol > 0.0 && (p->coarse_max < 1 || p->coarse_max > 4096))
     return fail(GMG_EINVAL, "coarse_max must be in [1, 4096]");
+  if (!(p->ir_target >= 0.0 && p->ir_target <= 1.0))
+    return fail(GMG_EINVAL, "ir_target must be in [0, 1]");
   if (p->smoother != GMG_SMOOTH_RBGS && p->smoother != GMG_SMOOTH_PCG)
     return fail(GMG_EINVAL, "smoother must be GMG_SMOOTH_RBGS or GMG_SMOOTH_PCG");
   if (p->deferred_norm != 0 && p->deferred_norm != 1)
@@ -1553,7 +1561,7 @@ static gmg_status ir_outer_step(gmg_handle* h, double* x, const double* sigma, i
                      h->b32, h->e32, h->partials + h->maxpart, kResChunk);
   hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, h->s, h->partials + h->maxpart, np,
                      h->partials + h->maxpart, np, h->st, inner_rtol, max_inner, h->p.omega0,
-                     &h->ir->done);
+                     &h->ir->done, (const double*)&h->ir->inner_rtol);
   const Roles<float> XS{{h->e32, (float*)h->w[0], (float*)h->w[1]}, &h->st->cur};
   for (int c = 0; c < max_inner; ++c) {
     const int f = enq_vcycle<float, TL>(h, h->e32, &h->st->cur, h->b32, &h->st->done);
@@ -1749,6 +1757,7 @@ gmg_status gmg_default_params(gmg_params* p) {
   p->theta_inc = 1.2;
   p->coarse_rtol = 0.1;
   p->coarse_max = 64;
+  p->ir_target = 0.5;
   return GMG_OK;
 }
 
@@ -2063,7 +2072,7 @@ gmg_status gmg_solve(gmg_handle* h, void* x, const void* sigma, double rtol, int
                        kResChunk);
     hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(256), 0, h->s, h->partials, np,
                        h->partials + h->maxpart, np, h->st, rtol, (int)max_cycles, h->p.omega0,
-                       nullptr);
+                       nullptr, nullptr);
     HIP_TRY(hipGetLastError());
     int launched = 0, chunk = 2;
     while (true) {
@@ -2157,7 +2166,7 @@ gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rt
   hipLaunchKernelGGL(k_count_mask, gr, kBlock, 0, h->s, lv.g, lv.active, h->partials + h->maxpart,
                      kResChunk);
   hipLaunchKernelGGL(k_ir_init, dim3(1), dim3(256), 0, h->s, h->partials, h->partials + h->maxpart,
-                     np, h->ir, h->st, rtol, (int)max_outer);
+                     np, h->ir, h->st, rtol, (int)max_outer, inner_rtol, h->p.ir_target);
   HIP_TRY(hipGetLastError());
   auto step = [&]() {
     return h->p.l_storage == GMG_BF16 ? ir_outer_step<uint16_t>(h, x, sigma, max_inner, inner_rtol)

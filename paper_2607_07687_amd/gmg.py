@@ -36,7 +36,7 @@ class gmg_params(ctypes.Structure):
                 ("pair_sweeps", ctypes.c_int32), ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
                 ("theta_inc", ctypes.c_double), ("coarse_rtol", ctypes.c_double),
-                ("coarse_max", ctypes.c_int32)]
+                ("coarse_max", ctypes.c_int32), ("ir_target", ctypes.c_double)]
 
 
 class gmg_solve_info(ctypes.Structure):

@@ -101,10 +101,15 @@ def test_batch_matches_oracle_subset():
                         inner_rtol=1e-4, inner_storage="f32")
         assert ro["status"] == "ok" and infos[p]["status"] == "GMG_OK"
         assert abs(infos[p]["outer"] - ro["outer"]) <= 1
-        act = O.active_set(O.normalize_faces(L, per), per)
-        e = (host(xs[p]) - ro["x"])[act]
-        xr = ro["x"][act] - ro["x"][act].mean()
-        assert np.linalg.norm(e - e.mean()) <= 1e-8 * np.linalg.norm(xr)
+        # the returned x meets the tolerance under the oracle's exact FP64
+        # residual (ir_target 0.5 stops the last step near half of it)
+        L64 = O.normalize_faces(L, per)
+        act = O.active_set(L64, per)
+        assert O.norm2(O.residual(host(xs[p]), s, L64, per), act) <= 1e-10 * O.norm2(s, act)
+        # and the two solutions differ by what 2e-10 of the residual allows:
+        # A (x - x_o) = r_o - r, whose norm is at most 2e-10 ||sigma||
+        d = host(xs[p]) - ro["x"]
+        assert O.norm2(O.residual(d, np.zeros_like(s), L64, per), act) <= 2e-10 * O.norm2(s, act)
     b.close()
 
 

@@ -158,10 +158,10 @@ def test_iterative_refinement_reaches_fp64_solution(storage):
     if storage == "bf16":
         # a face perturbation of relative size delta <= 2^-9 keeps A and the
         # rounded operator spectrally equivalent within 1 +- delta, so each
-        # outer step contracts by about delta plus the inner tolerance
+        # outer step contracts by about delta plus that step's inner tolerance
         h = ir["history"]
-        for a, b in zip(h, h[1:]):
-            assert b <= a * (2.0 ** -9 + 1e-4) * 4
+        for a, b, tol in zip(h, h[1:], ir["inner_tols"]):
+            assert b <= a * (2.0 ** -9 + tol) * 4
 
 
 def test_round_to_bf16_is_nearest_even():
@@ -172,3 +172,30 @@ def test_round_to_bf16_is_nearest_even():
     assert got[2] == 1.0 + 2 ** -6  # tie -> even (rounds up)
     assert got[3] == 1.0 + 2 ** -7
     assert abs(got[4] - v[4]) <= 2 ** -9 * abs(v[4])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_refinement_target_stops_inner_solves_at_the_outer_tolerance(seed):
+    # With inner_target = 0.5, the inner solve of a step that starts from
+    # residual r stops at 0.5 rtol ||sigma|| / ||r|| of its right-hand side
+    # when that is above inner_rtol: the step then brings the outer residual
+    # to about 0.5 rtol ||sigma|| (FP32 rounding of b and of the faces adds
+    # ~1e-7 of ||r||), so the solve ends right after it.  Against the fixed
+    # inner tolerance: never more outer steps, fewer or equal inner cycles.
+    L, s, per = P.sphere_box((24, 16, 16), (12.0, 8.0, 8.0), 4.0, "uniform", seed)
+    rtol = 1e-6
+    fixed = O.solve_ir(L, per, np.zeros_like(s), s, rtol=rtol, max_outer=10, max_inner=8,
+                       inner_rtol=1e-4, inner_target=0.0)
+    tgt = O.solve_ir(L, per, np.zeros_like(s), s, rtol=rtol, max_outer=10, max_inner=8,
+                     inner_rtol=1e-4, inner_target=0.5)
+    assert fixed["status"] == "ok" and tgt["status"] == "ok"
+    assert tgt["outer"] <= fixed["outer"] and tgt["inner_total"] <= fixed["inner_total"]
+    assert all(t == 1e-4 for t in fixed["inner_tols"])
+    h = tgt["history"]
+    for k, tol in enumerate(tgt["inner_tols"]):
+        # the tolerance is the larger of inner_rtol and 0.5 rtol / (||r_k|| / ||sigma||)
+        assert tol == max(1e-4, 0.5 * rtol / h[k]) or abs(tol / max(1e-4, 0.5 * rtol / h[k]) - 1) < 1e-12
+        if tol > 1e-4:  # a shortened step finishes the solve
+            assert k == len(tgt["inner_tols"]) - 1 and h[k + 1] <= rtol
+    # the fixed tolerance over-solves its last step far below rtol
+    assert fixed["history"][-1] < 1e-2 * rtol < tgt["history"][-1] <= rtol
