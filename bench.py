@@ -30,6 +30,15 @@ HBM_PEAK_GBS = 8000.0
 # two-sweep pass two).  The pass's own minimum, one read of everything and
 # one write of x for both sweeps, is the same 24 B per cell per launch.
 SWEEP_BYTES_PER_CELL = 24.0
+# With the uniform-brick map the faces of a uniform brick (128 x 2 x 2
+# cells whose faces are one constant per direction) are not data: the
+# kernels take them from the map's 32-B entry.  Per sweep the method then
+# moves 12 B per cell (x, sigma, x) plus the 12 B of faces per cell of the
+# other bricks plus the map.
+SWEEP_BYTES_NO_FACES = 12.0
+FACE_BYTES_PER_CELL = 12.0
+BRICK_CELLS = 128 * 2 * 2
+BRICK_BYTES = 32.0
 
 # hardware-counter summaries of the level-0 smoothing kernels (rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs of `bench.py --kernel-probe`), each naming
@@ -41,7 +50,7 @@ KERNELS = {
               [_CSRC + "gmg_sweep.h", _CSRC + "gmg_device.h", "paper_2607_07687_amd/build.py"]),
     "pair": (os.path.join(ROOT, "profiles", "sweep2_256_fp32_counters.md"),
              [_CSRC + "gmg_sweep2.h", _CSRC + "gmg_sweep.h", _CSRC + "gmg_device.h",
-              "paper_2607_07687_amd/build.py"]),
+              _CSRC + "gmg_kernels.h", "include/gmg.h", "paper_2607_07687_amd/build.py"]),
 }
 
 
@@ -549,19 +558,34 @@ def main():
         return e0.elapsed_time(e1) / (sweeps // per_launch)
 
     pair_kc = tiles[0].get("pair_kchunk", 0)
+    pair_ty = tiles[0].get("pair_ty", 16)
     pass_ms = launch_ms(2) if pair_kc else None
     G.gmg_set_pair_sweeps(h, 0, 0)
     fused_ms = launch_ms(1)
     kind = "pair" if pair_kc else "fused"
     launch = pass_ms if pair_kc else fused_ms
+    uni_bricks, bricks = G.gmg_level_uniform(h, 0)
+    h.close()
+    # the same kernel with no map (every face loaded), at the same tiling
+    nomap_ms = None
+    if pair_kc:
+        params.uniform_bricks = 0
+        h = G.gmg_setup(params, Ld)
+        G.gmg_set_pair_sweeps(h, 0, pair_kc, pair_ty)
+        nomap_ms = launch_ms(2)
+        h.close()
     copy_gbs = device_copy_gbs(stream)
     cells = 256 ** 3
     sweeps_per_launch = 2 if pair_kc else 1
-    alg_bytes = SWEEP_BYTES_PER_CELL * sweeps_per_launch * cells
+    # the pass reads the map; the fused sweep loads every face
+    face_cells = (bricks - uni_bricks) * BRICK_CELLS if pair_kc else cells
+    map_bytes = bricks * BRICK_BYTES if pair_kc else 0.0
+    sweep_bytes = SWEEP_BYTES_NO_FACES * cells + FACE_BYTES_PER_CELL * face_cells + map_bytes
+    alg_bytes = sweep_bytes * sweeps_per_launch
     achieved = alg_bytes / (launch * 1e-3) / 1e9
-    one_read_gbs = SWEEP_BYTES_PER_CELL * cells / (launch * 1e-3) / 1e9
+    one_read_gbs = sweep_bytes / (launch * 1e-3) / 1e9
+    dense_bytes = SWEEP_BYTES_PER_CELL * sweeps_per_launch * cells
     traffic = measured_traffic(kind)
-    h.close()
     if pair_kc:
         kname = (f"k_rb_sweep2<float,float,{tiles[0].get('pair_ty', 16)},false> "
                  "(level-0 two-sweep pass, 2 sweeps per launch)")
@@ -604,8 +628,21 @@ def main():
                      "traffic_unit": "HBM bytes per launch (counters)",
                      "avg_launch_us": launch * 1e3,
                      "alg_bytes_per_launch": alg_bytes,
-                     "alg_bytes_rule": f"{SWEEP_BYTES_PER_CELL:g} B per cell per sweep x "
-                                       f"{sweeps_per_launch} sweep(s) per launch x {cells} cells",
+                     "alg_bytes_rule": f"per sweep {SWEEP_BYTES_NO_FACES:g} B per cell (read x, "
+                                       f"sigma; write x) x {cells} cells + "
+                                       f"{FACE_BYTES_PER_CELL:g} B of faces per cell outside "
+                                       f"uniform bricks x {face_cells} cells + "
+                                       f"{map_bytes:g} B of brick map; x {sweeps_per_launch} "
+                                       "sweep(s) per launch",
+                     "uniform_bricks": [uni_bricks, bricks],
+                     "dense_faces": {
+                         "rule": f"{SWEEP_BYTES_PER_CELL:g} B per cell per sweep (every face "
+                                 f"loaded) x {sweeps_per_launch} x {cells} cells",
+                         "alg_bytes_per_launch": dense_bytes,
+                         "frac_at_map_launch": dense_bytes / (launch * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "no_map_launch_us": nomap_ms * 1e3 if nomap_ms else None,
+                         "no_map_frac": dense_bytes / (nomap_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                         if nomap_ms else None},
                      "one_read_min_gbs": one_read_gbs,
                      "one_read_min_frac": one_read_gbs / HBM_PEAK_GBS,
                      "traffic_gbs": traffic / (launch * 1e-3) / 1e9 if traffic else None,

@@ -152,6 +152,20 @@ typedef struct gmg_params {
                             instead of always reducing its own residual by
                             inner_rtol.  0: inner_rtol alone.  In [0, 1]
                             (default 0.5)                                      */
+  int32_t uniform_bricks; /* 1 (default): gmg_setup and gmg_update_faces mark
+                            the 128 x 2 x 2-cell bricks of every level in
+                            which every face of direction d reads one value
+                            u_d bit for bit (the faces just beyond the
+                            brick's high sides included, the zero faces of a
+                            low wall excepted); the residual kernels (norm,
+                            fused residual + restriction) take such blocks'
+                            faces from u instead of loading them, and so
+                            does the two-sweep pass for tiles whose region
+                            lies in such bricks, on levels of at least 2^23
+                            cells.  2: the same with the two-sweep pass on
+                            every level.  0: off.  Bitwise the same results
+                            in every case; less memory traffic where the
+                            faces are uniform (away from immersed bodies).   */
 } gmg_params;
 
 #define GMG_MAX_HISTORY 512
@@ -219,6 +233,11 @@ gmg_status gmg_level_shape(const gmg_handle* h, int32_t level, int32_t n[3],
  * level, element type l_storage; BF16 as raw uint16) into the caller's
  * device buffer `L_out`.  Asynchronous. */
 gmg_status gmg_level_faces(gmg_handle* h, int32_t level, void* L_out);
+
+/* Uniform-brick map of level `level` (see gmg_params.uniform_bricks): the
+ * number of bricks whose faces are uniform and the number of bricks (both 0
+ * when the map is off).  Synchronises the handle's stream. */
+gmg_status gmg_level_uniform(gmg_handle* h, int32_t level, int64_t* uniform, int64_t* total);
 
 /* Residual of the level-0 problem in dtype arithmetic (Sec. 3: the quantity
  * the V-cycle drives to zero):  r = sigma - A x on active cells, 0 elsewhere.

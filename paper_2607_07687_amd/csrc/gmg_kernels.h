@@ -81,4 +81,20 @@ struct OmegaRule {
 
 constexpr int BX = 128, BY = 2, BT = BX * BY;  // cell-kernel block: two waves per row
 
+// Uniform bricks: BX x BY x 2 cells of a level in which every face of
+// direction d reads the same value u_d (bit for bit), the high faces of the
+// brick's last column, row and plane included, except the faces of a low wall,
+// which read +0.  (A high wall's face is never read: the stencil takes it as
+// zero.)  The residual kernels take such a block's faces from u and the wall
+// flags of each cell instead of loading them: the same values, the same
+// arithmetic, bitwise the same result.  In immersed-boundary problems the faces
+// are 1 (times the coarsening factors on coarse levels) away from the bodies,
+// so most bricks qualify.
+constexpr int kUBZ = 2;  // planes per brick
+struct UBrick {
+  double u[3];  // the faces of x, y, z (as read through ldL)
+  int ok;       // 1: uniform
+  int pad;
+};
+
 }  // namespace gmg

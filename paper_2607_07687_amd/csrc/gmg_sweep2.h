@@ -38,7 +38,8 @@
 
 #include <type_traits>
 
-#include "gmg_sweep.h"  // wrap_coord (and gmg_device.h: relax_cell, xcd_tile)
+#include "gmg_kernels.h"  // UBrick
+#include "gmg_sweep.h"    // wrap_coord (and gmg_device.h: relax_cell, xcd_tile)
 
 namespace gmg {
 
@@ -153,14 +154,24 @@ struct S2Args {
   int corr = 1;
 };
 
+// The faces of a thread's pair column in a tile of uniform bricks (see
+// UBrick), as the loads would return them: u_d, +0 on a low wall, and zeros
+// outside a wall (columns and, per plane, planes).
+template <typename T>
+struct S2Uni {
+  T lx0, lx1, ly, lz;
+};
+
 // Issue the loads of plane m for the column with lane offsets vo4, vo2, vo1
 // (its in-plane offset in 4-, 2- and 1-byte elements, S2_OUT outside a wall)
 // and coarse in-plane offset `coff` (PROL: also the prolongation operands).
 // Every lane issues every load, so the number of loads in flight is the same
 // on every path and the compiler waits for exactly the plane being taken.
-template <typename T, typename TL, bool PROL>
+// UNI: the faces are the constants of f instead of loads.
+template <typename T, typename TL, bool PROL, bool UNI>
 __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, const S2Bufs& b,
-                                         int m, int vo4, int vo2, int vo1, int coff) {
+                                         int m, int vo4, int vo2, int vo1, int coff,
+                                         const S2Uni<T>& f) {
   const Geom& g = a.g;
   const int mw = wrap_coord(m, g.nz, g.pz);  // uniform
   const bool pin = mw >= 0;
@@ -168,9 +179,16 @@ __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, 
   const int so1 = mm * (int)g.sz, so2 = 2 * so1, so4 = 4 * so1;
   s2_ld2<T>(pin ? b.S : b.zero, vo4, so4, ld.s);
   s2_ld2<T>(pin ? b.sg : b.zero, vo4, so4, ld.sg);
-  s2_ldL2<T, TL>(pin ? b.lx : b.zero, vo4, vo2, so4, so2, ld.lx);
-  s2_ldL2<T, TL>(pin ? b.ly : b.zero, vo4, vo2, so4, so2, ld.ly);
-  s2_ldL2<T, TL>(pin ? b.lz : b.zero, vo4, vo2, so4, so2, ld.lz);
+  if constexpr (UNI) {
+    ld.lx[0] = pin ? f.lx0 : T(0);
+    ld.lx[1] = pin ? f.lx1 : T(0);
+    ld.ly[0] = ld.ly[1] = pin ? f.ly : T(0);
+    ld.lz[0] = ld.lz[1] = (pin && (mw > 0 || g.pz)) ? f.lz : T(0);
+  } else {
+    s2_ldL2<T, TL>(pin ? b.lx : b.zero, vo4, vo2, so4, so2, ld.lx);
+    s2_ldL2<T, TL>(pin ? b.ly : b.zero, vo4, vo2, so4, so2, ld.ly);
+    s2_ldL2<T, TL>(pin ? b.lz : b.zero, vo4, vo2, so4, so2, ld.lz);
+  }
   if constexpr (PROL) {
     // factors are 1 or 2; the pair's second cell has the next parent only
     // when c_x = 1.  Outside a wall the mask reads zero, and the coarse
@@ -232,11 +250,13 @@ __device__ __forceinline__ T s2_residual(T xc, T xe, T xw, T xn, T xs, T xt, T x
 // Sweeps 1 and 2 of the tile with origin (i0, j0) over the z-planes [k0, k1)
 // (PROL: with the coarse correction folded into S).  RES: also the sum of the
 // squared residuals of S over the tile's own active cells and planes (the
-// norm of the pass's input), returned to thread 0 (0 elsewhere).
-template <typename T, typename TL, int TY, bool PROL, bool RES = false>
+// norm of the pass's input), returned to thread 0 (0 elsewhere).  UNI: the
+// tile's grown region lies in uniform bricks of constants uc (s2_uniform_tile),
+// whose faces are then not loaded.
+template <typename T, typename TL, int TY, bool PROL, bool RES = false, bool UNI = false>
 __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T, TL>& a,
                                                  T* __restrict__ W, int i0, int j0, int k0,
-                                                 int k1, T omega) {
+                                                 int k1, T omega, const double* uc = nullptr) {
   using C = S2Cfg<TY>;
   const Geom& g = a.g;
   const int t = threadIdx.x;
@@ -255,6 +275,14 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
   const int coff = (off >= 0) ? (int)((jj >> (a.cy >> 1)) * a.gc.sy) + (ii >> (a.cx >> 1)) : 0;
   const int vo1 = off >= 0 ? off : S2_OUT, vo2 = off >= 0 ? 2 * off : S2_OUT,
             vo4 = off >= 0 ? 4 * off : S2_OUT;
+  S2Uni<T> fu{};
+  if constexpr (UNI) {
+    const bool in = off >= 0;
+    fu.lx0 = (in && (ii > 0 || g.px)) ? T(uc[0]) : T(0);
+    fu.lx1 = in ? T(uc[0]) : T(0);
+    fu.ly = (in && (jj > 0 || g.py)) ? T(uc[1]) : T(0);
+    fu.lz = in ? T(uc[2]) : T(0);
+  }
   const int nb = (int)g.n;  // at most S2_MAX_CELLS
   const S2Bufs b{__builtin_amdgcn_make_buffer_rsrc((void*)a.S, 0, 4 * nb, S2_RSRC_W3),
                  __builtin_amdgcn_make_buffer_rsrc((void*)a.sigma, 0, 4 * nb, S2_RSRC_W3),
@@ -296,11 +324,12 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
   }
   // prologue: planes k0-4 and k0-3 in registers (with two load sets, k0-2 in
   // flight); the loop starts at step k0-7, whose P3, P4 are those planes
-  s2_fetch<T, TL, PROL>(la, a, b, k0 - 4, vo4, vo2, vo1, coff);
-  s2_fetch<T, TL, PROL>(lb, a, b, k0 - 3, vo4, vo2, vo1, coff);
+  s2_fetch<T, TL, PROL, UNI>(la, a, b, k0 - 4, vo4, vo2, vo1, coff, fu);
+  s2_fetch<T, TL, PROL, UNI>(lb, a, b, k0 - 3, vo4, vo2, vo1, coff, fu);
   s2_take<T, PROL>(P3, la);
   s2_take<T, PROL>(P4, lb);
-  if constexpr (C::NSET == 2) s2_fetch<T, TL, PROL>(la, a, b, k0 - 2, vo4, vo2, vo1, coff);
+  if constexpr (C::NSET == 2)
+    s2_fetch<T, TL, PROL, UNI>(la, a, b, k0 - 2, vo4, vo2, vo1, coff, fu);
   // step k0-8's exchange (S, Ly, Lx of plane k0-4 = P3) so that step k0-7
   // can complete P3's high faces
   {
@@ -322,9 +351,9 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
     // or with one load set those of plane k+5 into `cur`; beyond the chunk's
     // last needed plane (k1+3) they are loaded but never used
     if constexpr (C::NSET == 2)
-      s2_fetch<T, TL, PROL>(nxt, a, b, k + 6, vo4, vo2, vo1, coff);
+      s2_fetch<T, TL, PROL, UNI>(nxt, a, b, k + 6, vo4, vo2, vo1, coff, fu);
     else
-      s2_fetch<T, TL, PROL>(cur, a, b, k + 5, vo4, vo2, vo1, coff);
+      s2_fetch<T, TL, PROL, UNI>(cur, a, b, k + 5, vo4, vo2, vo1, coff, fu);
     // complete plane k+3: high faces from the previous step's exchange
     P3.lxh = sm.lx0[q][R][ce];
     P3.lyh[0] = sm.ly[q][RN][cs];
@@ -471,6 +500,40 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
   return 0.0;
 }
 
+// Whether every face the tile with origin (i0, j0) and z-planes [k0, k1)
+// reads (the low faces of the in-domain cells of its grown region: columns
+// i0 - 4 .. i0 + 67, rows j0 - 4 .. j0 + TY + 3, planes k0 - 4 .. k1 + 3,
+// wrapped where periodic) lies in uniform bricks with the constants of the
+// brick of the tile's origin; then u holds them.  The region spans at most
+// two bricks in x, those of its first and last columns (or of i0 where the
+// first is outside a wall); the workgroup checks the bricks of those columns
+// on every row and plane of the region, a few independent loads per thread.
+// Called by the whole workgroup.
+template <int TY>
+__device__ bool s2_uniform_tile(const Geom& g, const UBrick* __restrict__ ub, int ubx, int uby,
+                                int i0, int j0, int k0, int k1, double (&u)[3]) {
+  if (ub == nullptr) return false;  // uniform over the workgroup
+  const UBrick* ref = ub + ((long long)(k0 / kUBZ) * uby + j0 / BY) * ubx + i0 / BX;
+  u[0] = ref->u[0];
+  u[1] = ref->u[1];
+  u[2] = ref->u[2];
+  bool ok = ref->ok != 0;
+  const int nys = TY + 8, nzs = k1 - k0 + 8, nslot = 3 * nys * nzs;
+#pragma unroll 4
+  for (int q = threadIdx.x; q < nslot; q += blockDim.x) {
+    const int xs = q % 3, ys = (q / 3) % nys, zs = q / (3 * nys);
+    const int ii = wrap_coord(xs == 0 ? i0 - 4 : (xs == 1 ? i0 : i0 + S2_TX + 3), g.nx, g.px);
+    const int jj = wrap_coord(j0 - 4 + ys, g.ny, g.py);
+    const int mw = wrap_coord(k0 - 4 + zs, g.nz, g.pz);
+    const bool in = ii >= 0 && jj >= 0 && mw >= 0;  // outside a wall: no faces
+    const UBrick& b = in ? ub[((long long)(mw / kUBZ) * uby + jj / BY) * ubx + ii / BX] : *ref;
+    ok &= b.ok != 0 && __double_as_longlong(b.u[0]) == __double_as_longlong(u[0]) &&
+          __double_as_longlong(b.u[1]) == __double_as_longlong(u[1]) &&
+          __double_as_longlong(b.u[2]) == __double_as_longlong(u[2]);
+  }
+  return __syncthreads_and(ok ? 1 : 0) != 0;
+}
+
 }  // namespace gmg
 
 // Two sweeps in one pass: X[rd] = sweep(sweep(X[rs] (+ P x_c))), at global
@@ -479,16 +542,21 @@ template <typename T, typename TL, int TY, bool PROL>
 __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
     gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
     const TL* __restrict__ L, const T* __restrict__ xc, const uint8_t* __restrict__ active,
-    gmg::Geom gc, int cx, int cy, int cz, int kchunk, const double* omega_p, const int* done) {
+    gmg::Geom gc, int cx, int cy, int cz, int kchunk, const double* omega_p, const int* done,
+    const gmg::UBrick* ub, int ubx, int uby) {
   if (gmg::stopped(done)) return;
   __shared__ gmg::S2Smem<T, TY> sm;
   gmg::S2Args<T, TL> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
   const int ntx = (g.nx + gmg::S2_TX - 1) / gmg::S2_TX, nty = (g.ny + TY - 1) / TY;
   const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);
   const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-  const int k0 = tz * kchunk;
-  gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0,
-                                 min(g.nz, k0 + kchunk), (T)(*omega_p));
+  const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
+  const T omega = (T)(*omega_p);
+  double u[3];
+  if (gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u))
+    gmg::rb_sweep2_tile<T, TL, TY, PROL, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega, u);
+  else
+    gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
 }
 
 // The first pass of a cycle under the deferred decision: the same pass
@@ -499,7 +567,8 @@ template <typename T, typename TL, int TY>
 __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
     gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
     const TL* __restrict__ L, const uint8_t* __restrict__ active, int kchunk,
-    const double* omega_p, const int* done, double* res_part, const int* gate) {
+    const double* omega_p, const int* done, double* res_part, const int* gate,
+    const gmg::UBrick* ub, int ubx, int uby) {
   if (gmg::stopped(done)) return;
   if (gate != nullptr && *gate == 0) return;
   __shared__ gmg::S2Smem<T, TY> sm;
@@ -507,8 +576,13 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
   const int ntx = (g.nx + gmg::S2_TX - 1) / gmg::S2_TX, nty = (g.ny + TY - 1) / TY;
   const int t = gmg::xcd_tile(blockIdx.x, gridDim.x);
   const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
-  const int k0 = tz * kchunk;
-  const double s = gmg::rb_sweep2_tile<T, TL, TY, false, true>(
-      sm, a, X.get(rd), tx * gmg::S2_TX, ty * TY, k0, min(g.nz, k0 + kchunk), (T)(*omega_p));
+  const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
+  const T omega = (T)(*omega_p);
+  double u[3];
+  const double s =
+      gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u)
+          ? gmg::rb_sweep2_tile<T, TL, TY, false, true, true>(sm, a, X.get(rd), i0, j0, k0, k1,
+                                                               omega, u)
+          : gmg::rb_sweep2_tile<T, TL, TY, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
   if (res_part != nullptr && threadIdx.x == 0) res_part[blockIdx.x] = s;
 }

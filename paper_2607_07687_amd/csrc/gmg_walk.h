@@ -19,15 +19,18 @@ namespace gmg {
 // issued on every path (a missing neighbour's offset points at the cell
 // itself) and the value selected afterwards, so no branch forces the
 // compiler to wait for all of them.
-template <typename T, typename TL, typename V, typename S, typename F>
-__device__ __forceinline__ void walk_column_vs(const Geom& g, V&& v, S&& side,
-                                               const TL* __restrict__ L, int i, int j, int k0,
-                                               int k1, F&& f) {
+//
+// walk_column_vsf takes the faces through face(d, q, hi), the face of
+// direction d stored at cell q, where hi tells a cell's high face (q is the
+// neighbour's index) from its low one: the stored faces, or a block's constant
+// faces (uniform bricks, whose low walls keep their zero faces), with the same
+// arithmetic either way.
+template <typename T, typename V, typename S, typename FL, typename F>
+__device__ __forceinline__ void walk_column_vsf(const Geom& g, V&& v, S&& side, FL&& face, int i,
+                                                int j, int k0, int k1, F&& f) {
   if (i >= g.nx || j >= g.ny || k0 >= k1) return;
   const Nb nx = neighbours(i, g.nx, g.px, 1);
   const Nb ny = neighbours(j, g.ny, g.py, g.sy);
-  const TL* __restrict__ Ly = L + g.n;
-  const TL* __restrict__ Lz = L + 2 * g.n;
   const long long base = (long long)j * g.sy + i;
   const long long top = (long long)(g.nz - 1) * g.sz;
   // the loads of one plane
@@ -38,13 +41,13 @@ __device__ __forceinline__ void walk_column_vs(const Geom& g, V&& v, S&& side,
     const long long id = (long long)k * g.sz + base;
     const long long hi = (k + 1 < g.nz) ? id + g.sz : base;
     p.vt = v(hi);
-    p.lzt = ldL<T>(Lz, hi);
-    p.lmx = ldL<T>(L, id);
-    p.lhx = ldL<T>(L, id + nx.hi);
+    p.lzt = face(2, hi, true);
+    p.lmx = face(0, id, false);
+    p.lhx = face(0, id + nx.hi, true);
     p.ve = v(id + nx.hi);
     p.vw = v(id + nx.lo);
-    p.lmy = ldL<T>(Ly, id);
-    p.lhy = ldL<T>(Ly, id + ny.hi);
+    p.lmy = face(1, id, false);
+    p.lhy = face(1, id + ny.hi, true);
     p.vn = v(id + ny.hi);
     p.vs = v(id + ny.lo);
     p.sd = side(id);
@@ -52,7 +55,7 @@ __device__ __forceinline__ void walk_column_vs(const Geom& g, V&& v, S&& side,
   long long idx = (long long)k0 * g.sz + base;
   T xc = v(idx);
   T xb = (k0 > 0) ? v(idx - g.sz) : (g.pz ? v(top + base) : xc);  // z low neighbour
-  T lzm = ldL<T>(Lz, idx);
+  T lzm = face(2, idx, false);
   // plane k from its loads, then roll the z-neighbours up
   auto plane = [&](int k, const Plane& cur) {
     // z high neighbour and face: next plane, wrap, or (wall) self with face 0
@@ -92,6 +95,15 @@ __device__ __forceinline__ void walk_column_vs(const Geom& g, V&& v, S&& side,
     cur = nxt;
   }
   plane(k, cur);
+}
+
+template <typename T, typename TL, typename V, typename S, typename F>
+__device__ __forceinline__ void walk_column_vs(const Geom& g, V&& v, S&& side,
+                                               const TL* __restrict__ L, int i, int j, int k0,
+                                               int k1, F&& f) {
+  walk_column_vsf<T>(
+      g, v, side, [&](int d, long long q, bool) { return ldL<T>(L + d * g.n, q); }, i, j, k0,
+      k1, f);
 }
 
 // walk_column_vs without a side value: f(idx, ax, D, vc).

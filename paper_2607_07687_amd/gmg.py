@@ -36,7 +36,8 @@ class gmg_params(ctypes.Structure):
                 ("pair_sweeps", ctypes.c_int32), ("omega0", ctypes.c_double), ("omega_min", ctypes.c_double),
                 ("omega_max", ctypes.c_double), ("theta_dec", ctypes.c_double),
                 ("theta_inc", ctypes.c_double), ("coarse_rtol", ctypes.c_double),
-                ("coarse_max", ctypes.c_int32), ("ir_target", ctypes.c_double)]
+                ("coarse_max", ctypes.c_int32), ("ir_target", ctypes.c_double),
+                ("uniform_bricks", ctypes.c_int32)]
 
 
 class gmg_solve_info(ctypes.Structure):
@@ -91,6 +92,9 @@ _SIGS = [
                                        ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
     ("gmg_level_faces", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("gmg_level_uniform", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]),
     ("gmg_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
@@ -351,6 +355,13 @@ def gmg_level_faces(h, level, out):
     p = _arr(out, "out", 3 * h.cells(level), dt, h.device)
     _check(load().gmg_level_faces(h.ptr, level, p))
     return out
+
+
+def gmg_level_uniform(h, level):
+    """(uniform bricks, bricks) of a level's uniform-brick map."""
+    u, t = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().gmg_level_uniform(h.ptr, level, ctypes.byref(u), ctypes.byref(t)))
+    return u.value, t.value
 
 
 def gmg_residual(h, x, sigma, r=None, norms=True):

@@ -50,6 +50,7 @@ def test_default_params_without_gpu():
     assert (p.omega0, p.omega_min, p.omega_max, p.theta_dec, p.theta_inc) == (1.0, 0.1, 1.0, 0.5, 1.2)
     assert p.rollback == 1
     assert (p.coarse_rtol, p.coarse_max) == (0.1, 64)
+    assert (p.ir_target, p.uniform_bricks) == (0.5, 1)
 
 
 def test_null_arguments_rejected_without_side_effects():
@@ -74,7 +75,8 @@ def test_shape_errors_detected_before_any_device_work():
     p = G.gmg_default_params((8, 8, 8), dtype=G.GMG_F32, cycle_dtype=G.GMG_F64)
     assert lib.gmg_setup(ctypes.byref(p), ctypes.c_void_p(8), None, ctypes.byref(out)) == G.GMG_EINVAL
     # the coarsest-level rule's parameters are checked before any device work
-    for kw in ({"coarse_rtol": 1.0}, {"coarse_rtol": -1e-3}, {"coarse_rtol": 0.1, "coarse_max": 0}):
+    for kw in ({"coarse_rtol": 1.0}, {"coarse_rtol": -1e-3}, {"coarse_rtol": 0.1, "coarse_max": 0},
+               {"uniform_bricks": 3}, {"uniform_bricks": -1}, {"ir_target": 1.5}):
         p = G.gmg_default_params((8, 8, 8), **kw)
         assert lib.gmg_setup(ctypes.byref(p), ctypes.c_void_p(8), None,
                              ctypes.byref(out)) == G.GMG_EINVAL
