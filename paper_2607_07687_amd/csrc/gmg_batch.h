@@ -127,10 +127,10 @@ __global__ __launch_bounds__(BT) void k_b_restrict(const BLevel<TL>* __restrict_
   const BTile t = tiles[blockIdx.x];
   const BLevel<TL>& d = lv[t.d];
   if (*d.done) return;
-  __shared__ float rows[BY][BX];
+  __shared__ float rows[1][BY][BX];
   const Roles<float> X{{d.x[0], d.x[1], d.x[2]}, d.sel};
   restrict_tile<float, TL>(rows, d.g, X.get(role), d.sigma, d.L, d.gc, d.cx, d.cy, d.cz,
-                           d.sigma_next, d.x_next0, t.i0, t.j0, t.k0);
+                           d.sigma_next, d.x_next0, t.i0, t.j0, t.k0, t.k0 + 1);
 }
 
 // Inner-cycle residual norm partials of role `role` at level 0.

@@ -83,14 +83,15 @@ __device__ __forceinline__ void walk_column_s(const Geom& g, const T* __restrict
 
 // r = sigma - A x on active cells (0 elsewhere) for column (i, j) over the
 // z-planes [k0, k1); optional store of r; returns the column's sum of r^2.
-// Faces through face(d, q, hi) (walk_column_vsf).
-template <typename T, typename FL>
+// Faces through face(d, q, hi) (walk_column_vsf, PF planes of loads in
+// flight).
+template <typename T, int PF = 2, typename FL>
 __device__ __forceinline__ double residual_column_f(const Geom& g, const T* __restrict__ x,
                                                     const T* __restrict__ sigma, FL&& face,
                                                     T* __restrict__ r, int i, int j, int k0,
                                                     int k1) {
   double acc = 0.0;
-  walk_column_vsf<T>(
+  walk_column_vsf<T, PF>(
       g, [&](long long q) { return x[q]; }, [&](long long q) { return sigma[q]; }, face, i, j,
       k0, k1, [&](long long idx, T ax, T D, T, T sv) {
         const T rv = (D != T(0)) ? sv - ax : T(0);
@@ -215,6 +216,25 @@ __device__ __forceinline__ int chunk_top_first(int b, int nzb, int per) {
   return (b % ng) * per + (per - 1 - b / ng);
 }
 
+// Logical (x, y, z) block of a 3-D grid from the hardware block, with the
+// linear block index mapped by xcd_tile: each XCD then runs a contiguous
+// range of blocks (whole rows of blocks, whole z-chunks), so the neighbour
+// rows and planes a column walk reads beyond its own block are mostly in the
+// same L2.  The residual norm at 256^3 takes 32.5 us so against 40.3 us in
+// the hardware order; the fused residual + restriction (four planes per
+// block) took longer (49.4 against 46.1 us) and keeps the hardware order.
+__device__ __forceinline__ int3 xcd_block() {
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int t = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  return make_int3(t % gridDim.x, (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y));
+}
+
+// Planes of loads in flight in the residual norm's walk over a block of
+// uniform faces: with the face loads gone a wave's plane is 24 B per lane
+// (FP32), so two planes in flight leave the walk bound by memory latency.
+template <typename T>
+constexpr int kResPF = sizeof(T) == 4 ? 3 : 2;
+
 // r = sigma - A x over a chunk of z-planes; one FP64 partial of r^2 per block
 // (stored by the block's z-chunk, whatever the dispatch order).
 template <typename T, typename TL>
@@ -224,20 +244,20 @@ __global__ __launch_bounds__(BT) void k_residual(Geom g, Roles<T> X, int role,
                                                  double* partials, int kchunk, const int* done,
                                                  int zper, const UBrick* ub, int ubx, int uby) {
   if (stopped(done)) return;
-  const int zb = chunk_top_first(blockIdx.z, gridDim.z, zper);
+  const int3 b = xcd_block();
+  const int zb = chunk_top_first(b.z, gridDim.z, zper);
   const int k0 = zb * kchunk, k1 = min(g.nz, k0 + kchunk);
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  const int i = b.x * BX + threadIdx.x, j = b.y * BY + threadIdx.y;
   double u[3];
   const double acc =
-      uniform_block(ub, ubx, uby, blockIdx.x, blockIdx.y, k0, k1, u)
-          ? residual_column_f<T>(g, X.get(role), sigma, UniformFaces<T>(g, u, i, j, k0), r, i,
-                                 j, k0, k1)
+      uniform_block(ub, ubx, uby, b.x, b.y, k0, k1, u)
+          ? residual_column_f<T, kResPF<T>>(g, X.get(role), sigma, UniformFaces<T>(g, u, i, j, k0),
+                                            r, i, j, k0, k1)
           : residual_column<T, TL>(g, X.get(role), sigma, L, r, i, j, k0, k1);
   if (partials) {
     const int tid = threadIdx.x + BX * threadIdx.y;
     const double s = block_sum(acc, tid, BT);
-    if (tid == 0)
-      partials[((long long)zb * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+    if (tid == 0) partials[((long long)zb * gridDim.y + b.y) * gridDim.x + b.x] = s;
   }
 }
 
@@ -293,57 +313,94 @@ __global__ __launch_bounds__(BT) void k_masked_sumsq(Geom g, const T* __restrict
 
 // Fused residual + restriction, one thread per FINE cell of the BX x BY tile
 // at (i0, j0): each thread sums the residuals of its column over the cz fine
-// planes of coarse plane K; x-pairs are combined by a lane shuffle and y-pairs
-// through LDS; the thread at each block's origin writes sigma_c and zeroes x_c.
-template <typename T, typename TL>
-__device__ __forceinline__ void restrict_tile(T (*rows)[BX], const Geom& gf,
+// planes of each coarse plane of [K0, K1) (at most RC of them, one walk up
+// the column); x-pairs are combined by a lane shuffle and y-pairs through LDS
+// (rows[r] for coarse plane K0 + r); the thread at each block's origin writes
+// sigma_c and zeroes x_c.
+template <typename T, typename TL, int RC = 1>
+__device__ __forceinline__ void restrict_tile(T (*rows)[BY][BX], const Geom& gf,
                                               const T* __restrict__ x,
                                               const T* __restrict__ sigma,
                                               const TL* __restrict__ L, const Geom& gc, int cx,
                                               int cy, int cz, T* __restrict__ sigma_c,
-                                              T* __restrict__ x_c, int i0, int j0, int K,
+                                              T* __restrict__ x_c, int i0, int j0, int K0, int K1,
                                               const double* uni = nullptr) {
+  static_assert(RC == 1 || RC == 2, "one or two coarse planes per tile");
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
-  T acc = T(0);
+  const int k0 = K0 * cz, k1 = K1 * cz;
+  T acc[RC];
+#pragma unroll
+  for (int r = 0; r < RC; ++r) acc[r] = T(0);
+  int pl = 0;  // fine planes walked so far
   auto add = [&](long long, T ax, T D, T, T sv) {
-    if (D != T(0)) acc += sv - ax;
+    if constexpr (RC == 1) {
+      if (D != T(0)) acc[0] += sv - ax;
+    } else {
+      if (D != T(0)) {
+        if (pl < cz)
+          acc[0] += sv - ax;
+        else
+          acc[1] += sv - ax;
+      }
+      ++pl;
+    }
   };
   auto xv = [&](long long q) { return x[q]; };
   auto sv = [&](long long q) { return sigma[q]; };
-  if (uni)  // a uniform block: the constant faces
-    walk_column_vsf<T>(gf, xv, sv, UniformFaces<T>(gf, uni, i, j, K * cz), i, j, K * cz,
-                       K * cz + cz, add);
-  else
+  if (uni) {  // a uniform block: the constant faces, every plane's loads in flight at once
+    if (RC == 2 && cz == 2)
+      walk_column_vsf<T, 4, true>(gf, xv, sv, UniformFaces<T>(gf, uni, i, j, k0), i, j, k0, k1,
+                                  add);
+    else
+      walk_column_vsf<T, 2, true>(gf, xv, sv, UniformFaces<T>(gf, uni, i, j, k0), i, j, k0, k1,
+                                  add);
+  } else {  // stored faces: the next plane's loads in flight (the registers of four
+            // planes of faces would cost occupancy)
     walk_column_vsf<T>(
-        gf, xv, sv, [&](int d, long long q, bool) { return ldL<T>(L + d * gf.n, q); }, i, j,
-        K * cz, K * cz + cz, add);
-  if (cx == 2) acc += __shfl_xor(acc, 1, 64);
+        gf, xv, sv, [&](int d, long long q, bool) { return ldL<T>(L + d * gf.n, q); }, i, j, k0,
+        k1, add);
+  }
+#pragma unroll
+  for (int r = 0; r < RC; ++r)
+    if (cx == 2) acc[r] += __shfl_xor(acc[r], 1, 64);
   if (cy == 2) {
-    rows[ty][tx] = acc;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) rows[r][ty][tx] = acc[r];
     __syncthreads();
-    acc += rows[ty ^ 1][tx];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] += rows[r][ty ^ 1][tx];
   }
   if (i < gf.nx && j < gf.ny && (i % cx) == 0 && (j % cy) == 0) {
-    const long long cidx = (long long)K * gc.sz + (long long)(j / cy) * gc.sy + i / cx;
-    sigma_c[cidx] = acc;
-    if (x_c) x_c[cidx] = T(0);
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      if (K0 + r >= K1) break;
+      const long long cidx = (long long)(K0 + r) * gc.sz + (long long)(j / cy) * gc.sy + i / cx;
+      sigma_c[cidx] = acc[r];
+      if (x_c) x_c[cidx] = T(0);
+    }
   }
 }
 
-template <typename T, typename TL>
+// Coarse planes per workgroup of the fused residual + restriction: 2 (four
+// fine planes of loads in flight per thread) where one plane per workgroup
+// would need at least this many workgroups, else 1.
+constexpr long long kRestrictPairBlocks = 16384;
+
+template <typename T, typename TL, int RC>
 __global__ __launch_bounds__(BT) void k_restrict_residual(
     Geom gf, Roles<T> X, int role, const T* __restrict__ sigma, const TL* __restrict__ L,
     Geom gc, int cx, int cy, int cz, T* __restrict__ sigma_c, T* __restrict__ x_c,
     const int* done, int zper, const UBrick* ub, int ubx, int uby) {
   if (stopped(done)) return;
-  __shared__ T rows[BY][BX];
-  const int K = chunk_top_first(blockIdx.z, gridDim.z, zper);
+  __shared__ T rows[RC][BY][BX];
+  const int K0 = RC * chunk_top_first(blockIdx.z, gridDim.z, zper);
+  const int K1 = min(gc.nz, K0 + RC);
   double u[3];
-  const bool uni = uniform_block(ub, ubx, uby, blockIdx.x, blockIdx.y, K * cz,
-                                 min(gf.nz, K * cz + cz), u);
-  restrict_tile<T, TL>(rows, gf, X.get(role), sigma, L, gc, cx, cy, cz, sigma_c, x_c,
-                       blockIdx.x * BX, blockIdx.y * BY, K, uni ? u : nullptr);
+  const bool uni =
+      uniform_block(ub, ubx, uby, blockIdx.x, blockIdx.y, K0 * cz, min(gf.nz, K1 * cz), u);
+  restrict_tile<T, TL, RC>(rows, gf, X.get(role), sigma, L, gc, cx, cy, cz, sigma_c, x_c,
+                           blockIdx.x * BX, blockIdx.y * BY, K0, K1, uni ? u : nullptr);
 }
 
 // Piecewise-constant prolongation + correction on active fine cells:
@@ -1054,15 +1111,28 @@ static int zper_after_passes(const gmg_handle* h, int l, int nu, int planes_per_
              : 1;
 }
 
+// Coarse planes per workgroup of level lv's fused residual + restriction.
+static int restrict_planes(const Level& lv, const Level& lc) {
+  const long long one = (long long)((lv.g.nx + BX - 1) / BX) * ((lv.g.ny + BY - 1) / BY) * lc.g.nz;
+  return one >= kRestrictPairBlocks ? 2 : 1;
+}
+
+// zper: the pass's z-chunk in workgroups of this launch (chunk_top_first).
 template <typename T, typename TL>
 static void enq_restrict(gmg_handle* h, int l, const Roles<T>& X, int role, const T* sigma,
                          T* sigma_c, T* x_c, const int* done, int zper = 1) {
   const Level& lv = h->lev[l];
   const Level& lc = h->lev[l + 1];
-  const dim3 grid((lv.g.nx + BX - 1) / BX, (lv.g.ny + BY - 1) / BY, lc.g.nz);
-  hipLaunchKernelGGL((k_restrict_residual<T, TL>), grid, kBlock, 0, h->s, lv.g, X, role, sigma,
-                     (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c, done, zper,
-                     lv.ub, lv.ubx, lv.uby);
+  const int rc = restrict_planes(lv, lc);
+  const dim3 grid((lv.g.nx + BX - 1) / BX, (lv.g.ny + BY - 1) / BY, (lc.g.nz + rc - 1) / rc);
+  if (rc == 2)
+    hipLaunchKernelGGL((k_restrict_residual<T, TL, 2>), grid, kBlock, 0, h->s, lv.g, X, role,
+                       sigma, (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c,
+                       done, zper, lv.ub, lv.ubx, lv.uby);
+  else
+    hipLaunchKernelGGL((k_restrict_residual<T, TL, 1>), grid, kBlock, 0, h->s, lv.g, X, role,
+                       sigma, (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c,
+                       done, zper, lv.ub, lv.ubx, lv.uby);
 }
 
 // LDS bytes the tail needs when it starts at level lt.
@@ -1286,9 +1356,13 @@ static int enq_vcycle(gmg_handle* h, T* X0, const int* sel, const T* sigma0, con
     }
     role[l] = r;
     if (coarsest) break;
-    enq_restrict<T, TL>(h, l, X, r, sg, (T*)h->lev[l + 1].sigma, (T*)h->lev[l + 1].x[0], done,
-                        pcg ? 1 : zper_after_passes(h, l, nsw, h->lev[l].c[2],
-                                                    h->lev[l + 1].g.nz));
+    {
+      const int rc = restrict_planes(h->lev[l], h->lev[l + 1]);
+      enq_restrict<T, TL>(h, l, X, r, sg, (T*)h->lev[l + 1].sigma, (T*)h->lev[l + 1].x[0], done,
+                          pcg ? 1
+                              : zper_after_passes(h, l, nsw, rc * h->lev[l].c[2],
+                                                  (h->lev[l + 1].g.nz + rc - 1) / rc));
+    }
   }
   if (lt < nl) {
     enq_tail<T, TL>(h, lt, done);

@@ -13,21 +13,29 @@ namespace gmg {
 // fixed for the column, and the z-neighbours and z-faces roll through
 // registers as the walk goes up.
 //
-// The loads of plane k+1 are issued before plane k is computed, so each wave
-// keeps two planes of loads in flight (the walk is otherwise one memory
-// latency per plane); the last plane is peeled off the loop.  Every load is
-// issued on every path (a missing neighbour's offset points at the cell
-// itself) and the value selected afterwards, so no branch forces the
-// compiler to wait for all of them.
+// The loads of planes k+1 .. k+PF-1 are issued before plane k is computed,
+// so each wave keeps PF planes of loads in flight (the walk is otherwise one
+// memory latency per plane).  PF = 2: the next plane's loads, the last plane
+// peeled off the loop.  PF > 2: a ring of PF plane registers with PF plane
+// steps per loop iteration, so that the ring is indexed by constants; the
+// planes past the last one are loaded again (clamped: at most PF - 1 extra
+// plane loads, which hit the cache) instead of branched around, and the last
+// planes, which load nothing, are computed after the loop.  ALL: a walk of
+// at most PF planes that issues every load at once.  Every load is issued on every
+// path (a missing neighbour's offset points at the cell itself) and the
+// value selected afterwards, so no branch forces the compiler to wait for
+// all of them.
 //
 // walk_column_vsf takes the faces through face(d, q, hi), the face of
 // direction d stored at cell q, where hi tells a cell's high face (q is the
 // neighbour's index) from its low one: the stored faces, or a block's constant
 // faces (uniform bricks, whose low walls keep their zero faces), with the same
 // arithmetic either way.
-template <typename T, typename V, typename S, typename FL, typename F>
+template <typename T, int PF = 2, bool ALL = false, typename V, typename S, typename FL,
+          typename F>
 __device__ __forceinline__ void walk_column_vsf(const Geom& g, V&& v, S&& side, FL&& face, int i,
                                                 int j, int k0, int k1, F&& f) {
+  static_assert(PF >= 2, "at least the next plane in flight");
   if (i >= g.nx || j >= g.ny || k0 >= k1) return;
   const Nb nx = neighbours(i, g.nx, g.px, 1);
   const Nb ny = neighbours(j, g.ny, g.py, g.sy);
@@ -86,15 +94,39 @@ __device__ __forceinline__ void walk_column_vsf(const Geom& g, V&& v, S&& side, 
     lzm = lzp;
     idx += g.sz;
   };
-  Plane cur, nxt;
-  load(k0, cur);
-  int k = k0;
-  for (; k + 1 < k1; ++k) {
-    load(k + 1, nxt);
+  if constexpr (ALL) {  // a walk of at most PF planes: every load in flight at once
+    Plane ring[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) load(min(k0 + q, k1 - 1), ring[q]);
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (k0 + q < k1) plane(k0 + q, ring[q]);
+  } else if constexpr (PF == 2) {  // the last plane peeled off; no plane loaded twice
+    Plane cur, nxt;
+    load(k0, cur);
+    int k = k0;
+    for (; k + 1 < k1; ++k) {
+      load(k + 1, nxt);
+      plane(k, cur);
+      cur = nxt;
+    }
     plane(k, cur);
-    cur = nxt;
+  } else {
+    Plane ring[PF];  // ring[q] holds plane k + q at the top of an iteration
+#pragma unroll
+    for (int q = 0; q + 1 < PF; ++q) load(min(k0 + q, k1 - 1), ring[q]);
+    int k = k0;
+    for (; k + PF <= k1; k += PF) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        load(min(k + q + PF - 1, k1 - 1), ring[(q + PF - 1) % PF]);
+        plane(k + q, ring[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q + 1 < PF; ++q)
+      if (k + q < k1) plane(k + q, ring[q]);
   }
-  plane(k, cur);
 }
 
 template <typename T, typename TL, typename V, typename S, typename F>

@@ -1,0 +1,55 @@
+"""GPU parity of the fused residual + restriction on grids where a workgroup
+takes two coarse planes (a launch of one coarse plane per workgroup would
+have at least 16384 workgroups): against the oracle element by element, and
+bitwise with and without the uniform-brick map.  Two fine planes per coarse
+plane with an odd number of coarse planes (the last workgroup takes one),
+and one fine plane per coarse plane (anisotropic coarsening, periodic x)."""
+import numpy as np
+import pytest
+
+from oracle import gmg_oracle as O
+from paper_2607_07687_amd import gmg as G
+from paper_2607_07687_amd import problems as P
+from tests.gpu_util import TOL, assert_close, dev, host, require_gpu, rounded, say, torch
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # 2 x 128 x 65 one-plane workgroups; c = (2, 2, 2), 65 coarse planes
+    "walls_256x256x130": lambda: P.sphere_box((256, 256, 130), (128.0, 128.0, 65.0), 20.0,
+                                              "uniform", 5),
+    # 8 x 64 x 33 one-plane workgroups; c = (2, 2, 1), 33 coarse planes
+    "periodic_x_1024x128x33": lambda: P.random_problem((1024, 128, 33), (True, False, False),
+                                                       seed=6, contrast=0.0, holes=0.001),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_restrict_two_coarse_planes_per_workgroup(name):
+    require_gpu()
+    say(f"restrict large {name}")
+    L, s, per = CASES[name]()
+    n = (L.shape[3], L.shape[2], L.shape[1])
+    L64, s64 = rounded(L, "f32"), rounded(s, "f32")
+    Ld, sd = dev(L64, "f32"), dev(s64, "f32")
+    hu = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F32), Ld)
+    ho = G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F32, uniform_bricks=0), Ld)
+    (nx, ny, nz), c = G.gmg_level_shape(hu, 0)
+    (cx, cy, cz), _ = G.gmg_level_shape(hu, 1)
+    blocks = -(-nx // 128) * -(-ny // 2) * cz
+    assert blocks >= 16384 and cz % 2 == 1, (blocks, cz)
+    u, t = G.gmg_level_uniform(hu, 0)
+    assert 0 < u < t
+    x = rounded(np.random.default_rng(7).standard_normal(s64.shape), "f32")
+    outs = []
+    for h in (hu, ho):
+        sc = torch.full((cz, cy, cx), 7.0, dtype=torch.float32, device="cuda")
+        xc = torch.full((cz, cy, cx), 7.0, dtype=torch.float32, device="cuda")
+        G.gmg_restrict_residual(h, 0, dev(x, "f32"), sd, sc, xc)
+        assert torch.count_nonzero(xc).item() == 0
+        outs.append(sc)
+    assert torch.equal(outs[0], outs[1])
+    want = O.restrict(O.residual(x, s64, L64, per), c)
+    assert_close(host(outs[0]), want, TOL["f32"], what=name)
+    hu.close()
+    ho.close()
