@@ -156,19 +156,30 @@ struct S2Args {
 
 // The faces of a thread's pair column in a tile of uniform bricks (see
 // UBrick), as the loads would return them: u_d, +0 on a low wall, and zeros
-// outside a wall (columns and, per plane, planes).
+// outside a wall (columns and, per plane, planes); lxh and lyh, the high x-
+// and y-faces the LDS exchange would deliver (the low faces of the pair to
+// the east and of the row above).
 template <typename T>
 struct S2Uni {
   T lx0, lx1, ly, lz;
+  T lxh, lyh;
 };
+
+// Face modes of the pass: loaded (S2_LOADED), uniform with per-plane wall
+// handling (S2_UNIFORM), or uniform on a tile whose fetched planes are all
+// inside the domain (S2_CONST): then every face a thread uses is the same
+// value on every plane, the exchange of faces is skipped, and the compiler
+// hoists each cell's diagonal and its reciprocal out of the plane loop.
+constexpr int S2_LOADED = 0, S2_UNIFORM = 1, S2_CONST = 2;
 
 // Issue the loads of plane m for the column with lane offsets vo4, vo2, vo1
 // (its in-plane offset in 4-, 2- and 1-byte elements, S2_OUT outside a wall)
 // and coarse in-plane offset `coff` (PROL: also the prolongation operands).
 // Every lane issues every load, so the number of loads in flight is the same
 // on every path and the compiler waits for exactly the plane being taken.
-// UNI: the faces are the constants of f instead of loads.
-template <typename T, typename TL, bool PROL, bool UNI>
+// UM (face mode) other than S2_LOADED: the faces are the constants of f
+// instead of loads.
+template <typename T, typename TL, bool PROL, int UM>
 __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, const S2Bufs& b,
                                          int m, int vo4, int vo2, int vo1, int coff,
                                          const S2Uni<T>& f) {
@@ -179,7 +190,12 @@ __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, 
   const int so1 = mm * (int)g.sz, so2 = 2 * so1, so4 = 4 * so1;
   s2_ld2<T>(pin ? b.S : b.zero, vo4, so4, ld.s);
   s2_ld2<T>(pin ? b.sg : b.zero, vo4, so4, ld.sg);
-  if constexpr (UNI) {
+  if constexpr (UM == S2_CONST) {
+    ld.lx[0] = f.lx0;
+    ld.lx[1] = f.lx1;
+    ld.ly[0] = ld.ly[1] = f.ly;
+    ld.lz[0] = ld.lz[1] = f.lz;
+  } else if constexpr (UM == S2_UNIFORM) {
     ld.lx[0] = pin ? f.lx0 : T(0);
     ld.lx[1] = pin ? f.lx1 : T(0);
     ld.ly[0] = ld.ly[1] = pin ? f.ly : T(0);
@@ -200,9 +216,10 @@ __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, 
   }
 }
 
-// Loaded plane -> column registers (PROL: S corrected on active cells).
-template <typename T, bool PROL>
-__device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld) {
+// Loaded plane -> column registers (PROL: S corrected on active cells).  The
+// high faces are completed later from the exchange (S2_CONST: from f).
+template <typename T, bool PROL, int UM>
+__device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld, const S2Uni<T>& f) {
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     if constexpr (PROL)
@@ -213,9 +230,9 @@ __device__ __forceinline__ void s2_take(S2Plane<T>& p, const S2Load<T>& ld) {
     p.lx[e] = ld.lx[e];
     p.ly[e] = ld.ly[e];
     p.lz[e] = ld.lz[e];
-    p.lyh[e] = T(0);
+    p.lyh[e] = UM == S2_CONST ? f.lyh : T(0);
   }
-  p.lxh = T(0);
+  p.lxh = UM == S2_CONST ? f.lxh : T(0);
 }
 
 // Element e of a pair held in registers: a select when e is known only at
@@ -250,10 +267,11 @@ __device__ __forceinline__ T s2_residual(T xc, T xe, T xw, T xn, T xs, T xt, T x
 // Sweeps 1 and 2 of the tile with origin (i0, j0) over the z-planes [k0, k1)
 // (PROL: with the coarse correction folded into S).  RES: also the sum of the
 // squared residuals of S over the tile's own active cells and planes (the
-// norm of the pass's input), returned to thread 0 (0 elsewhere).  UNI: the
-// tile's grown region lies in uniform bricks of constants uc (s2_uniform_tile),
-// whose faces are then not loaded.
-template <typename T, typename TL, int TY, bool PROL, bool RES = false, bool UNI = false>
+// norm of the pass's input), returned to thread 0 (0 elsewhere).  UM other
+// than S2_LOADED: the tile's grown region lies in uniform bricks of constants
+// uc (s2_uniform_tile), whose faces are then not loaded; S2_CONST also needs
+// every fetched plane inside the domain (s2_const_planes).
+template <typename T, typename TL, int TY, bool PROL, bool RES = false, int UM = S2_LOADED>
 __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args<T, TL>& a,
                                                  T* __restrict__ W, int i0, int j0, int k0,
                                                  int k1, T omega, const double* uc = nullptr) {
@@ -276,12 +294,15 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
   const int vo1 = off >= 0 ? off : S2_OUT, vo2 = off >= 0 ? 2 * off : S2_OUT,
             vo4 = off >= 0 ? 4 * off : S2_OUT;
   S2Uni<T> fu{};
-  if constexpr (UNI) {
+  if constexpr (UM != S2_LOADED) {
     const bool in = off >= 0;
     fu.lx0 = (in && (ii > 0 || g.px)) ? T(uc[0]) : T(0);
     fu.lx1 = in ? T(uc[0]) : T(0);
     fu.ly = (in && (jj > 0 || g.py)) ? T(uc[1]) : T(0);
     fu.lz = in ? T(uc[2]) : T(0);
+    const int xe = wrap_coord(xa + 2, g.nx, g.px), yn = wrap_coord(y + 1, g.ny, g.py);
+    fu.lxh = (jj >= 0 && xe >= 0 && (xe > 0 || g.px)) ? T(uc[0]) : T(0);
+    fu.lyh = (ii >= 0 && yn >= 0 && (yn > 0 || g.py)) ? T(uc[1]) : T(0);
   }
   const int nb = (int)g.n;  // at most S2_MAX_CELLS
   const S2Bufs b{__builtin_amdgcn_make_buffer_rsrc((void*)a.S, 0, 4 * nb, S2_RSRC_W3),
@@ -319,17 +340,28 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
   T r2a = T(0), r2b = T(0);       // sweep-2 red of planes k-1, k
   S2Load<T> la, lb;
   {
-    const S2Plane<T> z{};
+    // planes before the first fetched one (never computed on); S2_CONST gives
+    // them the tile's faces, so that every plane register holds the same
+    // faces and the per-cell diagonals stay loop-invariant
+    S2Plane<T> z{};
+    if constexpr (UM == S2_CONST) {
+      z.lx[0] = fu.lx0;
+      z.lx[1] = fu.lx1;
+      z.ly[0] = z.ly[1] = fu.ly;
+      z.lz[0] = z.lz[1] = fu.lz;
+      z.lxh = fu.lxh;
+      z.lyh[0] = z.lyh[1] = fu.lyh;
+    }
     P0 = P1 = P2 = z;
   }
   // prologue: planes k0-4 and k0-3 in registers (with two load sets, k0-2 in
   // flight); the loop starts at step k0-7, whose P3, P4 are those planes
-  s2_fetch<T, TL, PROL, UNI>(la, a, b, k0 - 4, vo4, vo2, vo1, coff, fu);
-  s2_fetch<T, TL, PROL, UNI>(lb, a, b, k0 - 3, vo4, vo2, vo1, coff, fu);
-  s2_take<T, PROL>(P3, la);
-  s2_take<T, PROL>(P4, lb);
+  s2_fetch<T, TL, PROL, UM>(la, a, b, k0 - 4, vo4, vo2, vo1, coff, fu);
+  s2_fetch<T, TL, PROL, UM>(lb, a, b, k0 - 3, vo4, vo2, vo1, coff, fu);
+  s2_take<T, PROL, UM>(P3, la, fu);
+  s2_take<T, PROL, UM>(P4, lb, fu);
   if constexpr (C::NSET == 2)
-    s2_fetch<T, TL, PROL, UNI>(la, a, b, k0 - 2, vo4, vo2, vo1, coff, fu);
+    s2_fetch<T, TL, PROL, UM>(la, a, b, k0 - 2, vo4, vo2, vo1, coff, fu);
   // step k0-8's exchange (S, Ly, Lx of plane k0-4 = P3) so that step k0-7
   // can complete P3's high faces
   {
@@ -337,9 +369,11 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
     if (col) {
       sm.s[q][R][cs] = P3.s[0];
       sm.s[q][R][cs + 1] = P3.s[1];
-      sm.ly[q][R][cs] = P3.ly[0];
-      sm.ly[q][R][cs + 1] = P3.ly[1];
-      sm.lx0[q][R][c] = P3.lx[0];
+      if constexpr (UM != S2_CONST) {
+        sm.ly[q][R][cs] = P3.ly[0];
+        sm.ly[q][R][cs + 1] = P3.ly[1];
+        sm.lx0[q][R][c] = P3.lx[0];
+      }
       sm.r1[q][R][c] = sm.b1[q][R][c] = sm.r2[q][R][c] = T(0);
     }
   }
@@ -351,13 +385,16 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
     // or with one load set those of plane k+5 into `cur`; beyond the chunk's
     // last needed plane (k1+3) they are loaded but never used
     if constexpr (C::NSET == 2)
-      s2_fetch<T, TL, PROL, UNI>(nxt, a, b, k + 6, vo4, vo2, vo1, coff, fu);
+      s2_fetch<T, TL, PROL, UM>(nxt, a, b, k + 6, vo4, vo2, vo1, coff, fu);
     else
-      s2_fetch<T, TL, PROL, UNI>(cur, a, b, k + 5, vo4, vo2, vo1, coff, fu);
+      s2_fetch<T, TL, PROL, UM>(cur, a, b, k + 5, vo4, vo2, vo1, coff, fu);
     // complete plane k+3: high faces from the previous step's exchange
-    P3.lxh = sm.lx0[q][R][ce];
-    P3.lyh[0] = sm.ly[q][RN][cs];
-    P3.lyh[1] = sm.ly[q][RN][cs + 1];
+    // (S2_CONST: they are already the tile's)
+    if constexpr (UM != S2_CONST) {
+      P3.lxh = sm.lx0[q][R][ce];
+      P3.lyh[0] = sm.ly[q][RN][cs];
+      P3.lyh[1] = sm.ly[q][RN][cs + 1];
+    }
     if constexpr (RES) {
       // plane k+3 is complete: the residual of S on both cells of the pair
       // (own cells of the tile on the chunk's own planes), from the values
@@ -456,7 +493,7 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
     P1 = P2;
     P2 = P3;
     P3 = P4;
-    s2_take<T, PROL>(P4, cur);  // plane k+5
+    s2_take<T, PROL, UM>(P4, cur, fu);  // plane k+5
     r1a = r1b;
     r1b = r1n;
     b1a = b1b;
@@ -466,9 +503,11 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
     if (col) {
       sm.s[w][R][cs] = P3.s[0];  // plane k+4
       sm.s[w][R][cs + 1] = P3.s[1];
-      sm.ly[w][R][cs] = P3.ly[0];
-      sm.ly[w][R][cs + 1] = P3.ly[1];
-      sm.lx0[w][R][c] = P3.lx[0];
+      if constexpr (UM != S2_CONST) {
+        sm.ly[w][R][cs] = P3.ly[0];
+        sm.ly[w][R][cs + 1] = P3.ly[1];
+        sm.lx0[w][R][c] = P3.lx[0];
+      }
       sm.r1[w][R][c] = r1b;  // plane k+3
       sm.b1[w][R][c] = b1b;  // plane k+2
       sm.r2[w][R][c] = r2b;  // plane k+1
@@ -534,6 +573,13 @@ __device__ bool s2_uniform_tile(const Geom& g, const UBrick* __restrict__ ub, in
   return __syncthreads_and(ok ? 1 : 0) != 0;
 }
 
+// Whether every plane the tile over [k0, k1) fetches and uses (k0 - 4 ..
+// k1 + 3) lies inside the domain and off the low z-wall's plane 0, so that
+// a uniform tile's faces are the same on all of them (S2_CONST).
+__device__ __forceinline__ bool s2_const_planes(const Geom& g, int k0, int k1) {
+  return g.pz || (k0 - 4 >= 1 && k1 + 3 < g.nz);
+}
+
 }  // namespace gmg
 
 // Two sweeps in one pass: X[rd] = sweep(sweep(X[rs] (+ P x_c))), at global
@@ -553,10 +599,14 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
   const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
   const T omega = (T)(*omega_p);
   double u[3];
-  if (gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u))
-    gmg::rb_sweep2_tile<T, TL, TY, PROL, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega, u);
-  else
+  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u))
     gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
+  else if (gmg::s2_const_planes(g, k0, k1))
+    gmg::rb_sweep2_tile<T, TL, TY, PROL, false, gmg::S2_CONST>(sm, a, X.get(rd), i0, j0, k0, k1,
+                                                               omega, u);
+  else
+    gmg::rb_sweep2_tile<T, TL, TY, PROL, false, gmg::S2_UNIFORM>(sm, a, X.get(rd), i0, j0, k0,
+                                                                 k1, omega, u);
 }
 
 // The first pass of a cycle under the deferred decision: the same pass
@@ -579,10 +629,14 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
   const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
   const T omega = (T)(*omega_p);
   double u[3];
-  const double s =
-      gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u)
-          ? gmg::rb_sweep2_tile<T, TL, TY, false, true, true>(sm, a, X.get(rd), i0, j0, k0, k1,
-                                                               omega, u)
-          : gmg::rb_sweep2_tile<T, TL, TY, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
+  double s;
+  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u))
+    s = gmg::rb_sweep2_tile<T, TL, TY, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
+  else if (gmg::s2_const_planes(g, k0, k1))
+    s = gmg::rb_sweep2_tile<T, TL, TY, false, true, gmg::S2_CONST>(sm, a, X.get(rd), i0, j0, k0,
+                                                                   k1, omega, u);
+  else
+    s = gmg::rb_sweep2_tile<T, TL, TY, false, true, gmg::S2_UNIFORM>(sm, a, X.get(rd), i0, j0,
+                                                                     k0, k1, omega, u);
   if (res_part != nullptr && threadIdx.x == 0) res_part[blockIdx.x] = s;
 }
