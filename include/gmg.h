@@ -235,9 +235,11 @@ gmg_status gmg_level_shape(const gmg_handle* h, int32_t level, int32_t n[3],
 gmg_status gmg_level_faces(gmg_handle* h, int32_t level, void* L_out);
 
 /* Uniform-brick map of level `level` (see gmg_params.uniform_bricks): the
- * number of bricks whose faces are uniform and the number of bricks (both 0
- * when the map is off).  Synchronises the handle's stream. */
-gmg_status gmg_level_uniform(gmg_handle* h, int32_t level, int64_t* uniform, int64_t* total);
+ * number of bricks whose faces are uniform, of those the number whose cells
+ * are all active (D != 0; may be NULL), and the number of bricks (all 0 when
+ * the map is off).  Synchronises the handle's stream. */
+gmg_status gmg_level_uniform(gmg_handle* h, int32_t level, int64_t* uniform,
+                             int64_t* uniform_active, int64_t* total);
 
 /* Residual of the level-0 problem in dtype arithmetic (Sec. 3: the quantity
  * the V-cycle drives to zero):  r = sigma - A x on active cells, 0 elsewhere.

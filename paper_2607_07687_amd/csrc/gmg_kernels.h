@@ -94,7 +94,7 @@ constexpr int kUBZ = 2;  // planes per brick
 struct UBrick {
   double u[3];  // the faces of x, y, z (as read through ldL)
   int ok;       // 1: uniform
-  int pad;
+  int act;      // 1: every cell of the brick is active (D != 0)
 };
 
 }  // namespace gmg

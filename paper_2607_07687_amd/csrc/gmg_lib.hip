@@ -157,6 +157,7 @@ struct UniformFaces {
 // brick's cell (1, 1, 1), which is on no wall.
 template <typename TL>
 __global__ __launch_bounds__(BT) void k_uniform_bricks(Geom g, const TL* __restrict__ L,
+                                                       const uint8_t* __restrict__ active,
                                                        UBrick* __restrict__ out) {
   const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
   const int i0 = bx * BX, j0 = by * BY, k0 = bz * kUBZ;
@@ -191,14 +192,19 @@ __global__ __launch_bounds__(BT) void k_uniform_bricks(Geom g, const TL* __restr
                              u[2]);
     }
   }
+  bool act = whole;  // the active mask of the level, already built
+  if (whole)
+    for (int k = k0; k < k0 + kUBZ; ++k)
+      act = act && active[(long long)k * g.sz + (long long)j * g.sy + i] != 0;
   ok = __syncthreads_and(ok ? 1 : 0) != 0;
+  act = __syncthreads_and(act ? 1 : 0) != 0;
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     UBrick& b = out[((long long)bz * gridDim.y + by) * gridDim.x + bx];
     b.u[0] = u[0];
     b.u[1] = u[1];
     b.u[2] = u[2];
     b.ok = ok ? 1 : 0;
-    b.pad = 0;
+    b.act = act ? 1 : 0;
   }
 }
 
@@ -1557,7 +1563,7 @@ static void enq_build_levels(gmg_handle* h) {
                        lv.active);
     if (lv.ub)
       hipLaunchKernelGGL((k_uniform_bricks<TL>), dim3(lv.ubx, lv.uby, lv.ubz), kBlock, 0, h->s,
-                         lv.g, (const TL*)lv.L, lv.ub);
+                         lv.g, (const TL*)lv.L, lv.active, lv.ub);
   }
 }
 
@@ -2444,18 +2450,23 @@ gmg_status gmg_solve_ir(gmg_handle* h, double* x, const double* sigma, double rt
   return GMG_OK;
 }
 
-gmg_status gmg_level_uniform(gmg_handle* h, int32_t level, int64_t* uniform, int64_t* total) {
+gmg_status gmg_level_uniform(gmg_handle* h, int32_t level, int64_t* uniform,
+                             int64_t* uniform_active, int64_t* total) {
   if (!h || !uniform || !total) return fail(GMG_EINVAL, "NULL argument");
   if (level < 0 || level >= h->nlev) return fail(GMG_EINVAL, "level out of range");
   const Level& lv = h->lev[level];
   *uniform = 0;
   *total = 0;
+  if (uniform_active) *uniform_active = 0;
   if (!lv.ub) return GMG_OK;
   const size_t nb = (size_t)lv.ubx * lv.uby * lv.ubz;
   std::vector<UBrick> host(nb);
   HIP_TRY(hipMemcpyAsync(host.data(), lv.ub, nb * sizeof(UBrick), hipMemcpyDeviceToHost, h->s));
   HIP_TRY(hipStreamSynchronize(h->s));
-  for (const UBrick& b : host) *uniform += b.ok ? 1 : 0;
+  for (const UBrick& b : host) {
+    *uniform += b.ok ? 1 : 0;
+    if (uniform_active) *uniform_active += (b.ok && b.act) ? 1 : 0;
+  }
   *total = (int64_t)nb;
   return GMG_OK;
 }

@@ -163,13 +163,17 @@ template <typename T>
 struct S2Uni {
   T lx0, lx1, ly, lz;
   T lxh, lyh;
+  uint32_t pa;  // S2_CONST with the correction: the active-mask bytes of the pair
 };
 
 // Face modes of the pass: loaded (S2_LOADED), uniform with per-plane wall
 // handling (S2_UNIFORM), or uniform on a tile whose fetched planes are all
 // inside the domain (S2_CONST): then every face a thread uses is the same
 // value on every plane, the exchange of faces is skipped, and the compiler
-// hoists each cell's diagonal and its reciprocal out of the plane loop.
+// hoists each cell's diagonal and its reciprocal out of the plane loop.  With
+// the folded correction S2_CONST also needs every cell of the region's
+// bricks active, and then takes the active mask as 1 on the domain's cells
+// instead of loading it.
 constexpr int S2_LOADED = 0, S2_UNIFORM = 1, S2_CONST = 2;
 
 // Issue the loads of plane m for the column with lane offsets vo4, vo2, vo1
@@ -210,7 +214,10 @@ __device__ __forceinline__ void s2_fetch(S2Load<T>& ld, const S2Args<T, TL>& a, 
     // when c_x = 1.  Outside a wall the mask reads zero, and the coarse
     // value (at a clamped address) is not used.
     const long long cb = (long long)(mm >> (a.cz >> 1)) * a.gc.sz + coff;
-    ld.pa = __builtin_amdgcn_raw_buffer_load_b16(pin ? b.act : b.zero, vo1, so1, 0);
+    if constexpr (UM == S2_CONST)
+      ld.pa = f.pa;
+    else
+      ld.pa = __builtin_amdgcn_raw_buffer_load_b16(pin ? b.act : b.zero, vo1, so1, 0);
 #pragma unroll
     for (int e = 0; e < 2; ++e) ld.pc[e] = a.xc[cb + (a.cx == 1 ? e : 0)];
   }
@@ -303,6 +310,7 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
     const int xe = wrap_coord(xa + 2, g.nx, g.px), yn = wrap_coord(y + 1, g.ny, g.py);
     fu.lxh = (jj >= 0 && xe >= 0 && (xe > 0 || g.px)) ? T(uc[0]) : T(0);
     fu.lyh = (ii >= 0 && yn >= 0 && (yn > 0 || g.py)) ? T(uc[1]) : T(0);
+    fu.pa = in ? 0x0101u : 0u;
   }
   const int nb = (int)g.n;  // at most S2_MAX_CELLS
   const S2Bufs b{__builtin_amdgcn_make_buffer_rsrc((void*)a.S, 0, 4 * nb, S2_RSRC_W3),
@@ -548,15 +556,18 @@ __device__ __forceinline__ double rb_sweep2_tile(S2Smem<T, TY>& sm, const S2Args
 // first is outside a wall); the workgroup checks the bricks of those columns
 // on every row and plane of the region, a few independent loads per thread.
 // Called by the whole workgroup.
+// act: whether every cell of those bricks is also active.
 template <int TY>
 __device__ bool s2_uniform_tile(const Geom& g, const UBrick* __restrict__ ub, int ubx, int uby,
-                                int i0, int j0, int k0, int k1, double (&u)[3]) {
+                                int i0, int j0, int k0, int k1, double (&u)[3], bool& act) {
+  act = false;
   if (ub == nullptr) return false;  // uniform over the workgroup
   const UBrick* ref = ub + ((long long)(k0 / kUBZ) * uby + j0 / BY) * ubx + i0 / BX;
   u[0] = ref->u[0];
   u[1] = ref->u[1];
   u[2] = ref->u[2];
   bool ok = ref->ok != 0;
+  bool all = ref->act != 0;
   const int nys = TY + 8, nzs = k1 - k0 + 8, nslot = 3 * nys * nzs;
 #pragma unroll 4
   for (int q = threadIdx.x; q < nslot; q += blockDim.x) {
@@ -569,7 +580,9 @@ __device__ bool s2_uniform_tile(const Geom& g, const UBrick* __restrict__ ub, in
     ok &= b.ok != 0 && __double_as_longlong(b.u[0]) == __double_as_longlong(u[0]) &&
           __double_as_longlong(b.u[1]) == __double_as_longlong(u[1]) &&
           __double_as_longlong(b.u[2]) == __double_as_longlong(u[2]);
+    all &= b.act != 0;
   }
+  act = __syncthreads_and(all ? 1 : 0) != 0;
   return __syncthreads_and(ok ? 1 : 0) != 0;
 }
 
@@ -599,9 +612,10 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
   const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
   const T omega = (T)(*omega_p);
   double u[3];
-  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u))
+  bool act;
+  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u, act))
     gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
-  else if (gmg::s2_const_planes(g, k0, k1))
+  else if (gmg::s2_const_planes(g, k0, k1) && (act || !PROL))
     gmg::rb_sweep2_tile<T, TL, TY, PROL, false, gmg::S2_CONST>(sm, a, X.get(rd), i0, j0, k0, k1,
                                                                omega, u);
   else
@@ -630,7 +644,8 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
   const T omega = (T)(*omega_p);
   double u[3];
   double s;
-  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u))
+  bool act;
+  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u, act))
     s = gmg::rb_sweep2_tile<T, TL, TY, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
   else if (gmg::s2_const_planes(g, k0, k1))
     s = gmg::rb_sweep2_tile<T, TL, TY, false, true, gmg::S2_CONST>(sm, a, X.get(rd), i0, j0, k0,

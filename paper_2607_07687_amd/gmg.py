@@ -94,6 +94,7 @@ _SIGS = [
     ("gmg_level_faces", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     ("gmg_level_uniform", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64)]),
     ("gmg_residual", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -357,11 +358,13 @@ def gmg_level_faces(h, level, out):
     return out
 
 
-def gmg_level_uniform(h, level):
-    """(uniform bricks, bricks) of a level's uniform-brick map."""
-    u, t = ctypes.c_int64(), ctypes.c_int64()
-    _check(load().gmg_level_uniform(h.ptr, level, ctypes.byref(u), ctypes.byref(t)))
-    return u.value, t.value
+def gmg_level_uniform(h, level, active=False):
+    """(uniform bricks, bricks) of a level's uniform-brick map; with active,
+    (uniform bricks, uniform bricks whose cells are all active, bricks)."""
+    u, a, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().gmg_level_uniform(h.ptr, level, ctypes.byref(u), ctypes.byref(a),
+                                    ctypes.byref(t)))
+    return (u.value, a.value, t.value) if active else (u.value, t.value)
 
 
 def gmg_residual(h, x, sigma, r=None, norms=True):

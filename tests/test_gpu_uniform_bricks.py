@@ -1,5 +1,6 @@
 """GPU checks of the uniform-brick map (blocks of 128 x 2 x 2 cells whose
-faces are one constant per direction, low walls at zero): the map of every
+faces are one constant per direction, low walls at zero; whether all their
+cells are active): the map of every
 level agrees with the rule evaluated on the host from the level's faces, and
 every entry point whose kernels read it (residual and its norms, the
 allocation-free residual, the fused residual + restriction, V-cycles, solves)
@@ -10,6 +11,7 @@ checked against the oracle in test_gpu_parity.py."""
 import numpy as np
 import pytest
 
+from oracle import gmg_oracle as O
 from paper_2607_07687_amd import gmg as G
 from paper_2607_07687_amd import problems as P
 from tests.gpu_util import dev, require_gpu, rounded, say, torch
@@ -32,6 +34,18 @@ def layered(n, per, split=8):
     return L, P.rhs_from_velocity(L, u, per), per
 
 
+def solid_slab(n, per, lo=10, hi=20):
+    """L = 1 except a slab of planes [lo, hi) whose faces (and the z faces
+    into it from above) are 0: inactive cells in bricks of uniform zero
+    faces, next to uniform active bricks."""
+    L = np.ones((3, n[2], n[1], n[0]))
+    L[:, lo:hi] = 0.0
+    L[2, hi] = 0.0
+    L = P.zero_wall_faces(L, per)
+    u = np.random.default_rng(8).uniform(-1.0, 1.0, L.shape)
+    return L, P.rhs_from_velocity(L, u, per), per
+
+
 # (name, builder) -> (L, sigma, periodic); level 0 at least 128 cells in x
 CASES = {
     "sphere_walls": lambda: P.sphere_box((256, 40, 36), (128.0, 20.0, 18.0), 7.0, "uniform", 1),
@@ -40,6 +54,7 @@ CASES = {
                                             contrast=0.0, holes=0.002),
     "ragged_walls": lambda: P.sphere_box((300, 21, 19), (60.0, 10.0, 9.0), 4.0, "uniform", 2),
     "layered_z": lambda: layered((256, 16, 40), (False, True, True)),
+    "solid_slab": lambda: solid_slab((256, 16, 40), (True, True, False)),
     # 2^23 cells: the default mode's two-sweep pass takes the map on level 0
     "sphere_2p23": lambda: P.sphere_box((256, 256, 128), (128.0, 128.0, 64.0), 32.0,
                                         "uniform", 3),
@@ -61,10 +76,14 @@ def level_faces(h, l, storage, prec):
     return out.cpu().numpy().astype(np.float64)
 
 
-def host_uniform(L, per):
-    """(uniform bricks, bricks) by the rule, from a level's faces as FP64."""
+def host_uniform(L, per, active=False):
+    """(uniform bricks, bricks) by the rule, from a level's faces as FP64;
+    with active, (uniform bricks, those whose cells are all active by the
+    oracle's active set, bricks)."""
     _, nz, ny, nx = L.shape
     bits = L.view(np.int64)
+    act = O.active_set(L, per)
+    nact = 0
     nbx, nby, nbz = -(-nx // UBX), -(-ny // UBY), -(-nz // UBZ)
     count = 0
     for bz in range(nbz):
@@ -99,7 +118,8 @@ def host_uniform(L, per):
                             got = bits[2, h0, j0:j0 + UBY, i0:i0 + UBX]
                         ok &= bool(np.all(got == np.float64(u[d]).view(np.int64)))
                 count += ok
-    return count, nbx * nby * nbz
+                nact += ok and bool(act[k0:k0 + UBZ, j0:j0 + UBY, i0:i0 + UBX].all())
+    return (count, nact, nbx * nby * nbz) if active else (count, nbx * nby * nbz)
 
 
 def pair(name, prec, storage, mode=2):
@@ -127,13 +147,15 @@ def test_map_matches_host_rule(name, prec, storage):
     say(f"uniform map {name} {prec}/{storage}")
     hu, ho, _, per = pair(name, prec, storage)
     for l in range(G.gmg_num_levels(hu)):
-        got = G.gmg_level_uniform(hu, l)
-        want = host_uniform(level_faces(hu, l, storage, prec), per)
+        got = G.gmg_level_uniform(hu, l, active=True)
+        want = host_uniform(level_faces(hu, l, storage, prec), per, active=True)
         assert got == want, f"level {l}: {got} vs {want}"
         assert G.gmg_level_uniform(ho, l) == (0, 0)
-    if name in ("sphere_walls", "tgv_periodic", "layered_z"):
-        u, t = G.gmg_level_uniform(hu, 0)
+    if name in ("sphere_walls", "tgv_periodic", "layered_z", "solid_slab"):
+        u, a, t = G.gmg_level_uniform(hu, 0, active=True)
         assert u >= t // 2 > 0, (u, t)  # the constant-face path is exercised
+        if name == "solid_slab":
+            assert 0 < a < u  # uniform bricks of inactive cells too
     hu.close()
     ho.close()
 
