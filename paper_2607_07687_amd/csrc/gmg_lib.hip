@@ -390,8 +390,9 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BY][BX], const Geom& gf,
 
 // Coarse planes per workgroup of the fused residual + restriction: 2 (four
 // fine planes of loads in flight per thread) where one plane per workgroup
-// would need at least this many workgroups, else 1.
-constexpr long long kRestrictPairBlocks = 16384;
+// would need at least this many workgroups, else 1 (at 256^3: levels 0 and
+// 1, 62 -> 45 and 11.5 -> 9.1 us; level 2 took 5.4 against 4.7 us).
+constexpr long long kRestrictPairBlocks = 4096;
 
 template <typename T, typename TL, int RC>
 __global__ __launch_bounds__(BT) void k_restrict_residual(
