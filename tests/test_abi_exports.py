@@ -60,6 +60,7 @@ def test_null_arguments_rejected_without_side_effects():
     assert lib.gmg_setup(None, None, None, ctypes.byref(out)) == G.GMG_EINVAL
     assert lib.gmg_solve(None, None, None, 1e-6, 10, None) == G.GMG_EINVAL
     assert lib.gmg_vcycle(None, None, None, None) == G.GMG_EINVAL
+    assert lib.gmg_level_uniform(None, 0, None, None, None) == G.GMG_EINVAL
     assert lib.gmg_last_error().decode() != ""
     assert lib.gmg_destroy(None) == G.GMG_OK
 
