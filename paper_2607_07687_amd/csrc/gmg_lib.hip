@@ -319,8 +319,8 @@ __global__ __launch_bounds__(BT) void k_masked_sumsq(Geom g, const T* __restrict
 
 // Fused residual + restriction, one thread per FINE cell of the BX x BY tile
 // at (i0, j0): each thread sums the residuals of its column over the cz fine
-// planes of each coarse plane of [K0, K1) (at most RC of them, one walk up
-// the column); x-pairs are combined by a lane shuffle and y-pairs through LDS
+// planes of each coarse plane of [K0, K1) (at most RC = 1, 2 or 4 of them,
+// one walk up the column); x-pairs are combined by a lane shuffle and y-pairs through LDS
 // (rows[r] for coarse plane K0 + r); the thread at each block's origin writes
 // sigma_c and zeroes x_c.
 template <typename T, typename TL, int RC = 1>
@@ -331,7 +331,7 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BY][BX], const Geom& gf,
                                               int cy, int cz, T* __restrict__ sigma_c,
                                               T* __restrict__ x_c, int i0, int j0, int K0, int K1,
                                               const double* uni = nullptr) {
-  static_assert(RC == 1 || RC == 2, "one or two coarse planes per tile");
+  static_assert(RC == 1 || RC == 2 || RC == 4, "1, 2 or 4 coarse planes per tile");
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int i = i0 + tx, j = j0 + ty;
   const int k0 = K0 * cz, k1 = K1 * cz;
@@ -344,10 +344,10 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BY][BX], const Geom& gf,
       if (D != T(0)) acc[0] += sv - ax;
     } else {
       if (D != T(0)) {
-        if (pl < cz)
-          acc[0] += sv - ax;
-        else
-          acc[1] += sv - ax;
+        const int c = cz == 2 ? pl >> 1 : pl;  // the plane's coarse plane in the tile
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+          if (c == r) acc[r] += sv - ax;
       }
       ++pl;
     }
@@ -355,12 +355,13 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BY][BX], const Geom& gf,
   auto xv = [&](long long q) { return x[q]; };
   auto sv = [&](long long q) { return sigma[q]; };
   if (uni) {  // a uniform block: the constant faces, every plane's loads in flight at once
-    if (RC == 2 && cz == 2)
-      walk_column_vsf<T, 4, true>(gf, xv, sv, UniformFaces<T>(gf, uni, i, j, k0), i, j, k0, k1,
-                                  add);
+    const UniformFaces<T> uf(gf, uni, i, j, k0);
+    if (RC == 4 && cz == 2)  // eight planes: a ring of three (no plane loaded twice)
+      walk_column_vsf<T, 3>(gf, xv, sv, uf, i, j, k0, k1, add);
+    else if (RC * cz >= 4)
+      walk_column_vsf<T, 4, true>(gf, xv, sv, uf, i, j, k0, k1, add);
     else
-      walk_column_vsf<T, 2, true>(gf, xv, sv, UniformFaces<T>(gf, uni, i, j, k0), i, j, k0, k1,
-                                  add);
+      walk_column_vsf<T, 2, true>(gf, xv, sv, uf, i, j, k0, k1, add);
   } else {  // stored faces: the next plane's loads in flight (the registers of four
             // planes of faces would cost occupancy)
     walk_column_vsf<T>(
@@ -388,11 +389,13 @@ __device__ __forceinline__ void restrict_tile(T (*rows)[BY][BX], const Geom& gf,
   }
 }
 
-// Coarse planes per workgroup of the fused residual + restriction: 2 (four
-// fine planes of loads in flight per thread) where one plane per workgroup
-// would need at least this many workgroups, else 1 (at 256^3: levels 0 and
-// 1, 62 -> 45 and 11.5 -> 9.1 us; level 2 took 5.4 against 4.7 us).
+// Coarse planes per workgroup of the fused residual + restriction: 4 (eight
+// fine planes, three planes of loads in flight) or 2 (four fine planes, all
+// loads in flight at once) where one plane per workgroup would need at least
+// this many workgroups, else 1.  At 256^3: level 0 62 -> 45 (2) -> 42 us
+// (4); level 1 11.5 -> 9.1 us (2); level 2 took 5.4 against 4.7 us with 2.
 constexpr long long kRestrictPairBlocks = 4096;
+constexpr long long kRestrictQuadBlocks = 16384;
 
 template <typename T, typename TL, int RC>
 __global__ __launch_bounds__(BT) void k_restrict_residual(
@@ -1121,7 +1124,7 @@ static int zper_after_passes(const gmg_handle* h, int l, int nu, int planes_per_
 // Coarse planes per workgroup of level lv's fused residual + restriction.
 static int restrict_planes(const Level& lv, const Level& lc) {
   const long long one = (long long)((lv.g.nx + BX - 1) / BX) * ((lv.g.ny + BY - 1) / BY) * lc.g.nz;
-  return one >= kRestrictPairBlocks ? 2 : 1;
+  return one >= kRestrictQuadBlocks ? 4 : (one >= kRestrictPairBlocks ? 2 : 1);
 }
 
 // zper: the pass's z-chunk in workgroups of this launch (chunk_top_first).
@@ -1132,7 +1135,11 @@ static void enq_restrict(gmg_handle* h, int l, const Roles<T>& X, int role, cons
   const Level& lc = h->lev[l + 1];
   const int rc = restrict_planes(lv, lc);
   const dim3 grid((lv.g.nx + BX - 1) / BX, (lv.g.ny + BY - 1) / BY, (lc.g.nz + rc - 1) / rc);
-  if (rc == 2)
+  if (rc == 4)
+    hipLaunchKernelGGL((k_restrict_residual<T, TL, 4>), grid, kBlock, 0, h->s, lv.g, X, role,
+                       sigma, (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c,
+                       done, zper, lv.ub, lv.ubx, lv.uby);
+  else if (rc == 2)
     hipLaunchKernelGGL((k_restrict_residual<T, TL, 2>), grid, kBlock, 0, h->s, lv.g, X, role,
                        sigma, (const TL*)lv.L, lc.g, lv.c[0], lv.c[1], lv.c[2], sigma_c, x_c,
                        done, zper, lv.ub, lv.ubx, lv.uby);
