@@ -1000,6 +1000,10 @@ static void launch_split(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd
                        done);
 }
 
+// Margin by which a later two-sweep-pass candidate of the autotuner must be
+// faster than the one it has kept.
+constexpr float kTuneMargin = 0.97f;
+
 // With uniform_bricks 1 the two-sweep pass takes the uniform-brick map on
 // levels of at least this many cells (2: on every level).  A workgroup checks
 // its region's bricks before it starts (one dependent round trip to memory,
@@ -1893,7 +1897,8 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
       float pbest = 1e30f;
       int pkc = 0, pty = lv.pair_ty;
       for (int ty : {16, 8}) {
-        const int pkcs[8] = {pair_kchunk(lv.g, ty), 4, 8, 16, 32, 64, 128, 256};
+        const int pkcs[8] = {pair_kchunk(lv.g, ty, pass_map(h, lv) ? 2 : 1), 4, 8, 16, 32, 64,
+                             128, 256};
         for (int kc : pkcs) {
           if (kc > lv.g.nz) continue;
           float cost = 0.f;
@@ -1913,7 +1918,11 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
             cost += ms / reps;
           }
           const float ms = 0.5f * cost;  // mean time of one pass
-          if (ms < pbest) {
+          // a later candidate must beat the one kept by kTuneMargin: the
+          // isolated times of close candidates change order from run to run
+          // (and differ from their times inside a cycle), while the first
+          // candidate of each height is the default rule's
+          if (ms < kTuneMargin * pbest) {
             pbest = ms;
             pkc = kc;
             pty = ty;
