@@ -1008,8 +1008,8 @@ constexpr float kTuneMargin = 0.97f;
 // levels of at least this many cells (2: on every level).  A workgroup checks
 // its region's bricks before it starts (one dependent round trip to memory,
 // about 2 us); on a 256^3 level the skipped face loads save far more (the
-// pass 8 % faster with a sphere of diameter 64, 35 % with no body), on 128^3
-// and smaller levels the check costs more than they save.
+// pass about a quarter faster with a sphere of diameter 64, a third with no
+// body), on 128^3 and smaller levels the check costs more than they save.
 constexpr long long kUniformPassCells = 1LL << 23;
 
 static const UBrick* pass_map(const gmg_handle* h, const Level& lv) {
