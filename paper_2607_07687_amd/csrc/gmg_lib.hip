@@ -819,6 +819,8 @@ struct Level {
   int pair_ty;     // tile rows of the two-sweep pass (8 or 16)
   UBrick* ub;      // uniform-brick map (NULL: off); ubx x uby x ubz bricks
   int ubx, uby, ubz;
+  S2TileMode* tm;  // face modes of the two-sweep pass's tiles (NULL: none)
+  int tm_ty, tm_kc;  // the tiling they were found for (tm_kc 0: none yet)
 };
 
 size_t dsize(int dt) { return dt == GMG_F64 ? 8 : (dt == GMG_BF16 ? 2 : 4); }
@@ -1016,6 +1018,42 @@ static const UBrick* pass_map(const gmg_handle* h, const Level& lv) {
   return (h->p.uniform_bricks == 2 || lv.g.n >= kUniformPassCells) ? lv.ub : nullptr;
 }
 
+// With a table of the tiles' face modes (found outside the cycle, when the
+// faces or the tiling change) a workgroup reads one entry instead of
+// checking its bricks, and the map pays from levels of this many cells on.
+constexpr long long kTileModeCells = 1LL << 21;
+
+static bool uses_tile_modes(const gmg_handle* h, const Level& lv) {
+  return lv.tm != nullptr && (h->p.uniform_bricks == 2 || lv.g.n >= kTileModeCells);
+}
+
+// The face-mode table of level lv's pass at (ty, kchunk), if it was found
+// for that tiling.
+static const S2TileMode* pass_modes(const gmg_handle* h, const Level& lv, int ty, int kchunk) {
+  return (uses_tile_modes(h, lv) && lv.tm_kc == kchunk && lv.tm_ty == ty) ? lv.tm : nullptr;
+}
+
+// Find the face modes of every level's current pass tiling (after the faces
+// or a tiling changed; never inside a captured cycle).
+static void refresh_pass_modes(gmg_handle* h) {
+  for (int l = 0; l < h->nlev; ++l) {
+    Level& lv = h->lev[l];
+    lv.tm_kc = 0;
+    if (!uses_tile_modes(h, lv) || lv.pair_kc <= 0) continue;
+    const int ty = lv.pair_ty, kc = lv.pair_kc;
+    const int nt = ((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + ty - 1) / ty) *
+                   ((lv.g.nz + kc - 1) / kc);
+    if (ty == 16)
+      hipLaunchKernelGGL((k_pass_modes<16>), dim3(nt), dim3(S2Cfg<16>::NTB), 0, h->s, lv.g, lv.ub,
+                         lv.ubx, lv.uby, kc, lv.tm);
+    else
+      hipLaunchKernelGGL((k_pass_modes<8>), dim3(nt), dim3(S2Cfg<8>::NTB), 0, h->s, lv.g, lv.ub,
+                         lv.ubx, lv.uby, kc, lv.tm);
+    lv.tm_ty = ty;
+    lv.tm_kc = kc;
+  }
+}
+
 // Two consecutive sweeps of level l as one two-sweep pass (FP32 cycles, even
 // nx): X[rd] = sweep(sweep(X[rs] (+ P x_c))), bitwise the result of two
 // sweeps; rd != rs.
@@ -1026,19 +1064,20 @@ static void launch_pair(gmg_handle* h, int l, const Roles<T>& X, int rs, int rd,
     const Level& lv = h->lev[l];
     const Geom gc = (xc && l + 1 < h->nlev) ? h->lev[l + 1].g : lv.g;
     const int cx = lv.c[0] ? lv.c[0] : 1, cy = lv.c[1] ? lv.c[1] : 1, cz = lv.c[2] ? lv.c[2] : 1;
-    const UBrick* ub = pass_map(h, lv);
     auto go = [&](auto tyc) {
       constexpr int TY = decltype(tyc)::value;
+      const S2TileMode* tm = pass_modes(h, lv, TY, kchunk);
+      const UBrick* ub = tm ? nullptr : pass_map(h, lv);
       const dim3 grid(((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + TY - 1) / TY) *
                       ((lv.g.nz + kchunk - 1) / kchunk));
       if (xc != nullptr)
         hipLaunchKernelGGL((k_rb_sweep2<T, TL, TY, true>), grid, dim3(S2Cfg<TY>::NTB), 0, h->s,
                            lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz,
-                           kchunk, &h->st->omega, done, ub, lv.ubx, lv.uby);
+                           kchunk, &h->st->omega, done, ub, lv.ubx, lv.uby, tm);
       else
         hipLaunchKernelGGL((k_rb_sweep2<T, TL, TY, false>), grid, dim3(S2Cfg<TY>::NTB), 0, h->s,
                            lv.g, X, rs, rd, sigma, (const TL*)lv.L, xc, lv.active, gc, cx, cy, cz,
-                           kchunk, &h->st->omega, done, ub, lv.ubx, lv.uby);
+                           kchunk, &h->st->omega, done, ub, lv.ubx, lv.uby, tm);
     };
     if (ty == 16)
       go(std::integral_constant<int, 16>{});
@@ -1065,7 +1104,9 @@ static void launch_pair_opt(gmg_handle* h, int l, const Roles<T>& X, int rs, int
       hipLaunchKernelGGL((k_rb_sweep2_res<T, TL, TY>), dim3(pass_blocks(lv)),
                          dim3(S2Cfg<TY>::NTB), 0, h->s, lv.g, X, rs, rd, sigma, (const TL*)lv.L,
                          lv.active, lv.pair_kc, o.omega ? o.omega : &h->st->omega, done,
-                         o.res_part, o.gate, pass_map(h, lv), lv.ubx, lv.uby);
+                         o.res_part, o.gate,
+                         pass_modes(h, lv, TY, lv.pair_kc) ? nullptr : pass_map(h, lv), lv.ubx,
+                         lv.uby, pass_modes(h, lv, TY, lv.pair_kc));
     };
     if (lv.pair_ty == 16)
       go(std::integral_constant<int, 16>{});
@@ -1526,6 +1567,7 @@ static void free_handle(gmg_handle* h) {
     (void)hipFree(h->lev[l].L);
     (void)hipFree(h->lev[l].active);
     (void)hipFree(h->lev[l].ub);
+    (void)hipFree(h->lev[l].tm);
     (void)hipFree(h->lev[l].x[0]);
     (void)hipFree(h->lev[l].x[1]);
     (void)hipFree(h->lev[l].sigma);
@@ -1597,6 +1639,7 @@ static gmg_status enq_load_faces(gmg_handle* h, const void* L) {
   if (p->l_storage == GMG_F64) enq_build_levels<double>(h);
   else if (p->l_storage == GMG_BF16) enq_build_levels<uint16_t>(h);
   else enq_build_levels<float>(h);
+  refresh_pass_modes(h);
   HIP_TRY(hipGetLastError());
   return GMG_OK;
 }
@@ -1659,8 +1702,14 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
     lv.uby = (lv.g.ny + BY - 1) / BY;
     lv.ubz = (lv.g.nz + kUBZ - 1) / kUBZ;
     lv.ub = nullptr;
-    if (p->uniform_bricks)
+    lv.tm = nullptr;
+    lv.tm_ty = lv.tm_kc = 0;
+    if (p->uniform_bricks) {
       HIP_TRY(hipMalloc(&lv.ub, (size_t)lv.ubx * lv.uby * lv.ubz * sizeof(UBrick)));
+      if (pair_capable(*p, lv.g))  // room for the most tiles: 64 x 8 columns, 1 plane
+        HIP_TRY(hipMalloc(&lv.tm, (size_t)((lv.g.nx + S2_TX - 1) / S2_TX) *
+                                      ((lv.g.ny + 7) / 8) * lv.g.nz * sizeof(S2TileMode)));
+    }
     if (l > 0) {
       HIP_TRY(hipMalloc(&lv.x[0], lv.g.n * cs));
       HIP_TRY(hipMalloc(&lv.x[1], lv.g.n * cs));
@@ -1938,6 +1987,7 @@ static gmg_status autotune_impl(gmg_handle* h, void* x, const void* sigma, int r
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  refresh_pass_modes(h);
   HIP_TRY(hipGetLastError());
   return drop_graphs(h);
 }
@@ -2510,6 +2560,8 @@ gmg_status gmg_set_pair_sweeps(gmg_handle* h, int32_t level, int32_t ty, int32_t
   if (kchunk < 0 || kchunk > h->lev[level].g.nz) return fail(GMG_EINVAL, "kchunk out of range");
   h->lev[level].pair_kc = kchunk;
   if (kchunk != 0) h->lev[level].pair_ty = ty;
+  refresh_pass_modes(h);
+  HIP_TRY(hipGetLastError());
   return drop_graphs(h);
 }
 

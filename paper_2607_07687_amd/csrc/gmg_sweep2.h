@@ -593,6 +593,40 @@ __device__ __forceinline__ bool s2_const_planes(const Geom& g, int k0, int k1) {
   return g.pz || (k0 - 4 >= 1 && k1 + 3 < g.nz);
 }
 
+// A tile's face mode for one tiling, found once per set of faces and tiling
+// (k_pass_modes) so that the pass reads it instead of checking the bricks.
+struct S2TileMode {
+  double u[3];  // the bricks' constants (uniform tiles)
+  int flags;    // S2M_UNIFORM, S2M_PLANES (s2_const_planes), S2M_ACTIVE
+  int pad;
+};
+constexpr int S2M_UNIFORM = 1, S2M_PLANES = 2, S2M_ACTIVE = 4;
+
+// The face mode of a pass tile: from the table tm when given, else by
+// checking the bricks of the map ub (or none: S2_LOADED).  Called by the
+// whole workgroup.
+template <int TY, bool PROL>
+__device__ __forceinline__ int s2_tile_mode(const Geom& g, const S2TileMode* __restrict__ tm,
+                                            const UBrick* __restrict__ ub, int ubx, int uby,
+                                            int t, int i0, int j0, int k0, int k1,
+                                            double (&u)[3]) {
+  int f;
+  if (tm != nullptr) {
+    const S2TileMode m = tm[t];
+    u[0] = m.u[0];
+    u[1] = m.u[1];
+    u[2] = m.u[2];
+    f = m.flags;
+  } else {
+    bool act;
+    const bool uni = s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u, act);
+    f = (uni ? S2M_UNIFORM : 0) | (s2_const_planes(g, k0, k1) ? S2M_PLANES : 0) |
+        (act ? S2M_ACTIVE : 0);
+  }
+  if (!(f & S2M_UNIFORM)) return S2_LOADED;
+  return ((f & S2M_PLANES) && ((f & S2M_ACTIVE) || !PROL)) ? S2_CONST : S2_UNIFORM;
+}
+
 }  // namespace gmg
 
 // Two sweeps in one pass: X[rd] = sweep(sweep(X[rs] (+ P x_c))), at global
@@ -602,7 +636,7 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
     gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
     const TL* __restrict__ L, const T* __restrict__ xc, const uint8_t* __restrict__ active,
     gmg::Geom gc, int cx, int cy, int cz, int kchunk, const double* omega_p, const int* done,
-    const gmg::UBrick* ub, int ubx, int uby) {
+    const gmg::UBrick* ub, int ubx, int uby, const gmg::S2TileMode* tm) {
   if (gmg::stopped(done)) return;
   __shared__ gmg::S2Smem<T, TY> sm;
   gmg::S2Args<T, TL> a{g, X.get(rs), sigma, L, xc, active, gc, cx, cy, cz};
@@ -612,10 +646,10 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2(
   const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
   const T omega = (T)(*omega_p);
   double u[3];
-  bool act;
-  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u, act))
+  const int mode = gmg::s2_tile_mode<TY, PROL>(g, tm, ub, ubx, uby, t, i0, j0, k0, k1, u);
+  if (mode == gmg::S2_LOADED)
     gmg::rb_sweep2_tile<T, TL, TY, PROL>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
-  else if (gmg::s2_const_planes(g, k0, k1) && (act || !PROL))
+  else if (mode == gmg::S2_CONST)
     gmg::rb_sweep2_tile<T, TL, TY, PROL, false, gmg::S2_CONST>(sm, a, X.get(rd), i0, j0, k0, k1,
                                                                omega, u);
   else
@@ -632,7 +666,7 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
     gmg::Geom g, gmg::Roles<T> X, int rs, int rd, const T* __restrict__ sigma,
     const TL* __restrict__ L, const uint8_t* __restrict__ active, int kchunk,
     const double* omega_p, const int* done, double* res_part, const int* gate,
-    const gmg::UBrick* ub, int ubx, int uby) {
+    const gmg::UBrick* ub, int ubx, int uby, const gmg::S2TileMode* tm) {
   if (gmg::stopped(done)) return;
   if (gate != nullptr && *gate == 0) return;
   __shared__ gmg::S2Smem<T, TY> sm;
@@ -644,14 +678,39 @@ __global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_rb_sweep2_res(
   const T omega = (T)(*omega_p);
   double u[3];
   double s;
-  bool act;
-  if (!gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u, act))
+  const int mode = gmg::s2_tile_mode<TY, false>(g, tm, ub, ubx, uby, t, i0, j0, k0, k1, u);
+  if (mode == gmg::S2_LOADED)
     s = gmg::rb_sweep2_tile<T, TL, TY, false, true>(sm, a, X.get(rd), i0, j0, k0, k1, omega);
-  else if (gmg::s2_const_planes(g, k0, k1))
+  else if (mode == gmg::S2_CONST)
     s = gmg::rb_sweep2_tile<T, TL, TY, false, true, gmg::S2_CONST>(sm, a, X.get(rd), i0, j0, k0,
                                                                    k1, omega, u);
   else
     s = gmg::rb_sweep2_tile<T, TL, TY, false, true, gmg::S2_UNIFORM>(sm, a, X.get(rd), i0, j0,
                                                                      k0, k1, omega, u);
   if (res_part != nullptr && threadIdx.x == 0) res_part[blockIdx.x] = s;
+}
+
+// The face modes of the tiles of a pass over level g with tiles of 64 x TY
+// columns and z-chunks of kchunk planes, one workgroup per tile (indexed as
+// the pass indexes them after xcd_tile).
+template <int TY>
+__global__ __launch_bounds__(gmg::S2Cfg<TY>::NTB) void k_pass_modes(
+    gmg::Geom g, const gmg::UBrick* __restrict__ ub, int ubx, int uby, int kchunk,
+    gmg::S2TileMode* __restrict__ tm) {
+  const int ntx = (g.nx + gmg::S2_TX - 1) / gmg::S2_TX, nty = (g.ny + TY - 1) / TY;
+  const int t = blockIdx.x;
+  const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+  const int i0 = tx * gmg::S2_TX, j0 = ty * TY, k0 = tz * kchunk, k1 = min(g.nz, k0 + kchunk);
+  double u[3];
+  bool act;
+  const bool uni = gmg::s2_uniform_tile<TY>(g, ub, ubx, uby, i0, j0, k0, k1, u, act);
+  if (threadIdx.x == 0) {
+    gmg::S2TileMode& m = tm[t];
+    m.u[0] = u[0];
+    m.u[1] = u[1];
+    m.u[2] = u[2];
+    m.flags = (uni ? gmg::S2M_UNIFORM : 0) | (gmg::s2_const_planes(g, k0, k1) ? gmg::S2M_PLANES : 0) |
+              (act ? gmg::S2M_ACTIVE : 0);
+    m.pad = 0;
+  }
 }

@@ -248,3 +248,26 @@ def test_default_mode_at_2p23_cells(storage):
     check_same(hu, ho, sd, "f32")
     hu.close()
     ho.close()
+
+
+def set_pairs_everywhere(h, ty, kc):
+    """Two-sweep passes on every level with an even nx (z-chunk min(kc, nz))."""
+    for l in range(G.gmg_num_levels(h)):
+        (nx, _, nz), _ = G.gmg_level_shape(h, l)
+        G.gmg_set_pair_sweeps(h, l, min(kc, nz) if nx % 2 == 0 else 0, ty)
+
+
+@pytest.mark.parametrize("tiling", [(16, 3), (8, 2), (16, 8)], ids=lambda t: f"{t[0]}x{t[1]}")
+@pytest.mark.parametrize("name", ["sphere_walls", "tgv_periodic", "solid_slab", "layered_z"])
+def test_pass_tile_modes_on_every_level(name, tiling):
+    """Passes on every level read the table of their tiles' face modes (found
+    when the tiling is set): bitwise the passes without the map, through
+    V-cycles and a solve, then again after the tiling changes."""
+    say(f"uniform tile modes {name} {tiling}")
+    hu, ho, sd, _ = pair(name, "f32", "f32")
+    for ty, kc in (tiling, (16 if tiling[0] == 8 else 8, tiling[1] + 1)):
+        for h in (hu, ho):
+            set_pairs_everywhere(h, ty, kc)
+        check_same(hu, ho, sd, "f32", seed=11)
+    hu.close()
+    ho.close()
