@@ -227,8 +227,9 @@ __device__ __forceinline__ int chunk_top_first(int b, int nzb, int per) {
 // range of blocks (whole rows of blocks, whole z-chunks), so the neighbour
 // rows and planes a column walk reads beyond its own block are mostly in the
 // same L2.  The residual norm at 256^3 takes 32.5 us so against 40.3 us in
-// the hardware order; the fused residual + restriction (four planes per
-// block) took longer (49.4 against 46.1 us) and keeps the hardware order.
+// the hardware order, the fused residual + restriction with four coarse
+// planes per block 39.9 against 41.8 us; with two coarse planes per block it
+// took longer (49.4 against 46.1 us) and keeps the hardware order.
 __device__ __forceinline__ int3 xcd_block() {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
@@ -404,13 +405,13 @@ __global__ __launch_bounds__(BT) void k_restrict_residual(
     const int* done, int zper, const UBrick* ub, int ubx, int uby) {
   if (stopped(done)) return;
   __shared__ T rows[RC][BY][BX];
-  const int K0 = RC * chunk_top_first(blockIdx.z, gridDim.z, zper);
+  const int3 b = RC == 4 ? xcd_block() : make_int3(blockIdx.x, blockIdx.y, blockIdx.z);
+  const int K0 = RC * chunk_top_first(b.z, gridDim.z, zper);
   const int K1 = min(gc.nz, K0 + RC);
   double u[3];
-  const bool uni =
-      uniform_block(ub, ubx, uby, blockIdx.x, blockIdx.y, K0 * cz, min(gf.nz, K1 * cz), u);
+  const bool uni = uniform_block(ub, ubx, uby, b.x, b.y, K0 * cz, min(gf.nz, K1 * cz), u);
   restrict_tile<T, TL, RC>(rows, gf, X.get(role), sigma, L, gc, cx, cy, cz, sigma_c, x_c,
-                           blockIdx.x * BX, blockIdx.y * BY, K0, K1, uni ? u : nullptr);
+                           b.x * BX, b.y * BY, K0, K1, uni ? u : nullptr);
 }
 
 // Piecewise-constant prolongation + correction on active fine cells:
