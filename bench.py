@@ -640,6 +640,9 @@ def main():
                                  f"loaded) x {sweeps_per_launch} x {cells} cells",
                          "alg_bytes_per_launch": dense_bytes,
                          "frac_at_map_launch": dense_bytes / (launch * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "note": "frac_at_map_launch prices the map pass at bytes it does not "
+                                 "move (uniform faces); above 1 it is no roofline, the map "
+                                 "rule above is",
                          "no_map_launch_us": nomap_ms * 1e3 if nomap_ms else None,
                          "no_map_frac": dense_bytes / (nomap_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
                          if nomap_ms else None},
