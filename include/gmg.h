@@ -152,20 +152,20 @@ typedef struct gmg_params {
                             instead of always reducing its own residual by
                             inner_rtol.  0: inner_rtol alone.  In [0, 1]
                             (default 0.5)                                      */
-  int32_t uniform_bricks; /* 1 (default): gmg_setup and gmg_update_faces mark
-                            the 128 x 2 x 2-cell bricks of every level in
-                            which every face of direction d reads one value
-                            u_d bit for bit (the faces just beyond the
-                            brick's high sides included, the zero faces of a
-                            low wall excepted); the residual kernels (norm,
-                            fused residual + restriction) take such blocks'
-                            faces from u instead of loading them, and so
-                            does the two-sweep pass for tiles whose region
-                            lies in such bricks, on levels of at least 2^23
-                            cells.  2: the same with the two-sweep pass on
-                            every level.  0: off.  Bitwise the same results
-                            in every case; less memory traffic where the
-                            faces are uniform (away from immersed bodies).   */
+  int32_t uniform_bricks; /* 1 (default): gmg_setup and gmg_update_faces mark,
+                            on every level of at least 2^21 cells, the
+                            128 x 2 x 2-cell bricks in which every face of
+                            direction d reads one value u_d bit for bit (the
+                            faces just beyond the brick's high sides
+                            included, the zero faces of a low wall
+                            excepted); the residual kernels (norm, fused
+                            residual + restriction) take such blocks' faces
+                            from u instead of loading them, and so does the
+                            two-sweep pass for tiles whose region lies in
+                            such bricks.  2: the same on every level.  0:
+                            off.  Bitwise the same results in every case;
+                            less memory traffic where the faces are uniform
+                            (away from immersed bodies).                      */
 } gmg_params;
 
 #define GMG_MAX_HISTORY 512

@@ -1019,19 +1019,25 @@ static const UBrick* pass_map(const gmg_handle* h, const Level& lv) {
   return (h->p.uniform_bricks == 2 || lv.g.n >= kUniformPassCells) ? lv.ub : nullptr;
 }
 
-// With a table of the tiles' face modes (found outside the cycle, when the
-// faces or the tiling change) a workgroup reads one entry instead of
-// checking its bricks, and the map pays from levels of this many cells on.
-constexpr long long kTileModeCells = 1LL << 21;
+// With uniform_bricks 1 a level has a uniform-brick map (read by its
+// residual kernels, and by its two-sweep pass through the table of tile
+// modes) when it has at least this many cells; with 2 every level has one.
+// On smaller levels the map's checks lengthen kernels that are bound by
+// latency, and rebuilding it costs each gmg_update_faces more than it saves
+// (a 256 x 64 x 64 sequence of solves with a face update per step: 3.17 ms
+// per step without the map, 3.45 with it on every level).
+constexpr long long kMapCells = 1LL << 21;
 
-static bool uses_tile_modes(const gmg_handle* h, const Level& lv) {
-  return lv.tm != nullptr && (h->p.uniform_bricks == 2 || lv.g.n >= kTileModeCells);
+static bool level_has_map(const gmg_params* p, const Geom& g) {
+  return p->uniform_bricks == 2 || (p->uniform_bricks == 1 && g.n >= kMapCells);
 }
+
+static bool uses_tile_modes(const Level& lv) { return lv.tm != nullptr; }
 
 // The face-mode table of level lv's pass at (ty, kchunk), if it was found
 // for that tiling.
 static const S2TileMode* pass_modes(const gmg_handle* h, const Level& lv, int ty, int kchunk) {
-  return (uses_tile_modes(h, lv) && lv.tm_kc == kchunk && lv.tm_ty == ty) ? lv.tm : nullptr;
+  return (uses_tile_modes(lv) && lv.tm_kc == kchunk && lv.tm_ty == ty) ? lv.tm : nullptr;
 }
 
 // Find the face modes of every level's current pass tiling (after the faces
@@ -1040,7 +1046,7 @@ static void refresh_pass_modes(gmg_handle* h) {
   for (int l = 0; l < h->nlev; ++l) {
     Level& lv = h->lev[l];
     lv.tm_kc = 0;
-    if (!uses_tile_modes(h, lv) || lv.pair_kc <= 0) continue;
+    if (!uses_tile_modes(lv) || lv.pair_kc <= 0) continue;
     const int ty = lv.pair_ty, kc = lv.pair_kc;
     const int nt = ((lv.g.nx + S2_TX - 1) / S2_TX) * ((lv.g.ny + ty - 1) / ty) *
                    ((lv.g.nz + kc - 1) / kc);
@@ -1705,7 +1711,7 @@ static gmg_status setup_impl(const gmg_params* p, const void* L, void* stream, g
     lv.ub = nullptr;
     lv.tm = nullptr;
     lv.tm_ty = lv.tm_kc = 0;
-    if (p->uniform_bricks) {
+    if (level_has_map(p, lv.g)) {
       HIP_TRY(hipMalloc(&lv.ub, (size_t)lv.ubx * lv.uby * lv.ubz * sizeof(UBrick)));
       if (pair_capable(*p, lv.g))  // room for the most tiles: 64 x 8 columns, 1 plane
         HIP_TRY(hipMalloc(&lv.tm, (size_t)((lv.g.nx + S2_TX - 1) / S2_TX) *

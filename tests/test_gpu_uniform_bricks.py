@@ -123,9 +123,9 @@ def host_uniform(L, per, active=False):
 
 
 def pair(name, prec, storage, mode=2):
-    """Handles with the map (mode 2: the two-sweep pass takes it on every
-    level, so that these small grids exercise it; 1: the default) and
-    without it, on the same inputs."""
+    """Handles with the map (mode 2: on every level, so that these small
+    grids exercise it; 1: the default, on levels of at least 2^21 cells)
+    and without it, on the same inputs."""
     require_gpu()
     L, s, per = CASES[name]()
     n = (L.shape[3], L.shape[2], L.shape[1])
@@ -226,7 +226,7 @@ def test_update_faces_rebuilds_map(prec, storage):
     G.gmg_update_faces(hu, L2d)
     G.gmg_update_faces(ho, L2d)
     fresh = G.gmg_setup(G.gmg_default_params((256, 40, 36), per, G.GMG_F32,
-                                             l_storage=STORE[storage]), L2d)
+                                             l_storage=STORE[storage], uniform_bricks=2), L2d)
     for l in range(G.gmg_num_levels(hu)):
         assert G.gmg_level_uniform(hu, l) == G.gmg_level_uniform(fresh, l)
         assert G.gmg_level_uniform(hu, l) == host_uniform(level_faces(hu, l, storage, prec), per)
