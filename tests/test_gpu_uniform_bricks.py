@@ -271,3 +271,28 @@ def test_pass_tile_modes_on_every_level(name, tiling):
         check_same(hu, ho, sd, "f32", seed=11)
     hu.close()
     ho.close()
+
+
+@pytest.mark.parametrize("name", ["sphere_walls", "tgv_periodic", "solid_slab"])
+def test_deferred_norm_pass_with_map(name):
+    """The deferred decision's first pass (which also sums its input's
+    residual, one partial per workgroup) in the uniform-face variants: solves
+    bitwise those without the map, histories and decisions included, at the
+    same pass tiling (the default z-chunk differs with the map, and with it
+    the partials' grouping)."""
+    say(f"uniform deferred norm {name}")
+    require_gpu()
+    L, s, per = CASES[name]()
+    n = (L.shape[3], L.shape[2], L.shape[1])
+    Ld, sd = dev(rounded(L, "f32"), "f32"), dev(rounded(s, "f32"), "f32")
+    hs = [G.gmg_setup(G.gmg_default_params(n, per, G.GMG_F32, uniform_bricks=m, deferred_norm=1),
+                      Ld) for m in (2, 0)]
+    for h in hs:
+        G.gmg_set_pair_sweeps(h, 0, min(6, n[2]), 16)
+    xs = [torch.zeros_like(sd) for _ in hs]
+    infos = [G.gmg_solve(h, x, sd, 1e-5, 40) for h, x in zip(hs, xs)]
+    assert torch.equal(xs[0], xs[1])
+    assert infos[0]["history"] == infos[1]["history"]
+    assert infos[0]["accepted"] == infos[1]["accepted"]
+    for h in hs:
+        h.close()
