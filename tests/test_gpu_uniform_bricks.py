@@ -1,12 +1,13 @@
 """GPU checks of the uniform-brick map (blocks of 128 x 2 x 2 cells whose
-faces are one constant per direction, low walls at zero; whether all their
-cells are active): the map of every
-level agrees with the rule evaluated on the host from the level's faces, and
-every entry point whose kernels read it (residual and its norms, the
-allocation-free residual, the fused residual + restriction, V-cycles, solves)
-gives bitwise the results of a handle without the map, on walls, periodic
-directions, holes, ragged tails, FP32/FP64 iterates and FP32/BF16/FP64 faces,
-and after gmg_update_faces.  The kernels without the map are themselves
+faces are one constant per direction, low walls at zero, and whether all
+their cells are active): the map of every level agrees with the rule
+evaluated on the host from the level's faces, and every entry point whose
+kernels read it (residual and its norms, the allocation-free residual, the
+fused residual + restriction, the two-sweep pass through its table of tile
+modes, V-cycles, solves, the deferred decision) gives bitwise the results of
+a handle without the map, on walls, periodic directions, holes, ragged
+tails, FP32/FP64 iterates and FP32/BF16/FP64 faces, after gmg_update_faces
+and after a change of tiling.  The kernels without the map are themselves
 checked against the oracle in test_gpu_parity.py."""
 import numpy as np
 import pytest
@@ -238,9 +239,9 @@ def test_update_faces_rebuilds_map(prec, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_default_mode_at_2p23_cells(storage):
-    """The default mode on a level of 2^23 cells (its two-sweep pass takes
-    the map there, tiles near the sphere not): bitwise the results without
-    the map."""
+    """The default mode on a level of 2^23 cells (its kernels take the map
+    there, tiles near the sphere not): bitwise the results without the
+    map."""
     say(f"uniform default mode 256x256x128 f32/{storage}")
     hu, ho, sd, per = pair("sphere_2p23", "f32", storage, mode=1)
     u, t = G.gmg_level_uniform(hu, 0)
